@@ -1,0 +1,118 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke
+check.  This module draws random numbers and lays out workload shapes; it
+holds none of the method's arithmetic.
+
+Generator (counter based, so any entry can be drawn independently):
+    mix(z)      = SplitMix64 finaliser (Steele, Lea & Flood 2014):
+                  z ^= z >> 30; z *= 0xBF58476D1CE4E5B9;
+                  z ^= z >> 27; z *= 0x94D049BB133111EB; z ^= z >> 31
+    key(s, id)  = mix(s ^ mix(id + 0x632BE59BD9B4E019))
+    word(s,id,i)= mix(key + (i + 1) * 0x9E3779B97F4A7C15)      (mod 2^64)
+    uniform     = (word >> 11) * 2^-53  in [0, 1)
+    sym_uniform = 2 * uniform - 1        in [-1, 1)
+The library implements the same definition for its own seeded node
+initialisation; `sym_uniform` is exact in binary64 on both sides.
+Normal draws (Box-Muller on pairs of uniforms) are used only for inputs
+handed over to both sides as arrays.
+"""
+
+import numpy as np
+
+M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def _mix(z):
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z ^ (z >> np.uint64(30))
+        z = z * np.uint64(0xBF58476D1CE4E5B9)
+        z = z ^ (z >> np.uint64(27))
+        z = z * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def words(seed, stream, n):
+    with np.errstate(over="ignore"):
+        key = _mix(np.uint64(seed) ^ _mix(np.uint64(stream) + np.uint64(0x632BE59BD9B4E019)))
+        i = np.arange(1, n + 1, dtype=np.uint64)
+        return _mix(key + i * GAMMA)
+
+
+def uniform(seed, stream, n):
+    return (words(seed, stream, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def sym_uniform(seed, stream, n):
+    return 2.0 * uniform(seed, stream, n) - 1.0
+
+
+def normal(seed, stream, n):
+    m = (n + 1) // 2
+    u = uniform(seed, stream, 2 * m)
+    u1 = 1.0 - u[0::2]          # (0, 1]
+    u2 = u[1::2]
+    r = np.sqrt(-2.0 * np.log(u1))
+    z = np.concatenate([r * np.cos(2 * np.pi * u2), r * np.sin(2 * np.pi * u2)])
+    return z[:n]
+
+
+def integers(seed, stream, n, lo, hi):
+    """n integers uniform in [lo, hi] (inclusive), by floor of uniform."""
+    u = uniform(seed, stream, n)
+    return lo + np.floor(u * (hi - lo + 1)).astype(np.int64)
+
+
+# ----------------------------------------------------------------------
+# workload shapes (sizes and draws only)
+# ----------------------------------------------------------------------
+C1_LEG = [(-2, 2), (-1, 3), (0, 6), (1, 3), (2, 2)]
+C4_LEG = [(-4, 4), (-3, 8), (-2, 16), (-1, 23), (0, 26), (1, 23), (2, 16), (3, 8), (4, 4)]
+
+
+def symmetric_sector_op(seed, stream, leg):
+    """Sector-preserving leg operator: per sector (G + G^T)/2, G ~ N(0,1).
+    Returns {q: n x n array}."""
+    out = {}
+    tot = sum(n * n for _, n in leg)
+    g = normal(seed, stream, tot)
+    o = 0
+    for q, n in leg:
+        G = g[o:o + n * n].reshape(n, n)
+        o += n * n
+        out[q] = 0.5 * (G + G.T)
+    return out
+
+
+def single_node_terms(seed, K, leg, streams_from=100):
+    """K three-factor terms, each factor a symmetric sector-preserving
+    operator on the (common) leg, coefficient 1."""
+    terms = []
+    for k in range(K):
+        ops = [symmetric_sector_op(seed, streams_from + 3 * k + j, leg) for j in range(3)]
+        terms.append((1.0, ops[0], ops[1], ops[2]))
+    return terms
+
+
+def random_composition(seed, stream, chi, S):
+    """Sizes of S sectors summing to chi: S-1 distinct cut points drawn
+    uniformly from 1..chi-1 (by rejection in draw order)."""
+    cuts = []
+    i = 0
+    while len(cuts) < S - 1:
+        c = int(integers(seed, stream, i + 1, 1, chi - 1)[i])
+        i += 1
+        if c not in cuts:
+            cuts.append(c)
+    cuts = sorted(cuts)
+    edges = [0] + cuts + [chi]
+    return [edges[a + 1] - edges[a] for a in range(S)]
+
+
+def batched_leg(seed, stream, chis=(32, 48, 64, 96, 128), smin=3, smax=9):
+    chi = chis[int(integers(seed, stream, 1, 0, len(chis) - 1)[0])]
+    S = int(integers(seed, stream + 1, 1, smin, smax)[0])
+    sizes = random_composition(seed, stream + 2, chi, S)
+    q0 = -((S - 1) // 2)
+    return [(q0 + i, sizes[i]) for i in range(S)]

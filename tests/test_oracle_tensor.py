@@ -1,0 +1,313 @@
+"""Pins of the oracle's tensor layer: block tables, H_eff, Lanczos, the
+tree tensor network and its observables."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import blocks, heff, lanczos
+from oracle.ed import DressedED, OriginalED
+from oracle.hamiltonian import Couplings, Hamiltonian
+from oracle.lattice import Lattice
+from oracle.ttn import TTN, Tree, allocate_sectors, default_nu_max, penalty_schedule
+from paper_2011_10658_amd import synth
+
+C1 = synth.C1_LEG
+C4 = synth.C4_LEG
+
+
+# -- block tables --------------------------------------------------------
+def _brute_table(l, r, p, flux=0):
+    out = []
+    for (il, (ql, nl)), (ir, (qr, nr)) in itertools.product(enumerate(l), enumerate(r)):
+        for ip, (qp, np_) in enumerate(p):
+            if ql + qr - qp == flux:
+                out.append(((ql, qr), (il, ir, ip), nl * nr * np_))
+    out.sort()
+    return [t for _, t, _ in out], [s for _, _, s in out]
+
+
+@pytest.mark.parametrize("legs,nblk,size", [((C1, C1, C1), 19, 792), ((C4, C4, C4), 61, 253604)])
+def test_block_table_counts(legs, nblk, size):
+    trip, offs = blocks.block_table(*legs)
+    assert len(trip) == nblk and offs[-1] == size
+    bt, bs = _brute_table(*legs)
+    assert trip == bt
+    assert list(np.diff(offs)) == bs
+
+
+def test_block_table_flux_and_roundtrip():
+    l = [(-1, 2), (0, 3), (2, 1)]
+    r = [(0, 2), (1, 1)]
+    p = [(-1, 2), (0, 1), (1, 3), (3, 2)]
+    for f in (-1, 0, 1, 2):
+        trip, offs = blocks.block_table(l, r, p, f)
+        bt, bs = _brute_table(l, r, p, f)
+        assert trip == bt
+        x = np.arange(offs[-1], dtype=float) + 1.0
+        D = blocks.to_dense(x, l, r, p, f)
+        assert np.count_nonzero(D) == offs[-1]
+        assert np.all(D[~blocks.allowed_mask(l, r, p, f)] == 0)
+        assert np.array_equal(blocks.from_dense(D, l, r, p, f), x)
+    # in-block index is (i_l * n_r + i_r) * n_p + i_p
+    trip, offs = blocks.block_table(l, r, p, 0)
+    x = np.arange(offs[-1], dtype=float)
+    D = blocks.to_dense(x, l, r, p, 0)
+    ol, orr, op = blocks.leg_offsets(l), blocks.leg_offsets(r), blocks.leg_offsets(p)
+    for b, (il, ir, ip) in enumerate(trip):
+        (ql, nl), (qr, nr), (qp, npp) = l[il], r[ir], p[ip]
+        for i, j, k in itertools.product(range(nl), range(nr), range(npp)):
+            assert D[ol[ql] + i, orr[qr] + j, op[qp] + k] == offs[b] + (i * nr + j) * npp + k
+
+
+# -- H_eff ---------------------------------------------------------------
+def _dense_terms(terms, leg):
+    return [(c, *(blocks.op_to_dense(o, leg, 0) for o in ops)) for c, *ops in terms]
+
+
+def test_heff_brute_force_tiny():
+    leg = [(-1, 2), (0, 2), (1, 1)]
+    terms = synth.single_node_terms(5, 2, leg)
+    dterms = _dense_terms(terms, leg)
+    mask = blocks.allowed_mask(leg, leg, leg)
+    rng = np.random.default_rng(0)
+    xd = rng.standard_normal(mask.shape) * mask
+    y = heff.apply_dense(xd, dterms)
+    # index-by-index sum of the definition
+    n = mask.shape[0]
+    yb = np.zeros_like(xd)
+    for c, A, B, C in dterms:
+        for i, j, k, a, b, cc in itertools.product(range(n), repeat=6):
+            yb[i, j, k] += c * A[i, a] * B[j, b] * C[k, cc] * xd[a, b, cc]
+    assert np.abs(y - yb).max() < 1e-12
+    assert np.abs(y[~mask]).max() < 1e-15
+
+
+def test_heff_c1_symmetric_and_flops():
+    terms = synth.single_node_terms(1, 8, C1)
+    dterms = _dense_terms(terms, C1)
+    legs = (C1, C1, C1)
+    H = heff.matrix(legs, dterms)
+    assert H.shape == (792, 792)
+    assert np.array_equal(H, H.T)
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal(792), rng.standard_normal(792)
+    hu, hv = heff.apply_flat(u, legs, dterms), heff.apply_flat(v, legs, dterms)
+    assert abs(u @ hv - hu @ v) <= 1e-13 * np.linalg.norm(hu) * np.linalg.norm(v)
+    metas = [(True, 0, True, 0, True, 0)] * 8
+    assert heff.flops(legs, metas) == 161280
+    assert heff.flops(legs, metas[:1]) == 20160
+
+
+def test_heff_shifted_factors_stay_in_blocks():
+    # a charge-shifting pair delta_A = +1, delta_C = +1 keeps y on allowed blocks
+    leg = [(-1, 2), (0, 3), (1, 2)]
+    rng = np.random.default_rng(1)
+    A = {q: rng.standard_normal((dict(leg)[q + 1], n)) for q, n in leg if q + 1 in dict(leg)}
+    C = {q: rng.standard_normal((dict(leg)[q + 1], n)) for q, n in leg if q + 1 in dict(leg)}
+    Ad, Cd = blocks.op_to_dense(A, leg, 1), blocks.op_to_dense(C, leg, 1)
+    legs = (leg, leg, leg)
+    size = int(blocks.allowed_mask(*legs).sum())
+    x = rng.standard_normal(size)
+    y = heff.apply_flat(x, legs, [(0.5, Ad, None, Cd)])
+    assert y.shape == x.shape and np.abs(y).max() > 0
+
+
+# -- Lanczos -------------------------------------------------------------
+def test_lanczos_interlacing_and_convergence():
+    terms = synth.single_node_terms(1, 8, C1)
+    legs = (C1, C1, C1)
+    H = heff.matrix(legs, _dense_terms(terms, C1))
+    lam = np.linalg.eigvalsh(H)[0]
+    x0 = synth.normal(1, 7, 792)
+    prev = np.inf
+    for m in (5, 10, 20, 30, 60):
+        theta, u, resid, a, b = lanczos.lanczos_cycle(lambda v: H @ v, x0, m)
+        assert theta >= lam - 1e-10
+        assert theta <= prev + 1e-12
+        prev = theta
+        # residual estimate equals the true residual of the Ritz pair
+        assert abs(np.linalg.norm(H @ u - theta * u) - resid) < 1e-8 * abs(theta)
+    theta, u, resid = lanczos.lowest(lambda v: H @ v, x0, m=40, tol=1e-12, max_cycles=20)
+    assert abs(theta - lam) < 1e-10 * abs(lam)
+    assert u[np.argmax(np.abs(u))] > 0
+
+
+def test_lanczos_exact_on_small_diagonal():
+    d = np.array([3.0, -1.0, 2.0, 0.5])
+    theta, u, resid, _, _ = lanczos.lanczos_cycle(lambda v: d * v, np.ones(4), 10)
+    assert abs(theta + 1.0) < 1e-14
+    assert np.allclose(u, [0, 1, 0, 0], atol=1e-12)
+
+
+# -- tree geometry and sectors ------------------------------------------
+def test_tree_shapes():
+    t = Tree(Lattice(4, 4, 4))
+    assert len(t.nodes) == 63
+    layers = [sum(1 for n in t.nodes if n["layer"] == k) for k in range(6)]
+    assert layers == [32, 16, 8, 4, 2, 1]
+    assert [t.nodes[k]["axis"] for k in (0, 32, 48, 56, 60, 62)] == [0, 1, 2, 0, 1, 2]
+    # bottom node merges two x-neighbours
+    n0 = t.nodes[0]
+    assert (n0["l"], n0["r"]) == (0, 1)
+    t2 = Tree(Lattice(2, 1, 1))
+    assert len(t2.nodes) == 1
+    with pytest.raises(ValueError):
+        Tree(Lattice(3, 2, 2))
+
+
+def _counts(ham):
+    out = []
+    for s in range(ham.lat.nsites):
+        v, c = np.unique(ham.site_charges(s), return_counts=True)
+        out.append({int(a): int(b) for a, b in zip(v, c)})
+    return out
+
+
+def test_sector_allocation_invariants():
+    lat = Lattice(4, 4, 4, boundary="free_flux")
+    counts = [{0: 141, 1: 126} if lat.parity(s) == 0 else {-1: 126, 0: 141}
+              for s in range(lat.nsites)]
+    tree = Tree(lat)
+    for Q, chi in ((8, 256), (0, 64)):
+        legs = allocate_sectors(tree, counts, Q, chi)
+        for e, leg in legs.items():
+            qs = [q for q, _ in leg]
+            assert qs == sorted(set(qs))
+            assert all(n > 0 for _, n in leg)
+            if e >= lat.nsites and e != tree.top:
+                assert sum(n for _, n in leg) <= chi
+        assert legs[tree.top] == [(Q, 1)]
+        for nd in tree.nodes:
+            L, R, P = (dict(legs[nd[k]]) for k in ("l", "r", "p"))
+            for q, n in P.items():
+                assert n <= sum(L[a] * R.get(q - a, 0) for a in L)
+            for q, n in L.items():
+                if nd["l"] >= lat.nsites:
+                    assert n <= sum(R[b] * P.get(q + b, 0) for b in R)
+
+
+# -- TTN against ED ------------------------------------------------------
+CPL = Couplings(t=1.0, m=0.7, g2e=1.3, g2m=0.9)
+
+
+def _init(tree, legs, seed=11):
+    out = {}
+    for n, nd in enumerate(tree.nodes):
+        _, offs = blocks.block_table(legs[nd["l"]], legs[nd["r"]], legs[nd["p"]])
+        out[n] = synth.sym_uniform(seed, n, int(offs[-1]))
+    return out
+
+
+def _make(lat, cpl, Q, chi, seed=11):
+    ham = Hamiltonian(lat, cpl)
+    tree = Tree(lat)
+    legs = allocate_sectors(tree, _counts(ham), Q, chi)
+    return TTN(ham, Q, chi, init=_init(tree, legs, seed), legs=legs)
+
+
+@pytest.mark.parametrize("L", [(2, 1, 1), (2, 2, 1)])
+def test_ttn_exact_bond_dim_equals_ed(L):
+    lat = Lattice(*L)
+    e0 = OriginalED(lat, CPL).spectrum()[0]
+    T = _make(lat, CPL, 0, 64)
+    for _ in range(3):
+        E = T.sweep(20.0, m=40, cycles=3, tol=1e-13)
+    assert abs(E - e0) < 1e-10 * abs(e0)
+    ob = T.observables()
+    assert abs(ob["Q"]) < 1e-12
+    assert ob["deltaL"] < 1e-9
+    # the renormalised energy equals <psi|H|psi> from the full state vector
+    psi = _full_state(T)
+    ham = T.ham
+    from oracle.ed import dense_dressed_hamiltonian
+    Hd = dense_dressed_hamiltonian(ham, 20.0)
+    assert abs(psi @ Hd @ psi / (psi @ psi) - E) < 1e-10 * abs(E)
+
+
+def _full_state(T):
+    """Contract the whole tree into a product-space vector (site 0 is the
+    slowest index, as in the Kronecker order)."""
+    tree = T.tree
+    vec = {s: (np.eye(T.ham.dims[s]), [s]) for s in range(tree.N)}
+    for n, nd in enumerate(tree.nodes):
+        Ml, sl = vec[nd["l"]]
+        Mr, sr = vec[nd["r"]]
+        x = T.nodes[n]
+        # M[(sites...), leg]
+        M = np.einsum("ua,vb,abc->uvc", Ml, Mr, x).reshape(-1, x.shape[2])
+        vec[nd["p"]] = (M, sl + sr)
+    M, sites = vec[tree.top]
+    dims = [T.ham.dims[s] for s in sites]
+    psi = M[:, 0].reshape(dims)
+    order = np.argsort(sites)
+    return np.transpose(psi, order).reshape(-1)
+
+
+def test_ttn_isometries_after_sweep():
+    T = _make(Lattice(2, 2, 1), CPL, 0, 8)
+    T.sweep(5.0, m=20, cycles=1)
+    T.move_to(T.tree.root)
+    for n in range(len(T.tree.nodes)):
+        if n == T.tree.root:
+            continue
+        x = T.nodes[n]
+        G = np.einsum("abc,abd->cd", x, x)
+        assert np.abs(G - np.eye(G.shape[0])).max() < 1e-13
+
+
+def test_ttn_variational_bound_2x2x2():
+    lat = Lattice(2, 2, 2)
+    e0 = OriginalED(lat, CPL).spectrum()[0]
+    T = _make(lat, CPL, 0, 16)
+    numax = default_nu_max(CPL)
+    prev = None
+    for s in range(6):
+        E = T.sweep(penalty_schedule(s, numax), m=20, cycles=1)
+    assert E >= e0 - 1e-9
+    ob = T.observables()
+    assert abs(ob["Q"]) < 1e-12
+    # Gauss law is exact by construction of every basis row
+    for s in range(lat.nsites):
+        rows = T.ham.rows[s]
+        assert np.all(rows[:, 0] + rows[:, 1:].sum(1) == 6 + lat.parity(s))
+
+
+def test_ttn_t0_closed_form():
+    g2e = 2.0
+    for m in (-1.5, 1.0):
+        c = Couplings(t=0.0, m=m, g2e=g2e, g2m=0.0)
+        lat = Lattice(2, 2, 1)
+        T = _make(lat, c, 0, 32)
+        for s in range(3):
+            E = T.sweep(10.0, m=30, cycles=2, tol=1e-13)
+        N = lat.nsites
+        exact = min(-m * N / 2, (m + g2e / 2) * N / 2)
+        assert abs(E - exact) < 1e-9
+        ob = T.observables()
+        # vacuum at large positive m, full charge crystal at large negative m
+        assert abs(ob["rho"] - (0.0 if m > 0 else 1.0)) < 1e-8
+
+
+def test_ttn_free_flux_nonzero_charge():
+    """Finite charge under free-flux boundaries: <Q> is exactly the sector
+    charge and the energy is bounded by dressed-site ED with L = 2."""
+    lat = Lattice(2, 1, 1, boundary="free_flux")
+    T = _make(lat, CPL, 1, 400)
+    for _ in range(2):
+        E = T.sweep(20.0, m=60, cycles=4, tol=1e-13)
+    ob = T.observables()
+    assert abs(ob["Q"] - 1.0) < 1e-12
+    d = DressedED(T.ham, Q=1)
+    e0 = np.linalg.eigvalsh(d.H.toarray())[0]
+    assert abs(E - e0) < 1e-9 * max(1.0, abs(e0))
+
+
+def test_penalty_schedule_shape():
+    nus = [penalty_schedule(s, 40.0) for s in range(12)]
+    assert abs(nus[0] - 2.0) < 1e-15 and abs(nus[3] - 10.0) < 1e-15
+    assert all(b > a for a, b in zip(nus[:8], nus[1:8]))
+    assert nus[7] == 40.0 and nus[11] == 40.0
+    d = np.diff(nus[3:8])
+    assert all(b > a for a, b in zip(d[:-1], d[1:]))  # quadratic stage accelerates
