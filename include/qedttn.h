@@ -1,0 +1,273 @@
+/*
+ * qedttn: tree-tensor-network node update for (3+1)D compact lattice QED
+ * (Magnifico, Felser, Silvi, Montangero, arXiv:2011.10658) on AMD MI355X.
+ *
+ * C ABI.  Conventions shared by every entry point:
+ *   - Every function returns an int status: QED_OK (0) on success, a
+ *     negative QED_ERR_* on error, QED_NOT_CONVERGED (+1) as a warning.
+ *     qed_last_error(ctx) returns a context-owned message for the last
+ *     failure on that context (valid until the next call on it).
+ *   - A context is single-threaded; separate contexts are independent.
+ *   - Host pointers are borrowed for the duration of the call; output
+ *     arrays are caller-allocated with the sizes stated below.
+ *   - Device pointers passed in are owned by the caller and borrowed.
+ *     Library-internal device memory comes from the registered allocator
+ *     (stream-ordered HIP allocations by default) and is released by
+ *     qed_destroy / the matching *_destroy.
+ *   - All GPU work is enqueued on the registered stream (the null stream
+ *     by default).  Functions that return host scalars synchronise it.
+ *   - Floating-point state is real FP64 unless stated; GEMM-heavy steps
+ *     can run in FP32 or BF16 with FP32 accumulation (qed_set_precision).
+ *
+ * Layout contract of a three-leg U(1) block tensor (legs l, r, p):
+ *   each leg is a list of sectors with strictly ascending charges q and
+ *   sizes n > 0.  The allowed blocks are the (l, r, p) sector triples with
+ *   q_l + q_r - q_p = flux (node tensors: flux 0), sorted by (q_l, q_r)
+ *   ascending; block b is stored at flat[off[b] .. off[b+1]) with off the
+ *   int64 prefix sums of n_l n_r n_p, and the entry (i_l, i_r, i_p) of a
+ *   block at (i_l * n_r + i_r) * n_p + i_p.
+ * Layout of a block-sparse leg operator with charge shift delta (maps
+ *   sector q to sector q + delta of the same leg): for every input sector
+ *   in ascending order whose shifted charge is a sector of the leg, one
+ *   dense row-major (n_{q+delta} x n_q) block, blocks concatenated.
+ */
+#ifndef QEDTTN_H
+#define QEDTTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QED_OK = 0,
+    QED_NOT_CONVERGED = 1,
+    QED_ERR_INVALID_ARG = -1,
+    QED_ERR_BAD_STATE = -2,
+    QED_ERR_OOM = -3,
+    QED_ERR_HIP = -4,
+    QED_ERR_NONFINITE = -6,
+    QED_ERR_UNSUPPORTED = -7,
+    QED_ERR_IO = -8
+};
+
+/* Boundary readings for open lattices.  The paper runs open boundaries,
+ * including finite charge density (Results, "Finite Density"), without
+ * fixing the outward half-links.  ZERO_FLUX freezes each outward rishon
+ * at k = 1 (E = 0; only Q = 0 exists); FREE_FLUX keeps it a free 3-state
+ * mode with electric energy (g_e^2/2) E^2 and no penalty partner.
+ * PERIODIC (used for the zero-density transition in the paper) is not
+ * supported by this version and returns QED_ERR_UNSUPPORTED. */
+enum { QED_BC_OPEN_ZERO_FLUX = 0, QED_BC_OPEN_FREE_FLUX = 1, QED_BC_PERIODIC = 2 };
+
+/* Arithmetic of the block GEMMs (H_eff matvec).  Lanczos, QR, the
+ * environment renormalisation and energies are always FP64. */
+enum { QED_FP64 = 0, QED_FP32 = 1, QED_BF16 = 2 };
+
+typedef struct qed_ctx qed_ctx;
+typedef struct qed_heff qed_heff;
+typedef struct qed_heff_batch qed_heff_batch;
+
+/* Per-sweep record (Methods, "Numerical Convergence": energy, penalty and
+ * link-constraint error tracked along the optimisation). */
+typedef struct {
+    double energy;     /* energy after the last node update of the sweep  */
+    double dE;         /* energy change against the previous sweep        */
+    double nu;         /* penalty coefficient used in this sweep          */
+    double deltaL;     /* sum over links of |<L_{x,mu} - 2>|              */
+    double Q;          /* <total charge>                                  */
+    double seconds;    /* wall time of the sweep                          */
+    double flops;      /* algorithmic H_eff matvec flops in the sweep     */
+    long long matvecs; /* H_eff applications in the sweep                 */
+} qed_sweep_report;
+
+/* ---------------------------------------------------------------- */
+/* context                                                           */
+/* ---------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `hip_device`.  hip_device < 0
+ * creates a host-only context (model, tree and block-table queries
+ * only; any GPU call on it returns QED_ERR_BAD_STATE).  *out is owned by
+ * the caller and freed with qed_destroy. */
+int qed_create(qed_ctx** out, int hip_device);
+int qed_destroy(qed_ctx* ctx);
+const char* qed_last_error(const qed_ctx* ctx);
+
+/* Device allocator hook: alloc(bytes, stream, user) returns device
+ * memory or NULL; free(ptr, stream, user) releases it.  Both NULL
+ * restores the default (hipMallocAsync / hipFreeAsync on the stream).
+ * Must be called before any device allocation of the context. */
+int qed_set_allocator(qed_ctx* ctx,
+                      void* (*alloc)(uint64_t bytes, void* stream, void* user),
+                      void (*free_fn)(void* ptr, void* stream, void* user),
+                      void* user);
+
+/* HIP stream (hipStream_t as void*) for all work of the context. */
+int qed_set_stream(qed_ctx* ctx, void* hip_stream);
+
+/* ---------------------------------------------------------------- */
+/* problem definition (Results, "The model", Eq. 1; Methods)         */
+/* ---------------------------------------------------------------- */
+
+/* Lattice Lx x Ly x Lz (sites x = (i, j, k), flat index
+ * i + Lx (j + Ly k)).  Each extent must be a power of two (binary tree,
+ * Methods "Tensor Networks"), with at least two sites; bc is a QED_BC_*. */
+int qed_set_lattice(qed_ctx* ctx, int Lx, int Ly, int Lz, int bc);
+
+/* Couplings of Eq. 1: hopping t, staggered mass m, electric g_e^2,
+ * magnetic g_m^2 (treated as independent, as in the paper). */
+int qed_set_couplings(qed_ctx* ctx, double t, double m, double g2_e, double g2_m);
+
+/* Physical line (Results): with a = 1/t, g_e^2 = g^2 t, g_m^2 = 8 t / g^2,
+ * so that g_e g_m = 2 sqrt(2) t.  Pure function, no context. */
+int qed_physical_line(double g2, double t, double* g2_e, double* g2_m);
+
+/* Link penalty nu sum (1 - delta_{2,L}) (Methods, penalty equation) and
+ * its driven schedule: n_linear sweeps growing linearly from nu_max/20
+ * to nu_max/4, then n_quadratic sweeps growing quadratically to nu_max,
+ * then constant.  n_linear = n_quadratic = 0 keeps nu = nu_max.
+ * adaptive must be 0 in this version. */
+int qed_set_penalty(qed_ctx* ctx, double nu_max, int n_linear, int n_quadratic, int adaptive);
+
+/* Total charge Q = N - L^3/2 (Results).  Q != 0 needs the free-flux
+ * boundary; |Q| above what the boundary can carry is QED_ERR_INVALID_ARG
+ * at qed_build_hamiltonian. */
+int qed_set_charge_sector(qed_ctx* ctx, int Q);
+
+/* Bond dimension chi of every internal tree leg (chi >= 1). */
+int qed_set_bond_dim(qed_ctx* ctx, int chi);
+
+/* Lanczos (Methods, step (ii)): cycles of `steps` steps with full
+ * reorthogonalisation, restarted from the Ritz vector until the residual
+ * is <= tol |theta| or `max_cycles` cycles ran (tol = 0: always all). */
+int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol);
+
+/* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16).  refine != 0 adds one
+ * FP64 Rayleigh quotient per node update on the reduced-precision paths
+ * (the node energy then carries an error second order in the eigenvector
+ * error). */
+int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine);
+
+/* Build the dressed-site bases, local operators, the term list, the tree
+ * and its leg sectors.  Needs lattice, couplings, charge and chi. */
+int qed_build_hamiltonian(qed_ctx* ctx);
+
+/* Local dimension of every site (int[N]). */
+int qed_get_local_dims(qed_ctx* ctx, int* dims);
+
+/* Tree shape: number of nodes, and for node n its legs as link ids
+ * (site s is link s, node n's parent leg is link N + n). */
+int qed_get_tree(qed_ctx* ctx, int* n_nodes, int* n_sites);
+int qed_get_node_links(qed_ctx* ctx, int node, int links[3]);
+
+/* Sectors of a link: up to `cap` (charge, size) pairs, *nsec set to the
+ * full count. */
+int qed_get_leg_sectors(qed_ctx* ctx, int link, int* charges, int* sizes, int cap, int* nsec);
+
+/* ---------------------------------------------------------------- */
+/* state                                                             */
+/* ---------------------------------------------------------------- */
+
+/* Seeded initial node tensors: entry i of node n is 2u - 1 with u the
+ * i-th SplitMix64 uniform of stream (seed, n) (counter-based: key =
+ * mix(seed ^ mix(n + 0x632BE59BD9B4E019)), word_i = mix(key + (i+1) *
+ * 0x9E3779B97F4A7C15), u = (word >> 11) 2^-53). */
+int qed_init_state(qed_ctx* ctx, uint64_t seed);
+
+/* Copy one node tensor in (host, FP64, canonical flat layout of length
+ * n_entries) or out.  Setting a node invalidates the environments. */
+int qed_set_node(qed_ctx* ctx, int node, const double* host_blocks, int64_t n_entries);
+int qed_get_node(qed_ctx* ctx, int node, double* host_blocks, int64_t n_entries);
+int qed_node_size(qed_ctx* ctx, int node, int64_t* n_entries);
+
+/* Run n sweeps (Methods: single-tensor updates from the lowest to the
+ * highest layer); rep (optional, n entries) receives one record each. */
+int qed_sweep(qed_ctx* ctx, int n, qed_sweep_report* rep);
+
+int qed_get_energy(qed_ctx* ctx, double* E);
+
+/* Local observables of the current state (isometry centre moved to the
+ * root): occ[N] = <psi^dag psi>_x, efield[3N] = <E_{x,mu}> (0 where the
+ * link does not exist), deltaL = sum_links |<L - 2>|, rho = mean of
+ * n_x = (1 - (-1)^x)/2 + (-1)^x psi^dag psi, Q = <total charge>.
+ * Any output pointer may be NULL. */
+int qed_get_observables(qed_ctx* ctx, double* occ, double* efield, double* deltaL,
+                        double* rho, double* Q);
+
+/* Cumulative counters of the context.  matvec_flops / matvecs: algorithmic
+ * work of every H_eff application (sweeps and node-level objects).
+ * With profiling on, every launch of the block-GEMM kernel that belongs
+ * to an H_eff application is bracketed by HIP events on the context's
+ * stream: gemm_launches, gemm_ms (sum of the event intervals) and
+ * gemm_flops (algorithmic flops of those launches). */
+typedef struct {
+    double matvec_flops;
+    long long matvecs;
+    long long gemm_launches;
+    double gemm_ms;
+    double gemm_flops;
+} qed_stats;
+
+/* Profiling switch (0/1) for the H_eff block-GEMM launches; resets the
+ * GEMM counters.  Synchronises the stream when stats are read. */
+int qed_set_profiling(qed_ctx* ctx, int on);
+int qed_get_stats(qed_ctx* ctx, qed_stats* out);
+
+/* ---------------------------------------------------------------- */
+/* block tables (pure host integer work, bit-exact contract)         */
+/* ---------------------------------------------------------------- */
+
+/* Allowed blocks of a three-leg tensor with the given flux.  triples
+ * (3*nblk ints: sector indices l, r, p) and offs (nblk+1 int64) may be
+ * NULL to query *nblk first; cap is the capacity in blocks. */
+int qed_node_blocks(const int* ch_l, const int* n_l, int s_l,
+                    const int* ch_r, const int* n_r, int s_r,
+                    const int* ch_p, const int* n_p, int s_p,
+                    int flux, int cap, int* nblk, int* triples, int64_t* offs);
+
+/* ---------------------------------------------------------------- */
+/* node-level effective Hamiltonian (Methods, steps (i)-(ii))         */
+/* ---------------------------------------------------------------- */
+
+/* One term c * A (x) B (x) C.  op[i] is a device FP64 block-sparse leg
+ * operator (layout above) for leg i (0 = l, 1 = r, 2 = p) with charge
+ * shift shift[i], or NULL for the identity.  shift_l + shift_r must
+ * equal shift_p. */
+typedef struct {
+    double coef;
+    const double* op[3];
+    int shift[3];
+} qed_term;
+
+/* Build H_eff = sum_k terms[k] on a node with the given legs, in the
+ * context's GEMM precision.  Operators are copied (converted) at create
+ * time; the caller keeps ownership of its buffers. */
+int qed_heff_create(qed_ctx* ctx,
+                    const int* ch_l, const int* n_l, int s_l,
+                    const int* ch_r, const int* n_r, int s_r,
+                    const int* ch_p, const int* n_p, int s_p,
+                    int K, const qed_term* terms, qed_heff** out);
+int qed_heff_destroy(qed_heff* h);
+
+/* y = H_eff x on device FP64 flat vectors of length *size (x, y must not
+ * alias). */
+int qed_heff_size(qed_heff* h, int64_t* size);
+int qed_heff_matvec(qed_heff* h, const double* x, double* y);
+
+/* Lanczos for the lowest eigenpair started from x (device FP64); x is
+ * overwritten by the normalised Ritz vector; *eval receives theta and
+ * *resid (may be NULL) the residual estimate.  `steps` per cycle, cycles
+ * and tolerance as set by qed_set_lanczos (steps <= 0: context value). */
+int qed_heff_lanczos(qed_heff* h, double* x_inout, int steps, double* eval, double* resid);
+
+/* Algorithmic work of one matvec: flops (identity factors and skipped
+ * dense work not counted) and the bytes of x, y and the non-identity
+ * operator blocks in the GEMM dtype. */
+int qed_heff_flops(qed_heff* h, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QEDTTN_H */

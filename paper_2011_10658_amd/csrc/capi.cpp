@@ -1,0 +1,544 @@
+// extern "C" boundary of libqedttn (declarations and contracts in
+// include/qedttn.h).  Every entry point turns internal errors into status
+// codes and a context-owned message.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "engine.h"
+
+using namespace qed;
+
+struct qed_ctx {
+    Ctx c;
+};
+
+struct qed_heff {
+    Heff h;
+    qed_ctx* owner = nullptr;
+};
+
+namespace {
+
+template <typename F>
+int guard(qed_ctx* ctx, F&& f) {
+    if (!ctx) return QED_ERR_INVALID_ARG;
+    try {
+        ctx->c.err.clear();
+        return f();
+    } catch (const Error& e) {
+        ctx->c.err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        ctx->c.err = "host out of memory";
+        return QED_ERR_OOM;
+    } catch (const std::exception& e) {
+        ctx->c.err = e.what();
+        return QED_ERR_INVALID_ARG;
+    }
+}
+
+Ctx& C(qed_ctx* c) { return c->c; }
+
+void need_device(Ctx& c) {
+    if (c.host_only) fail(QED_ERR_BAD_STATE, "host-only context: no GPU work possible");
+}
+
+void need_built(Ctx& c) {
+    if (!c.built || !c.eng) fail(QED_ERR_BAD_STATE, "call qed_build_hamiltonian first");
+}
+
+Leg make_leg(const int* ch, const int* n, int s) {
+    if (s <= 0 || !ch || !n) fail(QED_ERR_INVALID_ARG, "a leg needs at least one sector");
+    Leg L;
+    for (int i = 0; i < s; ++i) {
+        if (n[i] <= 0) fail(QED_ERR_INVALID_ARG, "sector sizes must be positive");
+        if (i && ch[i] <= ch[i - 1]) fail(QED_ERR_INVALID_ARG, "charges must be strictly ascending");
+        L.q.push_back(ch[i]);
+        L.n.push_back(n[i]);
+    }
+    return L;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int qed_create(qed_ctx** out, int hip_device) {
+    if (!out) return QED_ERR_INVALID_ARG;
+    *out = nullptr;
+    qed_ctx* ctx = new (std::nothrow) qed_ctx();
+    if (!ctx) return QED_ERR_OOM;
+    if (hip_device >= 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) {
+            delete ctx;
+            return QED_ERR_HIP;
+        }
+        if (hipSetDevice(hip_device) != hipSuccess) {
+            delete ctx;
+            return QED_ERR_HIP;
+        }
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, hip_device) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        ctx->c.dev.device = hip_device;
+        ctx->c.host_only = false;
+    }
+    *out = ctx;
+    return QED_OK;
+}
+
+int qed_destroy(qed_ctx* ctx) {
+    if (!ctx) return QED_ERR_INVALID_ARG;
+    try {
+        if (!ctx->c.host_only) {
+            (void)hipSetDevice(ctx->c.dev.device);
+            (void)hipStreamSynchronize(ctx->c.dev.stream);
+        }
+        ctx->c.eng.reset();
+        if (!ctx->c.host_only) (void)hipStreamSynchronize(ctx->c.dev.stream);
+    } catch (...) {
+    }
+    delete ctx;
+    return QED_OK;
+}
+
+const char* qed_last_error(const qed_ctx* ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+int qed_set_allocator(qed_ctx* ctx, void* (*alloc)(uint64_t, void*, void*),
+                      void (*free_fn)(void*, void*, void*), void* user) {
+    return guard(ctx, [&] {
+        if ((alloc == nullptr) != (free_fn == nullptr))
+            fail(QED_ERR_INVALID_ARG, "alloc and free must both be set or both be NULL");
+        if (C(ctx).dev.used) fail(QED_ERR_BAD_STATE, "the allocator must be set before any allocation");
+        C(ctx).dev.ualloc = alloc;
+        C(ctx).dev.ufree = free_fn;
+        C(ctx).dev.user = user;
+        return QED_OK;
+    });
+}
+
+int qed_set_stream(qed_ctx* ctx, void* stream) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        C(ctx).dev.sync();
+        C(ctx).dev.stream = (hipStream_t)stream;
+        return QED_OK;
+    });
+}
+
+int qed_set_lattice(qed_ctx* ctx, int Lx, int Ly, int Lz, int bc) {
+    return guard(ctx, [&] {
+        if (bc == QED_BC_PERIODIC) fail(QED_ERR_UNSUPPORTED, "periodic boundaries are not supported");
+        if (bc != QED_BC_OPEN_ZERO_FLUX && bc != QED_BC_OPEN_FREE_FLUX)
+            fail(QED_ERR_INVALID_ARG, "unknown boundary condition");
+        if (!pow2(Lx) || !pow2(Ly) || !pow2(Lz))
+            fail(QED_ERR_INVALID_ARG, "lattice extents must be powers of two");
+        if ((int64_t)Lx * Ly * Lz < 2 || (int64_t)Lx * Ly * Lz > 4096)
+            fail(QED_ERR_INVALID_ARG, "the lattice needs 2 .. 4096 sites");
+        Params& P = C(ctx).prm;
+        P.Lx = Lx;
+        P.Ly = Ly;
+        P.Lz = Lz;
+        P.bc = bc;
+        P.have_lattice = true;
+        C(ctx).built = false;
+        return QED_OK;
+    });
+}
+
+int qed_set_couplings(qed_ctx* ctx, double t, double m, double g2_e, double g2_m) {
+    return guard(ctx, [&] {
+        if (!std::isfinite(t) || !std::isfinite(m) || !std::isfinite(g2_e) || !std::isfinite(g2_m))
+            fail(QED_ERR_INVALID_ARG, "couplings must be finite");
+        Params& P = C(ctx).prm;
+        P.t = t;
+        P.m = m;
+        P.g2e = g2_e;
+        P.g2m = g2_m;
+        P.have_couplings = true;
+        C(ctx).built = false;
+        return QED_OK;
+    });
+}
+
+int qed_physical_line(double g2, double t, double* g2_e, double* g2_m) {
+    if (!g2_e || !g2_m || !(g2 > 0.0) || !std::isfinite(t)) return QED_ERR_INVALID_ARG;
+    *g2_e = g2 * t;
+    *g2_m = 8.0 * t / g2;
+    return QED_OK;
+}
+
+int qed_set_penalty(qed_ctx* ctx, double nu_max, int n_linear, int n_quadratic, int adaptive) {
+    return guard(ctx, [&] {
+        if (!(nu_max >= 0.0) || n_linear < 0 || n_quadratic < 0)
+            fail(QED_ERR_INVALID_ARG, "invalid penalty schedule");
+        if (adaptive) fail(QED_ERR_UNSUPPORTED, "the adaptive penalty switch is not implemented");
+        Params& P = C(ctx).prm;
+        P.nu_max = nu_max;
+        P.n_lin = n_linear;
+        P.n_quad = n_quadratic;
+        return QED_OK;
+    });
+}
+
+int qed_set_charge_sector(qed_ctx* ctx, int Q) {
+    return guard(ctx, [&] {
+        C(ctx).prm.Q = Q;
+        C(ctx).built = false;
+        return QED_OK;
+    });
+}
+
+int qed_set_bond_dim(qed_ctx* ctx, int chi) {
+    return guard(ctx, [&] {
+        if (chi < 1 || chi > 65536) fail(QED_ERR_INVALID_ARG, "chi out of range");
+        C(ctx).prm.chi = chi;
+        C(ctx).built = false;
+        return QED_OK;
+    });
+}
+
+int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol) {
+    return guard(ctx, [&] {
+        if (steps < 1 || steps > 64 || max_cycles < 1 || !(tol >= 0.0))
+            fail(QED_ERR_INVALID_ARG, "Lanczos: 1 <= steps <= 64, cycles >= 1, tol >= 0");
+        Params& P = C(ctx).prm;
+        P.lz_steps = steps;
+        P.lz_cycles = max_cycles;
+        P.lz_tol = tol;
+        return QED_OK;
+    });
+}
+
+int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine) {
+    return guard(ctx, [&] {
+        if (gemm_dtype == QED_BF16) fail(QED_ERR_UNSUPPORTED, "BF16 GEMMs are not available in this build");
+        if (gemm_dtype != QED_FP64 && gemm_dtype != QED_FP32)
+            fail(QED_ERR_INVALID_ARG, "unknown GEMM dtype");
+        C(ctx).prm.dtype = gemm_dtype;
+        C(ctx).prm.refine = refine ? 1 : 0;
+        return QED_OK;
+    });
+}
+
+int qed_build_hamiltonian(qed_ctx* ctx) {
+    return guard(ctx, [&] {
+        Ctx& c = C(ctx);
+        if (!c.prm.have_lattice || !c.prm.have_couplings)
+            fail(QED_ERR_BAD_STATE, "set the lattice and the couplings first");
+        if (!c.host_only) (void)hipSetDevice(c.dev.device);
+        auto e = std::make_unique<Engine>();
+        e->build(&c);
+        if (c.eng && !c.host_only) c.dev.sync();
+        c.eng = std::move(e);
+        c.built = true;
+        return QED_OK;
+    });
+}
+
+int qed_get_local_dims(qed_ctx* ctx, int* dims) {
+    return guard(ctx, [&] {
+        need_built(C(ctx));
+        if (!dims) fail(QED_ERR_INVALID_ARG, "dims is NULL");
+        const auto& m = C(ctx).eng->model;
+        for (int s = 0; s < m.lat.N; ++s) dims[s] = m.sites[s].d();
+        return QED_OK;
+    });
+}
+
+int qed_get_tree(qed_ctx* ctx, int* n_nodes, int* n_sites) {
+    return guard(ctx, [&] {
+        need_built(C(ctx));
+        if (n_nodes) *n_nodes = (int)C(ctx).eng->tree.nodes.size();
+        if (n_sites) *n_sites = C(ctx).eng->tree.N;
+        return QED_OK;
+    });
+}
+
+int qed_get_node_links(qed_ctx* ctx, int node, int links[3]) {
+    return guard(ctx, [&] {
+        need_built(C(ctx));
+        const Tree& t = C(ctx).eng->tree;
+        if (node < 0 || node >= (int)t.nodes.size() || !links) fail(QED_ERR_INVALID_ARG, "bad node");
+        links[0] = t.nodes[node].l;
+        links[1] = t.nodes[node].r;
+        links[2] = t.nodes[node].p;
+        return QED_OK;
+    });
+}
+
+int qed_get_leg_sectors(qed_ctx* ctx, int link, int* charges, int* sizes, int cap, int* nsec) {
+    return guard(ctx, [&] {
+        need_built(C(ctx));
+        const Engine& e = *C(ctx).eng;
+        if (link < 0 || link >= e.tree.nlinks()) fail(QED_ERR_INVALID_ARG, "bad link");
+        const Leg& L = e.legs[link];
+        if (nsec) *nsec = L.nsec();
+        for (int i = 0; i < L.nsec() && i < cap; ++i) {
+            if (charges) charges[i] = L.q[i];
+            if (sizes) sizes[i] = L.n[i];
+        }
+        return QED_OK;
+    });
+}
+
+int qed_init_state(qed_ctx* ctx, uint64_t seed) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        C(ctx).eng->init_nodes(seed);
+        return QED_OK;
+    });
+}
+
+int qed_node_size(qed_ctx* ctx, int node, int64_t* n_entries) {
+    return guard(ctx, [&] {
+        need_built(C(ctx));
+        const Engine& e = *C(ctx).eng;
+        if (node < 0 || node >= (int)e.tree.nodes.size() || !n_entries) fail(QED_ERR_INVALID_ARG, "bad node");
+        const auto& nd = e.tree.nodes[node];
+        *n_entries = make_table(e.legs[nd.l], e.legs[nd.r], e.legs[nd.p], 0).size();
+        return QED_OK;
+    });
+}
+
+int qed_set_node(qed_ctx* ctx, int node, const double* host, int64_t n) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (node < 0 || node >= (int)e.tree.nodes.size() || !host) fail(QED_ERR_INVALID_ARG, "bad node");
+        if (e.nodes.empty()) e.init_nodes(0);
+        TensorD& T = e.nodes[node];
+        if (n != T.tab.size()) fail(QED_ERR_INVALID_ARG, "wrong number of entries");
+        C(ctx).dev.upload(T.d->p, host, n * sizeof(double));
+        e.invalidate();
+        return QED_OK;
+    });
+}
+
+int qed_get_node(qed_ctx* ctx, int node, double* host, int64_t n) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (node < 0 || node >= (int)e.nodes.size() || !host) fail(QED_ERR_INVALID_ARG, "bad node");
+        TensorD& T = e.nodes[node];
+        if (n != T.tab.size()) fail(QED_ERR_INVALID_ARG, "wrong number of entries");
+        C(ctx).dev.download(host, T.d->p, n * sizeof(double));
+        return QED_OK;
+    });
+}
+
+int qed_sweep(qed_ctx* ctx, int n, qed_sweep_report* rep) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        if (n < 0) fail(QED_ERR_INVALID_ARG, "negative sweep count");
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state: call qed_init_state first");
+        for (int i = 0; i < n; ++i) e.sweep(i, rep ? rep + i : nullptr);
+        if (e.have_energy && !std::isfinite(e.energy)) fail(QED_ERR_NONFINITE, "non-finite energy");
+        return QED_OK;
+    });
+}
+
+int qed_get_energy(qed_ctx* ctx, double* E) {
+    return guard(ctx, [&] {
+        need_built(C(ctx));
+        if (!E) fail(QED_ERR_INVALID_ARG, "E is NULL");
+        if (!C(ctx).eng->have_energy) fail(QED_ERR_BAD_STATE, "no sweep has run");
+        *E = C(ctx).eng->energy;
+        return QED_OK;
+    });
+}
+
+int qed_get_observables(qed_ctx* ctx, double* occ, double* efield, double* deltaL, double* rho,
+                        double* Q) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state");
+        std::vector<double> s7;
+        e.observables(s7);
+        const Lattice& L = e.model.lat;
+        double dL = 0.0, q = 0.0, r = 0.0;
+        for (int x = 0; x < L.N; ++x) {
+            const double phi = s7[x * 7];
+            const int p = L.parity(x);
+            if (occ) occ[x] = phi;
+            q += phi - p;
+            r += p + (1 - 2 * p) * phi;
+            for (int mu = 0; mu < 3; ++mu) {
+                const int y = L.neighbour(x, 3 + mu);
+                if (efield) efield[x * 3 + mu] = y < 0 ? 0.0 : 1.0 - s7[x * 7 + 1 + 3 + mu];
+                if (y >= 0) dL += std::fabs(s7[x * 7 + 1 + 3 + mu] + s7[y * 7 + 1 + mu] - 2.0);
+            }
+        }
+        if (deltaL) *deltaL = dL;
+        if (rho) *rho = r / L.N;
+        if (Q) *Q = q;
+        return QED_OK;
+    });
+}
+
+int qed_set_profiling(qed_ctx* ctx, int on) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        C(ctx).dev.sync();
+        C(ctx).prof.reset();
+        C(ctx).prof.on = on != 0;
+        return QED_OK;
+    });
+}
+
+int qed_get_stats(qed_ctx* ctx, qed_stats* out) {
+    return guard(ctx, [&] {
+        if (!out) fail(QED_ERR_INVALID_ARG, "out is NULL");
+        if (!C(ctx).host_only) {
+            C(ctx).dev.sync();
+            C(ctx).prof.harvest();
+        }
+        out->matvec_flops = C(ctx).mv_flops;
+        out->matvecs = C(ctx).mv_count;
+        out->gemm_launches = C(ctx).prof.launches;
+        out->gemm_ms = C(ctx).prof.ms;
+        out->gemm_flops = C(ctx).prof.flops;
+        return QED_OK;
+    });
+}
+
+int qed_node_blocks(const int* ch_l, const int* n_l, int s_l, const int* ch_r, const int* n_r,
+                    int s_r, const int* ch_p, const int* n_p, int s_p, int flux, int cap, int* nblk,
+                    int* triples, int64_t* offs) {
+    try {
+        Leg l = make_leg(ch_l, n_l, s_l), r = make_leg(ch_r, n_r, s_r), p = make_leg(ch_p, n_p, s_p);
+        BlockTable t = make_table(l, r, p, flux);
+        if (!nblk) return QED_ERR_INVALID_ARG;
+        *nblk = t.nblk();
+        if ((triples || offs) && cap < t.nblk()) return QED_ERR_INVALID_ARG;
+        for (int b = 0; b < t.nblk(); ++b) {
+            if (triples) {
+                triples[3 * b] = t.s[0][b];
+                triples[3 * b + 1] = t.s[1][b];
+                triples[3 * b + 2] = t.s[2][b];
+            }
+            if (offs) offs[b] = t.off[b];
+        }
+        if (offs) offs[t.nblk()] = t.size();
+        return QED_OK;
+    } catch (const Error& e) {
+        return e.code;
+    } catch (...) {
+        return QED_ERR_INVALID_ARG;
+    }
+}
+
+int qed_heff_create(qed_ctx* ctx, const int* ch_l, const int* n_l, int s_l, const int* ch_r,
+                    const int* n_r, int s_r, const int* ch_p, const int* n_p, int s_p, int K,
+                    const qed_term* terms, qed_heff** out) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        if (!out || K < 0 || (K > 0 && !terms)) fail(QED_ERR_INVALID_ARG, "bad arguments");
+        *out = nullptr;
+        auto h = std::make_unique<qed_heff>();
+        Heff& H = h->h;
+        h->owner = ctx;
+        H.ctx = &C(ctx);
+        H.legs[0] = make_leg(ch_l, n_l, s_l);
+        H.legs[1] = make_leg(ch_r, n_r, s_r);
+        H.legs[2] = make_leg(ch_p, n_p, s_p);
+        H.tab = make_table(H.legs[0], H.legs[1], H.legs[2], 0);
+        if (H.tab.nblk() == 0) fail(QED_ERR_INVALID_ARG, "the node has no allowed block");
+        Dev* dev = &C(ctx).dev;
+        for (int k = 0; k < K; ++k) {
+            const qed_term& t = terms[k];
+            if (!std::isfinite(t.coef)) fail(QED_ERR_INVALID_ARG, "non-finite coefficient");
+            int sh[3];
+            for (int e = 0; e < 3; ++e) sh[e] = t.op[e] ? t.shift[e] : 0;
+            if (sh[0] + sh[1] != sh[2]) fail(QED_ERR_INVALID_ARG, "term shifts must obey shift_l + shift_r = shift_p");
+            HTerm ht{t.coef, {nullptr, nullptr, nullptr}};
+            for (int e = 0; e < 3; ++e) {
+                if (!t.op[e]) continue;
+                OpP o = make_op(dev, H.legs[e], sh[e], false);
+                if (o->lay.size)
+                    dev->check(hipMemcpyAsync(o->d64->p, t.op[e], o->lay.size * sizeof(double),
+                                              hipMemcpyDeviceToDevice, dev->stream), "operator copy");
+                ht.op[e] = o;
+            }
+            H.terms.push_back(ht);
+        }
+        const int dtype = C(ctx).prm.dtype;
+        H.plan = plan_matvec(H.legs, H.tab, H.terms, dtype);
+        H.plan.upload(dev);
+        if (dtype != QED_FP64) {
+            H.xc = std::make_shared<DBuf>(dev, H.tab.size() * sizeof(float));
+            H.yc = std::make_shared<DBuf>(dev, H.tab.size() * sizeof(float));
+        }
+        dev->sync();
+        *out = h.release();
+        return QED_OK;
+    });
+}
+
+int qed_heff_destroy(qed_heff* h) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    try {
+        (void)hipStreamSynchronize(h->h.ctx->dev.stream);
+    } catch (...) {
+    }
+    delete h;
+    return QED_OK;
+}
+
+int qed_heff_size(qed_heff* h, int64_t* size) {
+    if (!h || !size) return QED_ERR_INVALID_ARG;
+    *size = h->h.tab.size();
+    return QED_OK;
+}
+
+int qed_heff_matvec(qed_heff* h, const double* x, double* y) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    qed_ctx* ctx = h->owner;
+    return guard(ctx, [&] {
+        if (!x || !y || x == y) fail(QED_ERR_INVALID_ARG, "x and y must be distinct device buffers");
+        h->h.matvec(x, y);
+        h->h.ctx->dev.check(hipGetLastError(), "matvec");
+        return QED_OK;
+    });
+}
+
+int qed_heff_lanczos(qed_heff* h, double* x, int steps, double* eval, double* resid) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    qed_ctx* ctx = h->owner;
+    return guard(ctx, [&] {
+        if (!x || !eval) fail(QED_ERR_INVALID_ARG, "x and eval are required");
+        Heff& H = h->h;
+        const Params& P = H.ctx->prm;
+        const int m = steps > 0 ? steps : P.lz_steps;
+        if (m > 64) fail(QED_ERR_INVALID_ARG, "at most 64 Lanczos steps");
+        LanczosResult R = lanczos(&H.ctx->dev, H.lws,
+                                  [&](const double* v, double* w) { H.matvec(v, w); }, x,
+                                  H.tab.size(), m, P.lz_cycles, P.lz_tol);
+        *eval = R.theta;
+        if (resid) *resid = R.resid;
+        if (P.lz_tol > 0 && R.resid > P.lz_tol * std::fabs(R.theta)) return (int)QED_NOT_CONVERGED;
+        return (int)QED_OK;
+    });
+}
+
+int qed_heff_flops(qed_heff* h, double* flops, double* bytes) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    if (flops) *flops = h->h.plan.flops;
+    if (bytes) *bytes = h->h.plan.bytes;
+    return QED_OK;
+}
+
+}  // extern "C"

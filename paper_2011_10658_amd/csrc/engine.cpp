@@ -1,0 +1,576 @@
+// Host side of the device engine: memory, plans, Lanczos, the TTN sweep.
+//
+// Every contraction of the node update is planned here as a list of
+// block-level GEMM jobs and executed by the grouped batch-reduce GEMM
+// kernel in stages:
+//   H_eff matvec  (Methods, "Tensor Networks" steps (i)-(ii)):
+//     stage 0: T1 = x  x_p C_k   for every term with C_k != 1, every block
+//     stage 1: T2 = T1 x_r B_k   (batched over the l index)
+//     stage 2: y_b = sum_k c_k A_k T2_k  (or c_k T2_k when A_k = 1): one job
+//              per output block sums every term and input block that lands
+//              on it, so y is written once, with no atomics.
+//   renormalisation of the environment across a leg (step (iii) moves the
+//   isometry centre): T = n x_f1 A x_f2 B, then O[out, in] = sum over the
+//   two other legs of n * T, again one job per output block.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace qed {
+
+// ---------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------
+void Dev::check(hipError_t e, const char* what) {
+    if (e != hipSuccess)
+        fail(QED_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* Dev::alloc(size_t bytes) {
+    if (device < 0) fail(QED_ERR_BAD_STATE, "host-only context has no device memory");
+    used = true;
+    void* p = nullptr;
+    if (ualloc) {
+        p = ualloc((uint64_t)bytes, (void*)stream, user);
+        if (!p) fail(QED_ERR_OOM, "allocator hook returned NULL");
+        return p;
+    }
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e == hipErrorOutOfMemory) fail(QED_ERR_OOM, "out of device memory");
+    check(e, "hipMallocAsync");
+    return p;
+}
+
+void Dev::release(void* p) {
+    if (!p) return;
+    if (ufree) {
+        ufree(p, (void*)stream, user);
+        return;
+    }
+    (void)hipFreeAsync(p, stream);
+}
+
+void Dev::sync() { check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+void Dev::upload(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream), "upload");
+    sync();  // the host buffer may be temporary
+}
+
+void Dev::download(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream), "download");
+    sync();
+}
+
+const void* LegOpD::data(int dtype) {
+    if (dtype == QED_FP64) return f64();
+    if (!d32 && lay.size) {
+        d32 = std::make_shared<DBuf>(dev, lay.size * sizeof(float));
+        launch_f64_to_f32(f64(), d32->as<float>(), lay.size, dev->stream);
+    }
+    return d32 ? d32->p : nullptr;
+}
+
+OpP make_op(Dev* dev, const Leg& leg, int delta, bool zero) {
+    auto o = std::make_shared<LegOpD>();
+    o->dev = dev;
+    o->leg = leg;
+    o->lay = make_op_layout(leg, delta);
+    if (o->lay.size) {
+        o->d64 = std::make_shared<DBuf>(dev, o->lay.size * sizeof(double));
+        if (zero) launch_fill(o->d64->as<double>(), o->lay.size, 0.0, dev->stream);
+    }
+    return o;
+}
+
+// ---------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------
+namespace {
+
+GRef gabs(const void* p) { return GRef{p, 0, TAG_ABS, 0}; }
+GRef gtag(int tag, int64_t off) { return GRef{nullptr, off, tag, 0}; }
+
+// a dense block: pointer, sector indices and extents per leg
+struct BV {
+    GRef p;
+    int s[3];
+    int n[3];
+};
+
+struct Builder {
+    Plan& P;
+    int esize;
+    explicit Builder(Plan& p) : P(p), esize(p.dtype == QED_FP64 ? 8 : 4) {}
+
+    GRef ws(int64_t n) {
+        GRef r = gtag(TAG_WS, P.ws_elems);
+        P.ws_elems += (n + 63) & ~(int64_t)63;
+        return r;
+    }
+    void stage(int s) {
+        while ((int)P.jobs.size() <= s) {
+            P.jobs.emplace_back();
+            P.prods.emplace_back();
+            P.stage_flops.push_back(0.0);
+        }
+    }
+    void add_flops(int s, double f) {
+        stage(s);
+        P.stage_flops[s] += f;
+        P.flops += f;
+    }
+    void job1(int s, GRef C, int M, int N, int ldc, int batch, int64_t bsC, const GProd& p) {
+        stage(s);
+        GJob j{};
+        j.C = C;
+        j.bsC = bsC;
+        j.M = M;
+        j.N = N;
+        j.ldc = ldc;
+        j.batch = batch;
+        j.p0 = (int)P.prods[s].size();
+        P.prods[s].push_back(p);
+        j.p1 = j.p0 + 1;
+        j.acc = 0;
+        P.jobs[s].push_back(j);
+    }
+    // the product that applies `op` (block opblk, n_out x n_in) on leg e
+    // of block `in`; returns the job shape through M, N, ldc, batch, bsC
+    static GProd mode_prod(const BV& in, int e, GRef opblk, int nout, double alpha, int& M, int& N,
+                           int& ldc, int& batch, int64_t& bsC) {
+        GProd p{};
+        p.alpha = alpha;
+        p.nred = 1;
+        const int n0 = in.n[0], n1 = in.n[1], n2 = in.n[2];
+        if (e == 2) {
+            p.A = in.p; p.lda = n2; p.tA = 0;
+            p.B = opblk; p.ldb = n2; p.tB = 1;
+            p.K = n2;
+            M = n0 * n1; N = nout; ldc = nout; batch = 1; bsC = 0;
+        } else if (e == 1) {
+            p.A = opblk; p.lda = n1; p.tA = 0; p.bsA = 0;
+            p.B = in.p; p.ldb = n2; p.tB = 0; p.bsB = (int64_t)n1 * n2;
+            p.K = n1;
+            M = nout; N = n2; ldc = n2; batch = n0; bsC = (int64_t)nout * n2;
+        } else {
+            p.A = opblk; p.lda = n0; p.tA = 0;
+            p.B = in.p; p.ldb = n1 * n2; p.tB = 0;
+            p.K = n0;
+            M = nout; N = n1 * n2; ldc = n1 * n2; batch = 1; bsC = 0;
+        }
+        return p;
+    }
+    // fresh-workspace mode product; returns false if the output sector
+    // does not exist
+    bool mode(int s, const BV& in, int e, LegOpD& op, const Leg& leg, BV& out) {
+        const int so = op.lay.out_of_in[in.s[e]];
+        if (so < 0) return false;
+        const int nout = leg.n[so];
+        GRef opblk = gabs((const char*)op.data(P.dtype) + op.lay.off[in.s[e]] * esize);
+        int M, N, ldc, batch;
+        int64_t bsC;
+        out = in;
+        out.s[e] = so;
+        out.n[e] = nout;
+        const int64_t sz = (int64_t)out.n[0] * out.n[1] * out.n[2];
+        out.p = ws(sz);
+        GProd p = mode_prod(in, e, opblk, nout, 1.0, M, N, ldc, batch, bsC);
+        job1(s, out.p, M, N, ldc, batch, bsC, p);
+        add_flops(s, 2.0 * in.n[0] * in.n[1] * in.n[2] * nout);
+        return true;
+    }
+};
+
+int64_t key3(int a, int b, int c) { return ((int64_t)a * 4096 + b) * 4096 + c; }
+
+}  // namespace
+
+void Plan::upload(Dev* dev) {
+    dj.clear();
+    dp.clear();
+    dt.clear();
+    ntiles.clear();
+    for (size_t s = 0; s < jobs.size(); ++s) {
+        std::vector<GTile> tiles;
+        for (size_t j = 0; j < jobs[s].size(); ++j) {
+            const GJob& J = jobs[s][j];
+            const int tm = (J.M + GEMM_TM - 1) / GEMM_TM, tn = (J.N + GEMM_TN - 1) / GEMM_TN;
+            for (int b = 0; b < J.batch; ++b)
+                for (int a = 0; a < tm; ++a)
+                    for (int c = 0; c < tn; ++c) tiles.push_back(GTile{(int)j, b, a, c});
+        }
+        auto bj = std::make_shared<DBuf>(dev, jobs[s].size() * sizeof(GJob));
+        auto bp = std::make_shared<DBuf>(dev, std::max<size_t>(1, prods[s].size()) * sizeof(GProd));
+        auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
+        dev->check(hipMemcpyAsync(bj->p, jobs[s].data(), jobs[s].size() * sizeof(GJob),
+                                  hipMemcpyHostToDevice, dev->stream), "plan upload");
+        if (!prods[s].empty())
+            dev->check(hipMemcpyAsync(bp->p, prods[s].data(), prods[s].size() * sizeof(GProd),
+                                      hipMemcpyHostToDevice, dev->stream), "plan upload");
+        dev->check(hipMemcpyAsync(bt->p, tiles.data(), tiles.size() * sizeof(GTile),
+                                  hipMemcpyHostToDevice, dev->stream), "plan upload");
+        dj.push_back(bj);
+        dp.push_back(bp);
+        dt.push_back(bt);
+        ntiles.push_back((int)tiles.size());
+    }
+    dev->sync();  // host vectors of this plan may change afterwards
+}
+
+void Prof::record_begin(hipStream_t s, hipEvent_t& a) {
+    (void)hipEventCreate(&a);
+    (void)hipEventRecord(a, s);
+}
+
+void Prof::harvest() {
+    for (size_t i = 0; i < ev.size(); ++i) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, ev[i].first, ev[i].second) == hipSuccess) ms += t;
+        flops += ev_flops[i];
+        (void)hipEventDestroy(ev[i].first);
+        (void)hipEventDestroy(ev[i].second);
+    }
+    ev.clear();
+    ev_flops.clear();
+}
+
+void Prof::reset() {
+    harvest();
+    launches = 0;
+    ms = flops = 0.0;
+}
+
+Prof::~Prof() {
+    for (auto& e : ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+}
+
+void Plan::run(Dev* dev, void* ws, void* x, void* y) {
+    Bases b;
+    b.b[TAG_ABS] = nullptr;
+    b.b[TAG_WS] = ws;
+    b.b[TAG_X] = x;
+    b.b[TAG_Y] = y;
+    for (size_t s = 0; s < dj.size(); ++s) {
+        if (!ntiles[s]) continue;
+        const bool timed = prof && prof->on;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) prof->record_begin(dev->stream, e0);
+        if (dtype == QED_FP64)
+            launch_brgemm<double>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(),
+                                  ntiles[s], b, dev->stream);
+        else
+            launch_brgemm<float>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(),
+                                 ntiles[s], b, dev->stream);
+        if (timed) {
+            prof->record_begin(dev->stream, e1);
+            prof->ev.push_back({e0, e1});
+            prof->ev_flops.push_back(s < stage_flops.size() ? stage_flops[s] : 0.0);
+            prof->launches += 1;
+        }
+    }
+    dev->check(hipGetLastError(), "brgemm launch");
+}
+
+Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
+                 int dtype) {
+    Plan P;
+    P.dtype = dtype;
+    Builder B(P);
+    B.stage(2);
+    std::map<int64_t, int> bidx;
+    for (int b = 0; b < tab.nblk(); ++b) bidx[key3(tab.s[0][b], tab.s[1][b], tab.s[2][b])] = b;
+    std::vector<std::vector<GProd>> groups(tab.nblk());
+    for (const HTerm& t : terms) {
+        if (t.coef == 0.0) continue;
+        for (int b = 0; b < tab.nblk(); ++b) {
+            BV cur;
+            cur.p = gtag(TAG_X, tab.off[b]);
+            for (int e = 0; e < 3; ++e) {
+                cur.s[e] = tab.s[e][b];
+                cur.n[e] = legs[e].n[cur.s[e]];
+            }
+            // output sectors must all exist
+            int os[3];
+            bool ok = true;
+            for (int e = 0; e < 3; ++e) {
+                os[e] = t.op[e] ? t.op[e]->lay.out_of_in[cur.s[e]] : cur.s[e];
+                if (os[e] < 0) ok = false;
+            }
+            if (!ok) continue;
+            auto it = bidx.find(key3(os[0], os[1], os[2]));
+            if (it == bidx.end()) continue;
+            const int ob = it->second;
+            if (t.op[2]) {
+                BV nxt;
+                B.mode(0, cur, 2, *t.op[2], legs[2], nxt);
+                cur = nxt;
+            }
+            if (t.op[1]) {
+                BV nxt;
+                B.mode(1, cur, 1, *t.op[1], legs[1], nxt);
+                cur = nxt;
+            }
+            GProd p{};
+            if (t.op[0]) {
+                const int nout = legs[0].n[os[0]];
+                GRef opblk = gabs((const char*)t.op[0]->data(dtype) +
+                                  t.op[0]->lay.off[cur.s[0]] * B.esize);
+                int M, N, ldc, batch;
+                int64_t bsC;
+                p = Builder::mode_prod(cur, 0, opblk, nout, t.coef, M, N, ldc, batch, bsC);
+                B.add_flops(2, 2.0 * cur.n[0] * cur.n[1] * cur.n[2] * nout);
+            } else {
+                p.ident = 1;
+                p.B = cur.p;
+                p.ldb = cur.n[1] * cur.n[2];
+                p.alpha = t.coef;
+                p.nred = 1;
+            }
+            groups[ob].push_back(p);
+        }
+    }
+    for (int b = 0; b < tab.nblk(); ++b) {
+        GJob j{};
+        j.C = gtag(TAG_Y, tab.off[b]);
+        const int n0 = legs[0].n[tab.s[0][b]], n1 = legs[1].n[tab.s[1][b]],
+                  n2 = legs[2].n[tab.s[2][b]];
+        j.M = n0;
+        j.N = n1 * n2;
+        j.ldc = n1 * n2;
+        j.batch = 1;
+        j.p0 = (int)P.prods[2].size();
+        for (auto& p : groups[b]) P.prods[2].push_back(p);
+        j.p1 = (int)P.prods[2].size();
+        j.acc = 0;
+        P.jobs[2].push_back(j);
+    }
+    // algorithmic bytes: x, y and the operator blocks in the GEMM dtype
+    const double es = B.esize;
+    P.bytes = 2.0 * tab.size() * es;
+    for (const HTerm& t : terms)
+        for (int e = 0; e < 3; ++e)
+            if (t.op[e] && t.coef != 0.0) P.bytes += t.op[e]->lay.size * es;
+    return P;
+}
+
+Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
+                 const std::vector<OpP>& outs) {
+    Plan P;
+    P.dtype = QED_FP64;
+    Builder B(P);
+    B.stage(2);
+    const Leg* legs = n.legs;
+    const BlockTable& tab = n.tab;
+    int f1 = which == 0 ? 1 : 0;
+    int f2 = which == 2 ? 1 : 2;
+    std::map<int64_t, int> bidx;
+    for (int b = 0; b < tab.nblk(); ++b) bidx[key3(tab.s[0][b], tab.s[1][b], tab.s[2][b])] = b;
+    // groups keyed by (output, input sector of the output operator)
+    std::map<std::pair<int, int>, std::vector<GProd>> groups;
+    for (const RTerm& t : terms) {
+        if (t.coef == 0.0) continue;
+        for (int b = 0; b < tab.nblk(); ++b) {
+            BV cur;
+            cur.p = gabs(n.ptr() + tab.off[b]);
+            for (int e = 0; e < 3; ++e) {
+                cur.s[e] = tab.s[e][b];
+                cur.n[e] = legs[e].n[cur.s[e]];
+            }
+            if (t.a) {
+                BV nx;
+                if (!B.mode(0, cur, f1, *t.a, legs[f1], nx)) continue;
+                cur = nx;
+            }
+            if (t.b) {
+                BV nx;
+                if (!B.mode(1, cur, f2, *t.b, legs[f2], nx)) continue;
+                cur = nx;
+            }
+            // partner block of the isometry: same sectors on f1, f2
+            int ps[3] = {cur.s[0], cur.s[1], cur.s[2]};
+            if (which == 2) ps[2] = legs[2].find(legs[0].q[ps[0]] + legs[1].q[ps[1]]);
+            else if (which == 0) ps[0] = legs[0].find(legs[2].q[ps[2]] - legs[1].q[ps[1]]);
+            else ps[1] = legs[1].find(legs[2].q[ps[2]] - legs[0].q[ps[0]]);
+            if (ps[which] < 0) continue;
+            auto it = bidx.find(key3(ps[0], ps[1], ps[2]));
+            if (it == bidx.end()) continue;
+            const int pb = it->second;
+            const OpP& out = outs[t.out];
+            const int sin = cur.s[which], sout = ps[which];
+            if (out->lay.out_of_in[sin] != sout)
+                fail(QED_ERR_BAD_STATE, "renormalised operator: charge shift mismatch");
+            GRef nb = gabs(n.ptr() + tab.off[pb]);
+            const int no = legs[which].n[sout], ni = cur.n[which];
+            GProd p{};
+            p.alpha = t.coef;
+            p.nred = 1;
+            if (which == 2) {
+                const int K = cur.n[0] * cur.n[1];
+                p.A = nb; p.tA = 1; p.lda = no;
+                p.B = cur.p; p.tB = 0; p.ldb = ni;
+                p.K = K;
+                P.flops += 2.0 * K * no * ni;
+            } else if (which == 0) {
+                const int K = cur.n[1] * cur.n[2];
+                p.A = nb; p.tA = 0; p.lda = K;
+                p.B = cur.p; p.tB = 1; p.ldb = K;
+                p.K = K;
+                P.flops += 2.0 * K * no * ni;
+            } else {
+                const int na = cur.n[0], nc = cur.n[2];
+                p.A = nb; p.tA = 0; p.lda = nc; p.rsA = (int64_t)no * nc;
+                p.B = cur.p; p.tB = 1; p.ldb = nc; p.rsB = (int64_t)ni * nc;
+                p.K = nc;
+                p.nred = na;
+                P.flops += 2.0 * na * nc * no * ni;
+            }
+            groups[{t.out, sin}].push_back(p);
+        }
+    }
+    for (int o = 0; o < (int)outs.size(); ++o) {
+        const OpP& out = outs[o];
+        for (int s = 0; s < out->leg.nsec(); ++s) {
+            const int so = out->lay.out_of_in[s];
+            if (so < 0) continue;
+            GJob j{};
+            j.C = gabs(out->d64->as<double>() + out->lay.off[s]);
+            j.M = out->leg.n[so];
+            j.N = out->leg.n[s];
+            j.ldc = j.N;
+            j.batch = 1;
+            j.p0 = (int)P.prods[2].size();
+            auto it = groups.find({o, s});
+            if (it != groups.end())
+                for (auto& p : it->second) P.prods[2].push_back(p);
+            j.p1 = (int)P.prods[2].size();
+            P.jobs[2].push_back(j);
+        }
+    }
+    return P;
+}
+
+Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out) {
+    Plan P;
+    P.dtype = QED_FP64;
+    Builder B(P);
+    B.stage(0);
+    for (int b = 0; b < in.tab.nblk(); ++b) {
+        BV cur;
+        cur.p = gabs(in.ptr() + in.tab.off[b]);
+        for (int k = 0; k < 3; ++k) {
+            cur.s[k] = in.tab.s[k][b];
+            cur.n[k] = in.legs[k].n[cur.s[k]];
+        }
+        const int so = op->lay.out_of_in[cur.s[e]];
+        if (so != cur.s[e]) fail(QED_ERR_BAD_STATE, "mode product expects a sector-preserving op");
+        GRef opblk = gabs(op->f64() + op->lay.off[cur.s[e]]);
+        int M, N, ldc, batch;
+        int64_t bsC;
+        GProd p = Builder::mode_prod(cur, e, opblk, cur.n[e], 1.0, M, N, ldc, batch, bsC);
+        B.job1(0, gabs(out + in.tab.off[b]), M, N, ldc, batch, bsC, p);
+        P.flops += 2.0 * cur.n[0] * cur.n[1] * cur.n[2] * cur.n[e];
+    }
+    return P;
+}
+
+// ---------------------------------------------------------------------
+// Lanczos (Methods, step (ii)), FP64 on the device
+// ---------------------------------------------------------------------
+void LanczosWS::ensure(Dev* dev, int mm, int64_t nn) {
+    if (V && m >= mm && n >= nn) return;
+    m = std::max(mm, m);
+    n = std::max(nn, n);
+    const int G = dot_grid(n);
+    V = std::make_shared<DBuf>(dev, (size_t)(m + 1) * n * sizeof(double));
+    w = std::make_shared<DBuf>(dev, n * sizeof(double));
+    alpha = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+    beta = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+    coef = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+    partial = std::make_shared<DBuf>(dev, (size_t)72 * G * sizeof(double));
+    sv = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+    work = std::make_shared<DBuf>(dev, 256 * sizeof(double));
+    st = std::make_shared<DBuf>(dev, sizeof(LState));
+    pv = std::make_shared<DBuf>(dev, 512 * sizeof(double));
+    pi = std::make_shared<DBuf>(dev, 512 * sizeof(int64_t));
+    scal = std::make_shared<DBuf>(dev, 8 * sizeof(double));
+}
+
+LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const double*, double*)>& apply,
+                      double* x, int64_t n, int m, int cycles, double tol) {
+    if (n <= 0) fail(QED_ERR_INVALID_ARG, "empty eigenproblem");
+    m = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(m, 64), n));
+    W.ensure(dev, m, n);
+    hipStream_t s = dev->stream;
+    double* V = W.V->as<double>();
+    double* w = W.w->as<double>();
+    double* al = W.alpha->as<double>();
+    double* be = W.beta->as<double>();
+    double* co = W.coef->as<double>();
+    double* part = W.partial->as<double>();
+    double* sc = W.scal->as<double>();
+    LState* st = W.st->as<LState>();
+    LanczosResult R;
+    const int64_t ld = n;
+    for (int cyc = 0; cyc < std::max(1, cycles); ++cyc) {
+        launch_dots(x, n, 1, x, n, part, sc + 0, 1, nullptr, 0, s);
+        launch_lz_start(V, x, sc + 0, n, st, m, s);
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + (int64_t)j * ld;
+            apply(vj, w);
+            ++R.matvecs;
+            launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
+            launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
+            for (int pass = 0; pass < 2; ++pass) {
+                launch_dots(V, ld, j + 1, w, n, part, co, 0, st, 1, s);
+                launch_lz_subtract(w, V, ld, j + 1, co, n, st, s);
+            }
+            launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
+            launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
+            launch_lz_next(V, ld, j, w, be, n, st, s);
+        }
+        launch_tridiag(al, be, W.sv->as<double>(), st, W.work->as<double>(), s);
+        launch_ritz(x, V, ld, W.sv->as<double>(), n, st, s);
+        launch_dots(x, n, 1, x, n, part, sc + 2, 1, nullptr, 0, s);
+        launch_normalise_sign(x, n, sc + 2, W.pv->as<double>(), W.pi->as<int64_t>(), sc + 3, s);
+        dev->check(hipGetLastError(), "lanczos launch");
+        LState hs;
+        dev->download(&hs, st, sizeof(LState));
+        R.theta = hs.theta;
+        R.resid = hs.resid;
+        R.cycles = cyc + 1;
+        if (!std::isfinite(hs.theta) || !std::isfinite(hs.norm) || hs.norm == 0.0)
+            fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value (zero or invalid start vector?)");
+        if (hs.resid <= tol * std::max(std::fabs(hs.theta), 1e-300)) break;
+    }
+    return R;
+}
+
+// ---------------------------------------------------------------------
+// node-level H_eff
+// ---------------------------------------------------------------------
+void Heff::matvec(const double* x, double* y) {
+    Dev* dev = &ctx->dev;
+    plan.prof = &ctx->prof;
+    ctx->mv_flops += plan.flops;
+    ctx->mv_count += 1;
+    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * (plan.dtype == QED_FP64 ? 8 : 4));
+    const int64_t n = tab.size();
+    if (plan.dtype == QED_FP64) {
+        plan.run(dev, w, (void*)x, (void*)y);
+    } else {
+        launch_f64_to_f32(x, xc->as<float>(), n, dev->stream);
+        plan.run(dev, w, xc->p, yc->p);
+        launch_f32_to_f64(yc->as<float>(), y, n, dev->stream);
+    }
+}
+
+}  // namespace qed

@@ -1,0 +1,265 @@
+// Device-side engine of the TTN node update: memory, block-sparse leg
+// operators, contraction plans, the Lanczos driver and the sweep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "model.h"
+#include "tree.h"
+
+namespace qed {
+
+// ---- kernel launchers (kernels.hip) ----------------------------------
+template <typename T>
+void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
+void launch_fill(double*, int64_t, double, hipStream_t);
+void launch_f64_to_f32(const double*, float*, int64_t, hipStream_t);
+void launch_f32_to_f64(const float*, double*, int64_t, hipStream_t);
+int dot_grid(int64_t n);
+void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64_t n,
+                 double* partial, double* out, int mode, const LState* st, int skip,
+                 hipStream_t stream);
+void launch_lz_three_term(double*, const double*, int64_t, int, const double*, const double*,
+                          int64_t, const LState*, hipStream_t);
+void launch_lz_subtract(double*, const double*, int64_t, int, const double*, int64_t,
+                        const LState*, hipStream_t);
+void launch_lz_beta(const double*, double*, double*, int, LState*, double, hipStream_t);
+void launch_lz_next(double*, int64_t, int, const double*, const double*, int64_t, const LState*,
+                    hipStream_t);
+void launch_lz_start(double*, const double*, const double*, int64_t, LState*, int, hipStream_t);
+void launch_tridiag(const double*, const double*, double*, LState*, double*, hipStream_t);
+void launch_ritz(double*, const double*, int64_t, const double*, int64_t, const LState*,
+                 hipStream_t);
+void launch_normalise_sign(double*, int64_t, const double*, double*, int64_t*, double*,
+                           hipStream_t);
+void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_t);
+void launch_qr(const QRMat*, int, int, double*, double*, double*, hipStream_t);
+void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
+                        hipStream_t);
+
+// ---- device memory ---------------------------------------------------
+struct Dev {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    void* (*ualloc)(uint64_t, void*, void*) = nullptr;
+    void (*ufree)(void*, void*, void*) = nullptr;
+    void* user = nullptr;
+    bool used = false;
+
+    void check(hipError_t e, const char* what);
+    void* alloc(size_t bytes);
+    void release(void* p);
+    void sync();
+    void upload(void* dst, const void* src, size_t bytes);
+    void download(void* dst, const void* src, size_t bytes);
+};
+
+struct DBuf {
+    Dev* dev = nullptr;
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf(Dev* d, size_t b) : dev(d), bytes(b) { p = b ? d->alloc(b) : nullptr; }
+    ~DBuf() {
+        if (p) dev->release(p);
+    }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    template <typename T> T* as() const { return (T*)p; }
+};
+using BufP = std::shared_ptr<DBuf>;
+
+// Grow-only scratch area.
+struct Arena {
+    BufP buf;
+    void* get(Dev* d, size_t bytes) {
+        if (!buf || buf->bytes < bytes) {
+            buf.reset();
+            buf = std::make_shared<DBuf>(d, bytes + bytes / 4 + 4096);
+        }
+        return buf->p;
+    }
+};
+
+// Block-sparse operator on one leg (FP64 master data, lazy FP32 copy).
+struct LegOpD {
+    Leg leg;
+    OpLayout lay;
+    BufP d64, d32;
+    Dev* dev = nullptr;
+    const double* f64() const { return d64 ? d64->as<double>() : nullptr; }
+    const void* data(int dtype);
+};
+using OpP = std::shared_ptr<LegOpD>;
+
+OpP make_op(Dev* dev, const Leg& leg, int delta, bool zero = true);
+
+// Node tensor (canonical block layout, FP64).
+struct TensorD {
+    Leg legs[3];
+    BlockTable tab;
+    BufP d;
+    double* ptr() const { return d ? d->as<double>() : nullptr; }
+};
+
+// ---- profiling of the H_eff GEMM launches ------------------------------
+struct Prof {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> ev_flops;
+    long long launches = 0;
+    double ms = 0.0, flops = 0.0;
+    void record_begin(hipStream_t s, hipEvent_t& a);
+    void harvest();     // fold finished event pairs into ms (stream synced)
+    void reset();
+    ~Prof();
+};
+
+// ---- contraction plans -----------------------------------------------
+struct Plan {
+    int dtype = QED_FP64;   // QED_FP64 or QED_FP32 (GEMM arithmetic)
+    std::vector<double> stage_flops;
+    Prof* prof = nullptr;   // set for H_eff applications when profiling
+    std::vector<std::vector<GJob>> jobs;
+    std::vector<std::vector<GProd>> prods;
+    int64_t ws_elems = 0;
+    double flops = 0.0;
+    double bytes = 0.0;
+    // device copies
+    std::vector<BufP> dj, dp, dt;
+    std::vector<int> ntiles;
+    void upload(Dev* dev);
+    void run(Dev* dev, void* ws, void* x, void* y);
+};
+
+struct HTerm {
+    double coef;
+    OpP op[3];   // null = identity
+};
+
+// y = sum_k coef_k A_k (x) B_k (x) C_k  x on the canonical layout.
+Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
+                 int dtype);
+
+// Renormalised operators n^T (A (x) B) n on leg `which` of node tensor n.
+struct RTerm {
+    double coef;
+    OpP a, b;    // on the two other legs in (l, r, p) order; null = identity
+    int out;     // index into outs
+};
+Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
+                 const std::vector<OpP>& outs);
+
+// out_tensor = op applied on leg e of in_tensor (sector preserving op)
+Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out);
+
+// ---- Lanczos -----------------------------------------------------------
+struct LanczosWS {
+    int m = 0;
+    int64_t n = 0;
+    BufP V, w, alpha, beta, coef, partial, sv, work, st, pv, pi, scal;
+    void ensure(Dev* dev, int m, int64_t n);
+};
+
+struct LanczosResult {
+    double theta = 0.0, resid = 0.0;
+    int cycles = 0;
+    long long matvecs = 0;
+};
+
+// Lowest eigenpair; x (device FP64, length n) is the start vector and
+// receives the normalised Ritz vector.
+LanczosResult lanczos(Dev* dev, LanczosWS& ws, const std::function<void(const double*, double*)>& apply,
+                      double* x, int64_t n, int m, int cycles, double tol);
+
+// ---- node-level effective Hamiltonian (C ABI object) ------------------
+struct Ctx;
+
+struct Heff {
+    Ctx* ctx = nullptr;
+    Leg legs[3];
+    BlockTable tab;
+    std::vector<HTerm> terms;
+    Plan plan;
+    Arena ws;
+    BufP xc, yc;   // compute-type staging for reduced precision
+    LanczosWS lws;
+    void matvec(const double* x, double* y);
+};
+
+// ---- the TTN sweep engine ---------------------------------------------
+struct EnvD {
+    OpP H[2];
+    std::map<int, OpP> open;
+    bool valid = false;
+};
+
+struct Params {
+    int Lx = 0, Ly = 0, Lz = 0, bc = QED_BC_OPEN_ZERO_FLUX;
+    double t = 1, m = 1, g2e = 1, g2m = 1;
+    double nu_max = 10.0;
+    int n_lin = 0, n_quad = 0;
+    int Q = 0, chi = 16;
+    int lz_steps = 30, lz_cycles = 1;
+    double lz_tol = 0.0;
+    int dtype = QED_FP64, refine = 1;
+    bool have_lattice = false, have_couplings = false;
+};
+
+struct Engine {
+    Ctx* ctx = nullptr;
+    Model model;
+    Tree tree;
+    std::vector<Leg> legs;
+    std::vector<TensorD> nodes;
+    std::vector<EnvD> up, dn;
+    std::vector<std::vector<OpP>> siteops;   // per site, per op id
+    std::vector<std::vector<char>> inside;   // per link: site membership
+    std::vector<std::vector<int>> tsites;    // per term: its sites
+    int centre = -1;
+    int sweeps_done = 0;
+    double energy = 0.0;
+    bool have_energy = false;
+    Arena ws;
+    LanczosWS lws;
+    long long matvecs = 0;
+    double flops = 0.0;
+
+    void build(Ctx* c);
+    void init_nodes(uint64_t seed);
+    bool ready() const { return !nodes.empty(); }
+    void invalidate() { centre = -1; }
+    void prepare();
+    void sweep(int s, qed_sweep_report* rep);
+    void observables(std::vector<double>& site7);
+
+    double nu_for(int s) const;
+    OpP qr_toward(int n, int which);
+    void absorb(int n, int e, const OpP& R);
+    void move(int a, int b);
+    void move_to(int target);
+    void build_env(int n, int which, EnvD& out);
+    EnvD& env_for(int n, int which);
+    double update(int n, double nu);
+};
+
+struct Ctx {
+    Dev dev;
+    Prof prof;
+    double mv_flops = 0.0;
+    long long mv_count = 0;
+    bool host_only = true;
+    std::string err;
+    Params prm;
+    std::unique_ptr<Engine> eng;
+    bool built = false;
+};
+
+}  // namespace qed

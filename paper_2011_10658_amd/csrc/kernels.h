@@ -1,0 +1,78 @@
+// Device data structures shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qed {
+
+// Pointer into one of the buffers bound at launch time: tag 0 = absolute
+// address `abs`; tag t > 0 = bases[t] + off elements of the compute type.
+enum { TAG_ABS = 0, TAG_WS = 1, TAG_X = 2, TAG_Y = 3, NTAGS = 4 };
+
+struct GRef {
+    const void* abs;
+    int64_t off;
+    int tag;
+    int pad;
+};
+
+struct Bases {
+    void* b[NTAGS];
+};
+
+// One (batch-reduce) product alpha * sum_{r < nred} op(A_r) op(B_r),
+// op(A) M x K, op(B) K x N.  tA = 1: op(A)[m][k] = A[k * lda + m];
+// tB = 1: op(B)[k][n] = B[n * ldb + k].  ident = 1: A is the identity and
+// op(B) (M x N, tB = 0) is added.  bsA/bsB: strides between batch items.
+struct GProd {
+    GRef A, B;
+    int64_t rsA, rsB, bsA, bsB;
+    double alpha;
+    int K, lda, ldb, tA, tB, nred, ident, pad;
+};
+
+// Output C (M x N, row-major, ldc) of `batch` items (stride bsC), the sum
+// of products [p0, p1); acc = 1 adds into C, 0 overwrites.
+struct GJob {
+    GRef C;
+    int64_t bsC;
+    int M, N, ldc, batch, p0, p1, acc, pad;
+};
+
+// Work item of one workgroup: tile (tm, tn) of batch item b of job j.
+struct GTile {
+    int job, b, tm, tn;
+};
+
+constexpr int GEMM_TM = 32;
+constexpr int GEMM_TN = 32;
+constexpr int GEMM_KC = 16;
+constexpr int GEMM_THREADS = 256;
+
+// Per-block description for packing a node tensor into the column-major
+// matrices of its sectors along one leg (QR), and back.
+struct PackBlk {
+    int64_t off;       // block offset in the tensor
+    int64_t mat;       // offset of the sector matrix in the packed buffer
+    int n[3];          // block extents (l, r, p)
+    int leg;           // leg whose index becomes the column
+    int rows;          // rows of the sector matrix (its leading dimension)
+    int row0;          // first row of this block inside the sector matrix
+};
+
+// One sector matrix for the QR kernel.
+struct QRMat {
+    int64_t mat;       // offset in the packed buffer (column-major)
+    int64_t rout;      // offset of the R block (row-major cols x cols)
+    int rows, cols;
+};
+
+// Lanczos state living on the device.
+struct LState {
+    int k;             // number of valid steps (== m unless broken down)
+    int broken;
+    double theta, resid, norm;
+};
+
+}  // namespace qed

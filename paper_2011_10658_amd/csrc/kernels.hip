@@ -1,0 +1,691 @@
+// HIP kernels of the TTN node update for gfx950 (CDNA4, wave64).
+//
+//  * k_brgemm: grouped batch-reduce GEMM.  Every contraction of the hot
+//    path (H_eff mode products, the term-summed output accumulation, the
+//    environment renormalisation) is a list of jobs, each a sum of
+//    products of dense symmetry blocks; one workgroup owns one 32 x 32
+//    output tile, stages A/B through LDS and runs 16x16x4 MFMA on four
+//    waves.  FP64 and FP32 instances; FP32 accumulates in FP32.
+//  * FP64 Lanczos vector kernels: multi-row dot products with wave64
+//    shuffle reductions in a fixed order (deterministic), fused updates.
+//  * k_tridiag_lowest: lowest eigenpair of the Lanczos tridiagonal
+//    (Sturm bisection + inverse iteration with partial pivoting).
+//  * k_householder_qr: per-sector Householder QR, one workgroup per
+//    sector matrix, wave-parallel over columns, diag(R) >= 0.
+#include "kernels.h"
+
+namespace qed {
+
+template <typename T> struct Mfma;
+
+// Operand layout of both 16x16x4 instructions: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  The accumulator layout differs:
+// FP32 keeps rows 4 (l / 16) + i in item i, FP64 keeps rows 4 i + l / 16.
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 step(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 step(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+template <typename T>
+__device__ __forceinline__ T* resolve(const GRef& r, const Bases& bs) {
+    if (r.tag == TAG_ABS) return (T*)r.abs;
+    return (T*)bs.b[r.tag] + r.off;
+}
+
+// ---------------------------------------------------------------------
+// grouped batch-reduce GEMM
+// ---------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(GEMM_THREADS) void k_brgemm(const GJob* __restrict__ jobs,
+                                                         const GProd* __restrict__ prods,
+                                                         const GTile* __restrict__ tiles,
+                                                         Bases bases) {
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ T As[GEMM_TM][GEMM_KC + 1];
+    __shared__ T Bs[GEMM_KC][GEMM_TN + 1];
+    const GTile tl = tiles[blockIdx.x];
+    const GJob J = jobs[tl.job];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = (wave >> 1) * 16;
+    const int wn = (wave & 1) * 16;
+    const int m0 = tl.tm * GEMM_TM;
+    const int n0 = tl.tn * GEMM_TN;
+    v4 acc = {0, 0, 0, 0};
+    for (int p = J.p0; p < J.p1; ++p) {
+        const GProd P = prods[p];
+        const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+        const T alpha = (T)P.alpha;
+        if (P.ident) {
+            const int col = n0 + wn + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + wm + Mfma<T>::row(lane, i);
+                if (row < J.M && col < J.N) acc[i] += alpha * Bb[(int64_t)row * P.ldb + col];
+            }
+            continue;
+        }
+        const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        for (int r = 0; r < P.nred; ++r) {
+            const T* A = Ab + (int64_t)r * P.rsA;
+            const T* B = Bb + (int64_t)r * P.rsB;
+            for (int k0 = 0; k0 < P.K; k0 += GEMM_KC) {
+                __syncthreads();
+                for (int e = tid; e < GEMM_TM * GEMM_KC; e += GEMM_THREADS) {
+                    int m, k;
+                    if (P.tA) { m = e % GEMM_TM; k = e / GEMM_TM; }
+                    else { k = e % GEMM_KC; m = e / GEMM_KC; }
+                    const int gm = m0 + m, gk = k0 + k;
+                    T v = (T)0;
+                    if (gm < J.M && gk < P.K)
+                        v = P.tA ? A[(int64_t)gk * P.lda + gm] : A[(int64_t)gm * P.lda + gk];
+                    As[m][k] = v * alpha;
+                }
+                for (int e = tid; e < GEMM_KC * GEMM_TN; e += GEMM_THREADS) {
+                    int k, n;
+                    if (P.tB) { k = e % GEMM_KC; n = e / GEMM_KC; }
+                    else { n = e % GEMM_TN; k = e / GEMM_TN; }
+                    const int gn = n0 + n, gk = k0 + k;
+                    T v = (T)0;
+                    if (gn < J.N && gk < P.K)
+                        v = P.tB ? B[(int64_t)gn * P.ldb + gk] : B[(int64_t)gk * P.ldb + gn];
+                    Bs[k][n] = v;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < GEMM_KC; kk += 4) {
+                    const T a = As[wm + (lane & 15)][kk + (lane >> 4)];
+                    const T b = Bs[kk + (lane >> 4)][wn + (lane & 15)];
+                    acc = Mfma<T>::step(a, b, acc);
+                }
+            }
+        }
+    }
+    T* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    const int col = n0 + wn + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = m0 + wm + Mfma<T>::row(lane, i);
+        if (row < J.M && col < J.N) {
+            T* c = C + (int64_t)row * J.ldc + col;
+            *c = J.acc ? *c + acc[i] : acc[i];
+        }
+    }
+}
+
+template <typename T>
+void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
+                   const Bases& bases, hipStream_t st) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_brgemm<T>, dim3(ntiles), dim3(GEMM_THREADS), 0, st, jobs, prods, tiles,
+                       bases);
+}
+
+template void launch_brgemm<double>(const GJob*, const GProd*, const GTile*, int, const Bases&,
+                                    hipStream_t);
+template void launch_brgemm<float>(const GJob*, const GProd*, const GTile*, int, const Bases&,
+                                   hipStream_t);
+
+// ---------------------------------------------------------------------
+// element-wise helpers
+// ---------------------------------------------------------------------
+__global__ void k_fill(double* x, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (double)a[i];
+}
+
+static int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+void launch_fill(double* x, int64_t n, double v, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, x, n, v);
+}
+void launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, st, a, b, n);
+}
+void launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, st, a, b, n);
+}
+
+// ---------------------------------------------------------------------
+// FP64 reductions (fixed partition and order: bitwise reproducible)
+// ---------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+constexpr int DOT_ROWS = 8;
+
+int dot_grid(int64_t n) {
+    int64_t g = (n + 1023) / 1024;
+    if (g > 512) g = 512;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// partial[r * G + block] = sum over the block's slice of V[r] . w, r < nrows
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ V, int64_t ldv,
+                                                     int nrows, const double* __restrict__ w,
+                                                     int64_t n, double* __restrict__ partial,
+                                                     const LState* st, int skip_if_broken) {
+    if (skip_if_broken && st && st->broken) return;
+    __shared__ double sh[DOT_ROWS][4];
+    const int G = gridDim.x;
+    const int64_t chunk = (n + G - 1) / G;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int r0 = 0; r0 < nrows; r0 += DOT_ROWS) {
+        double s[DOT_ROWS];
+#pragma unroll
+        for (int q = 0; q < DOT_ROWS; ++q) s[q] = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+            const double wi = w[i];
+#pragma unroll
+            for (int q = 0; q < DOT_ROWS; ++q)
+                if (r0 + q < nrows) s[q] += V[(int64_t)(r0 + q) * ldv + i] * wi;
+        }
+#pragma unroll
+        for (int q = 0; q < DOT_ROWS; ++q) {
+            double v = wave_sum(s[q]);
+            if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < DOT_ROWS && r0 + (int)threadIdx.x < nrows) {
+            const int q = threadIdx.x;
+            partial[(int64_t)(r0 + q) * G + blockIdx.x] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
+        }
+        __syncthreads();
+    }
+}
+
+// out[r] = sum_b partial[r * G + b] (sequential in b); mode 1: sqrt
+__global__ void k_dot_final(const double* __restrict__ partial, int G, int nrows,
+                            double* __restrict__ out, int mode, const LState* st,
+                            int skip_if_broken) {
+    if (skip_if_broken && st && st->broken) return;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) s += partial[(int64_t)r * G + b];
+    out[r] = mode == 1 ? sqrt(s) : s;
+}
+
+void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64_t n,
+                 double* partial, double* out, int mode, const LState* st, int skip,
+                 hipStream_t stream) {
+    const int G = dot_grid(n);
+    hipLaunchKernelGGL(k_dot_partial, dim3(G), dim3(256), 0, stream, V, ldv, nrows, w, n, partial,
+                       st, skip);
+    hipLaunchKernelGGL(k_dot_final, dim3((nrows + 63) / 64), dim3(64), 0, stream, partial, G, nrows,
+                       out, mode, st, skip);
+}
+
+// ---------------------------------------------------------------------
+// Lanczos step kernels (all no-ops once the state has broken down)
+// ---------------------------------------------------------------------
+// w -= alpha[j] v_j + beta[j-1] v_{j-1}
+__global__ void k_lz_three_term(double* __restrict__ w, const double* __restrict__ V, int64_t ldv,
+                                int j, const double* __restrict__ alpha,
+                                const double* __restrict__ beta, int64_t n, const LState* st) {
+    if (st->broken) return;
+    const double a = alpha[j];
+    const double b = j > 0 ? beta[j - 1] : 0.0;
+    const double* vj = V + (int64_t)j * ldv;
+    const double* vm = j > 0 ? V + (int64_t)(j - 1) * ldv : nullptr;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double t = a * vj[i];
+        if (vm) t += b * vm[i];
+        w[i] -= t;
+    }
+}
+
+// w -= sum_{r < nrows} c[r] V[r]
+__global__ void k_lz_subtract(double* __restrict__ w, const double* __restrict__ V, int64_t ldv,
+                              int nrows, const double* __restrict__ c, int64_t n,
+                              const LState* st) {
+    if (st->broken) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int r = 0; r < nrows; ++r) t += c[r] * V[(int64_t)r * ldv + i];
+        w[i] -= t;
+    }
+}
+
+// beta[j] = sqrt(ww); breakdown test against the scale of T
+__global__ void k_lz_beta(const double* ww, double* alpha, double* beta, int j, LState* st,
+                          double tol) {
+    if (st->broken) return;
+    double b = sqrt(*ww);
+    double scale = 1.0;
+    for (int i = 0; i <= j; ++i) scale = fmax(scale, fabs(alpha[i]));
+    for (int i = 0; i < j; ++i) scale = fmax(scale, beta[i]);
+    if (b <= tol * scale) {
+        beta[j] = 0.0;
+        st->broken = 1;
+        st->k = j + 1;
+    } else {
+        beta[j] = b;
+    }
+}
+
+// V[j+1] = w / beta[j]
+__global__ void k_lz_next(double* __restrict__ V, int64_t ldv, int j,
+                          const double* __restrict__ w, const double* __restrict__ beta,
+                          int64_t n, const LState* st) {
+    if (st->broken) return;
+    const double inv = 1.0 / beta[j];
+    double* v = V + (int64_t)(j + 1) * ldv;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = w[i] * inv;
+}
+
+// dst = src / *nrm  (start vector); records the norm
+__global__ void k_lz_start(double* __restrict__ dst, const double* __restrict__ src,
+                           const double* nrm, int64_t n, LState* st, int m) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->broken = 0;
+        st->k = m;
+        st->norm = *nrm;
+    }
+    const double inv = 1.0 / *nrm;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] * inv;
+}
+
+// lowest eigenpair of the k x k tridiagonal (alpha, beta): Sturm-count
+// bisection to full precision, then inverse iteration with a pivoted
+// tridiagonal LU.  Writes s[0..k), st->theta and st->resid.
+__global__ void k_tridiag_lowest(const double* alpha, const double* beta, double* s, LState* st,
+                                 double* work) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int k = st->k;
+    double lo = 0.0, hi = 0.0, tnorm = 0.0;
+    for (int i = 0; i < k; ++i) {
+        double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < k - 1 ? fabs(beta[i]) : 0.0);
+        double a = alpha[i] - r, b = alpha[i] + r;
+        if (i == 0 || a < lo) lo = a;
+        if (i == 0 || b > hi) hi = b;
+        tnorm = fmax(tnorm, fabs(alpha[i]) + r);
+    }
+    const double tiny = 1e-300;
+    for (int it = 0; it < 2000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        // number of eigenvalues < mid
+        int cnt = 0;
+        double d = alpha[0] - mid;
+        if (d == 0.0) d = -tiny;
+        if (d < 0) ++cnt;
+        for (int i = 1; i < k; ++i) {
+            d = alpha[i] - mid - beta[i - 1] * beta[i - 1] / d;
+            if (d == 0.0) d = -tiny;
+            if (d < 0) ++cnt;
+        }
+        if (cnt >= 1) hi = mid; else lo = mid;
+    }
+    const double theta = 0.5 * (lo + hi);
+    // inverse iteration on (T - theta I)
+    double* dl = work;
+    double* dd = work + 64;
+    double* du = work + 128;
+    double* du2 = work + 192;
+    int piv[64];
+    for (int i = 0; i < k; ++i) s[i] = 1.0;
+    const double eps = 2.3e-16 * (tnorm > 0 ? tnorm : 1.0);
+    for (int iter = 0; iter < 3; ++iter) {
+        for (int i = 0; i < k; ++i) {
+            dd[i] = alpha[i] - theta;
+            if (i < k - 1) { dl[i] = beta[i]; du[i] = beta[i]; }
+            du2[i] = 0.0;
+            piv[i] = i;
+        }
+        for (int i = 0; i < k - 1; ++i) {
+            if (fabs(dd[i]) >= fabs(dl[i])) {
+                if (dd[i] == 0.0) dd[i] = eps;
+                double f = dl[i] / dd[i];
+                dl[i] = f;
+                dd[i + 1] -= f * du[i];
+            } else {
+                double f = dd[i] / dl[i];
+                dd[i] = dl[i];
+                dl[i] = f;
+                double tmp = du[i];
+                du[i] = dd[i + 1];
+                dd[i + 1] = tmp - f * dd[i + 1];
+                if (i < k - 2) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+                piv[i] = i + 1;
+            }
+        }
+        if (dd[k - 1] == 0.0) dd[k - 1] = eps;
+        for (int i = 0; i < k - 1; ++i) {
+            if (piv[i] == i) {
+                s[i + 1] -= dl[i] * s[i];
+            } else {
+                double tmp = s[i];
+                s[i] = s[i + 1];
+                s[i + 1] = tmp - dl[i] * s[i];
+            }
+        }
+        s[k - 1] /= dd[k - 1];
+        if (k > 1) s[k - 2] = (s[k - 2] - du[k - 2] * s[k - 1]) / dd[k - 2];
+        for (int i = k - 3; i >= 0; --i) s[i] = (s[i] - du[i] * s[i + 1] - du2[i] * s[i + 2]) / dd[i];
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += s[i] * s[i];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < k; ++i) s[i] /= nrm;
+    }
+    st->theta = theta;
+    st->resid = fabs(beta[k - 1] * s[k - 1]);
+}
+
+// u = sum_{r < k} s[r] V[r]
+__global__ void k_ritz(double* __restrict__ u, const double* __restrict__ V, int64_t ldv,
+                       const double* __restrict__ s, int64_t n, const LState* st) {
+    const int k = st->k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int r = 0; r < k; ++r) t += s[r] * V[(int64_t)r * ldv + i];
+        u[i] = t;
+    }
+}
+
+// per block: largest |u| and its first index
+__global__ __launch_bounds__(256) void k_argmax_partial(const double* __restrict__ u, int64_t n,
+                                                        double* pv, int64_t* pi) {
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    const int G = gridDim.x;
+    const int64_t chunk = (n + G - 1) / G;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double bv = -1.0;
+    int64_t bi = -1;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        double a = fabs(u[i]);
+        if (a > bv) { bv = a; bi = i; }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            double v2 = sv[threadIdx.x + o];
+            int64_t i2 = si[threadIdx.x + o];
+            double v1 = sv[threadIdx.x];
+            int64_t i1 = si[threadIdx.x];
+            if (v2 > v1 || (v2 == v1 && i2 >= 0 && (i1 < 0 || i2 < i1))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pv[blockIdx.x] = sv[0];
+        pi[blockIdx.x] = si[0];
+    }
+}
+
+// fac = sign(u[argmax |u|]) / nrm, decided once by a single thread before
+// any element is rescaled
+__global__ void k_sign_factor(const double* __restrict__ u, const double* nrm,
+                              const double* pv, const int64_t* pi, int G, double* fac) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double bv = -1.0;
+    int64_t bi = -1;
+    for (int b = 0; b < G; ++b)
+        if (pv[b] > bv || (pv[b] == bv && pi[b] >= 0 && (bi < 0 || pi[b] < bi))) {
+            bv = pv[b];
+            bi = pi[b];
+        }
+    const double sg = (bi >= 0 && u[bi] < 0) ? -1.0 : 1.0;
+    *fac = sg / *nrm;
+}
+
+__global__ void k_scale_by(double* __restrict__ u, int64_t n, const double* fac) {
+    const double f = *fac;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        u[i] *= f;
+}
+
+void launch_lz_three_term(double* w, const double* V, int64_t ldv, int j, const double* alpha,
+                          const double* beta, int64_t n, const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_three_term, dim3(grid_for(n)), dim3(256), 0, s, w, V, ldv, j, alpha,
+                       beta, n, st);
+}
+void launch_lz_subtract(double* w, const double* V, int64_t ldv, int nrows, const double* c,
+                        int64_t n, const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_subtract, dim3(grid_for(n)), dim3(256), 0, s, w, V, ldv, nrows, c, n,
+                       st);
+}
+void launch_lz_beta(const double* ww, double* alpha, double* beta, int j, LState* st, double tol,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, s, ww, alpha, beta, j, st, tol);
+}
+void launch_lz_next(double* V, int64_t ldv, int j, const double* w, const double* beta, int64_t n,
+                    const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_next, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, j, w, beta, n, st);
+}
+void launch_lz_start(double* dst, const double* src, const double* nrm, int64_t n, LState* st,
+                     int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_lz_start, dim3(grid_for(n)), dim3(256), 0, s, dst, src, nrm, n, st, m);
+}
+void launch_tridiag(const double* alpha, const double* beta, double* sv, LState* st, double* work,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_tridiag_lowest, dim3(1), dim3(64), 0, s, alpha, beta, sv, st, work);
+}
+void launch_ritz(double* u, const double* V, int64_t ldv, const double* sv, int64_t n,
+                 const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_ritz, dim3(grid_for(n)), dim3(256), 0, s, u, V, ldv, sv, n, st);
+}
+void launch_normalise_sign(double* u, int64_t n, const double* nrm, double* pv, int64_t* pi,
+                           double* fac, hipStream_t s) {
+    const int G = dot_grid(n);
+    hipLaunchKernelGGL(k_argmax_partial, dim3(G), dim3(256), 0, s, u, n, pv, pi);
+    hipLaunchKernelGGL(k_sign_factor, dim3(1), dim3(1), 0, s, u, nrm, pv, pi, G, fac);
+    hipLaunchKernelGGL(k_scale_by, dim3(grid_for(n)), dim3(256), 0, s, u, n, fac);
+}
+
+// ---------------------------------------------------------------------
+// QR of the sector matrices of a node matricised along one leg
+// ---------------------------------------------------------------------
+// pack (dir = 0): tensor -> column-major sector matrices; unpack (dir = 1)
+__global__ void k_pack(const PackBlk* __restrict__ blks, double* __restrict__ tensor,
+                       double* __restrict__ packed, int dir) {
+    const PackBlk B = blks[blockIdx.x];
+    const int64_t size = (int64_t)B.n[0] * B.n[1] * B.n[2];
+    for (int64_t e = blockIdx.y * (int64_t)blockDim.x + threadIdx.x; e < size;
+         e += (int64_t)gridDim.y * blockDim.x) {
+        const int ip = (int)(e % B.n[2]);
+        const int64_t t = e / B.n[2];
+        const int ir = (int)(t % B.n[1]);
+        const int il = (int)(t / B.n[1]);
+        int row, col;
+        if (B.leg == 2) { col = ip; row = il * B.n[1] + ir; }
+        else if (B.leg == 0) { col = il; row = ir * B.n[2] + ip; }
+        else { col = ir; row = il * B.n[2] + ip; }
+        const int64_t pidx = B.mat + (int64_t)col * B.rows + B.row0 + row;
+        if (dir == 0) packed[pidx] = tensor[B.off + e];
+        else tensor[B.off + e] = packed[pidx];
+    }
+}
+
+void launch_pack(const PackBlk* blks, int nblk, int64_t maxsize, double* tensor, double* packed,
+                 int dir, hipStream_t s) {
+    if (nblk <= 0) return;
+    int64_t gy = (maxsize + 255) / 256;
+    if (gy > 256) gy = 256;
+    if (gy < 1) gy = 1;
+    hipLaunchKernelGGL(k_pack, dim3(nblk, (int)gy), dim3(256), 0, s, blks, tensor, packed, dir);
+}
+
+// Householder QR of one column-major rows x cols matrix per workgroup
+// (rows >= cols).  On exit the packed matrix holds the explicit Q with
+// orthonormal columns and R (row-major cols x cols) is written at
+// rbuf + rout; signs are fixed so that diag(R) >= 0.  `qbuf` is a
+// scratch matrix of the same shape as the input.
+__global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict__ mats,
+                                                        double* __restrict__ packed,
+                                                        double* __restrict__ qbuf,
+                                                        double* __restrict__ rbuf) {
+    extern __shared__ double lds[];
+    const QRMat Mt = mats[blockIdx.x];
+    const int m = Mt.rows, n = Mt.cols;
+    double* A = packed + Mt.mat;
+    double* Qm = qbuf + Mt.mat;
+    double* R = rbuf + Mt.rout;
+    double* tau = lds;          // n
+    double* diag = lds + n;     // n  (R_jj)
+    double* red = lds + 2 * n;  // 4
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = 0; j < n; ++j) {
+        // norm of A[j:, j]
+        double s = 0.0;
+        for (int i = j + tid; i < m; i += 256) s += A[(int64_t)j * m + i] * A[(int64_t)j * m + i];
+        s = wave_sum(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        if (tid == 0) {
+            const double norm2 = ((red[0] + red[1]) + red[2]) + red[3];
+            const double x0 = A[(int64_t)j * m + j];
+            const double nrm = sqrt(norm2);
+            if (nrm == 0.0) {
+                tau[j] = 0.0;
+                diag[j] = 0.0;
+            } else {
+                const double al = x0 >= 0.0 ? -nrm : nrm;
+                const double v0 = x0 - al;
+                const double vtv = v0 * v0 + (norm2 - x0 * x0);
+                tau[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+                diag[j] = al;
+                A[(int64_t)j * m + j] = v0;
+            }
+        }
+        __syncthreads();
+        const double tj = tau[j];
+        if (tj != 0.0) {
+            // trailing columns: each wave owns columns j+1+wave, +4, ...
+            for (int k = j + 1 + wave; k < n; k += 4) {
+                double d = 0.0;
+                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * m + i] * A[(int64_t)k * m + i];
+                d = wave_sum(d);
+                d = __shfl(d, 0, 64);
+                const double f = tj * d;
+                for (int i = j + lane; i < m; i += 64) A[(int64_t)k * m + i] -= f * A[(int64_t)j * m + i];
+            }
+        }
+        __syncthreads();
+    }
+    // R (before the sign fix): strict upper part from A, diagonal from diag
+    for (int e = tid; e < n * n; e += 256) {
+        const int r = e / n, c = e % n;
+        R[e] = c > r ? A[(int64_t)c * m + r] : (c == r ? diag[r] : 0.0);
+    }
+    // explicit Q = H_0 ... H_{n-1} [I; 0]
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
+        const int c = (int)(e / m), r = (int)(e % m);
+        Qm[e] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj != 0.0) {
+            for (int k = j + wave; k < n; k += 4) {
+                double d = 0.0;
+                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * m + i] * Qm[(int64_t)k * m + i];
+                d = wave_sum(d);
+                d = __shfl(d, 0, 64);
+                const double f = tj * d;
+                for (int i = j + lane; i < m; i += 64) Qm[(int64_t)k * m + i] -= f * A[(int64_t)j * m + i];
+            }
+        }
+        __syncthreads();
+    }
+    // sign fix diag(R) >= 0, copy Q back over the packed matrix
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
+        const int c = (int)(e / m);
+        A[e] = diag[c] < 0.0 ? -Qm[e] : Qm[e];
+    }
+    for (int e = tid; e < n * n; e += 256) {
+        const int r = e / n;
+        if (diag[r] < 0.0) R[e] = -R[e];
+    }
+}
+
+void launch_qr(const QRMat* mats, int nmats, int maxcols, double* packed, double* qbuf,
+               double* rbuf, hipStream_t s) {
+    if (nmats <= 0) return;
+    size_t lds = (size_t)(2 * maxcols + 4) * sizeof(double);
+    hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), lds, s, mats, packed, qbuf, rbuf);
+}
+
+// ---------------------------------------------------------------------
+// local expectation values: out[c] = sum_i rho_ii rows[i][c], c < 7
+// ---------------------------------------------------------------------
+__global__ void k_site_expect(const double* __restrict__ rho, const int64_t* __restrict__ diag_pos,
+                              const signed char* __restrict__ rows, int d, double* __restrict__ out) {
+    __shared__ double acc[7][64];
+    const int t = threadIdx.x;
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = t; i < d; i += 64) {
+        const double w = rho[diag_pos[i]];
+        for (int c = 0; c < 7; ++c) s[c] += w * rows[i * 7 + c];
+    }
+    for (int c = 0; c < 7; ++c) acc[c][t] = s[c];
+    __syncthreads();
+    if (t < 7) {
+        double v = 0.0;
+        for (int i = 0; i < 64; ++i) v += acc[t][i];
+        out[t] = v;
+    }
+}
+
+void launch_site_expect(const double* rho, const int64_t* diag_pos, const signed char* rows, int d,
+                        double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_site_expect, dim3(1), dim3(64), 0, s, rho, diag_pos, rows, d, out);
+}
+
+}  // namespace qed
