@@ -275,6 +275,7 @@ def test_lanczos_large_vector_deterministic(ctx):
     253,604 entries): two runs are bitwise identical and match the oracle
     (the Ritz sign is decided once, before any element is rescaled)."""
     ctx.set_precision(lib.FP64)
+    ctx.set_lanczos(6, 1, 0.0)
     leg = synth.C4_LEG
     legs = (leg, leg, leg)
     terms = [(c, (a, b, cc), (0, 0, 0)) for c, a, b, cc in synth.single_node_terms(4, 3, leg)]
