@@ -455,6 +455,7 @@ Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
             P.jobs[2].push_back(j);
         }
     }
+    split_long_reductions(P, 2);
     return P;
 }
 
@@ -480,6 +481,179 @@ Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out) {
         P.flops += 2.0 * cur.n[0] * cur.n[1] * cur.n[2] * cur.n[e];
     }
     return P;
+}
+
+namespace {
+
+GRef gshift(GRef r, int64_t elems, int esize) {
+    if (r.tag == TAG_ABS) r.abs = (const char*)r.abs + elems * esize;
+    else r.off += elems;
+    return r;
+}
+
+}  // namespace
+
+void split_long_reductions(Plan& P, int s) {
+    const int64_t KCHUNK = 1024;
+    const int MIN_TILES = 32;
+    const int esize = P.dtype == QED_FP64 ? 8 : 4;
+    if ((int)P.jobs.size() <= s) return;
+    while ((int)P.jobs.size() <= s + 1) {
+        P.jobs.emplace_back();
+        P.prods.emplace_back();
+        P.stage_flops.push_back(0.0);
+    }
+    std::vector<GJob> old = P.jobs[s];
+    std::vector<GProd> oldp = P.prods[s];
+    P.jobs[s].clear();
+    P.prods[s].clear();
+    for (const GJob& J : old) {
+        const int64_t tiles = (int64_t)((J.M + GEMM_TM - 1) / GEMM_TM) * ((J.N + GEMM_TN - 1) / GEMM_TN) * J.batch;
+        int64_t W = 0;
+        for (int p = J.p0; p < J.p1; ++p)
+            if (!oldp[p].ident) W += (int64_t)oldp[p].K * oldp[p].nred;
+        if (J.batch != 1 || tiles >= MIN_TILES || W <= 2 * KCHUNK) {
+            GJob j = J;
+            j.p0 = (int)P.prods[s].size();
+            for (int p = J.p0; p < J.p1; ++p) P.prods[s].push_back(oldp[p]);
+            j.p1 = (int)P.prods[s].size();
+            P.jobs[s].push_back(j);
+            continue;
+        }
+        std::vector<std::vector<GProd>> chunks(1);
+        std::vector<GProd> direct;
+        int64_t cur = 0;
+        auto push = [&](const GProd& q, int64_t w) {
+            if (cur > 0 && cur + w > KCHUNK) {
+                chunks.emplace_back();
+                cur = 0;
+            }
+            chunks.back().push_back(q);
+            cur += w;
+        };
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd& q = oldp[p];
+            if (q.ident) {
+                direct.push_back(q);
+                continue;
+            }
+            if (q.nred > 1) {
+                const int rc = (int)std::max<int64_t>(1, KCHUNK / std::max(1, q.K));
+                for (int r0 = 0; r0 < q.nred; r0 += rc) {
+                    GProd sub = q;
+                    sub.A = gshift(q.A, (int64_t)r0 * q.rsA, esize);
+                    sub.B = gshift(q.B, (int64_t)r0 * q.rsB, esize);
+                    sub.nred = std::min(rc, q.nred - r0);
+                    push(sub, (int64_t)sub.K * sub.nred);
+                }
+            } else {
+                for (int k0 = 0; k0 < q.K; k0 += (int)KCHUNK) {
+                    GProd sub = q;
+                    const int kl = (int)std::min<int64_t>(KCHUNK, q.K - k0);
+                    sub.A = gshift(q.A, q.tA ? (int64_t)k0 * q.lda : k0, esize);
+                    sub.B = gshift(q.B, q.tB ? (int64_t)k0 : (int64_t)k0 * q.ldb, esize);
+                    sub.K = kl;
+                    push(sub, kl);
+                }
+            }
+        }
+        GJob sum{};
+        sum.C = J.C;
+        sum.M = J.M;
+        sum.N = J.N;
+        sum.ldc = J.ldc;
+        sum.batch = 1;
+        sum.acc = J.acc;
+        sum.p0 = (int)P.prods[s + 1].size();
+        for (auto& ch : chunks) {
+            if (ch.empty()) continue;
+            GRef part = GRef{nullptr, P.ws_elems, TAG_WS, 0};
+            P.ws_elems += ((int64_t)J.M * J.N + 63) & ~(int64_t)63;
+            GJob pj{};
+            pj.C = part;
+            pj.M = J.M;
+            pj.N = J.N;
+            pj.ldc = J.N;
+            pj.batch = 1;
+            pj.p0 = (int)P.prods[s].size();
+            for (auto& q : ch) P.prods[s].push_back(q);
+            pj.p1 = (int)P.prods[s].size();
+            P.jobs[s].push_back(pj);
+            GProd add{};
+            add.ident = 1;
+            add.B = part;
+            add.ldb = J.N;
+            add.alpha = 1.0;
+            add.nred = 1;
+            P.prods[s + 1].push_back(add);
+        }
+        for (auto& q : direct) P.prods[s + 1].push_back(q);
+        sum.p1 = (int)P.prods[s + 1].size();
+        P.jobs[s + 1].push_back(sum);
+    }
+}
+
+void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs) {
+    if (m < n) fail(QED_ERR_BAD_STATE, "QR of a wide matrix");
+    if (n > 8192) fail(QED_ERR_UNSUPPORTED, "sector wider than 8192 columns");
+    const int64_t direct_max = std::max<int64_t>(4096, 16 * (int64_t)n);
+    if (m <= direct_max) {
+        DBuf scratch(dev, (size_t)m * n * sizeof(double));
+        QRMat q{0, 0, m, rrs, rcs, (int)m, n};
+        DBuf dq(dev, sizeof(QRMat));
+        dev->upload(dq.p, &q, sizeof(QRMat));
+        launch_qr(dq.as<QRMat>(), 1, n, M, scratch.as<double>(), R, dev->stream);
+        dev->check(hipGetLastError(), "qr launch");
+        return;
+    }
+    const int64_t b = std::max<int64_t>(2048, 4 * (int64_t)n);
+    const int P = (int)(m / b);
+    const int64_t ls = (int64_t)P * n;   // rows of the stacked R factors
+    DBuf S(dev, (size_t)ls * n * sizeof(double));
+    DBuf T(dev, (size_t)m * n * sizeof(double));
+    std::vector<QRMat> qs;
+    for (int i = 0; i < P; ++i) {
+        const int64_t r0 = (int64_t)i * b;
+        const int64_t rows = i == P - 1 ? m - r0 : b;
+        qs.push_back(QRMat{r0, (int64_t)i * n, m, 1, ls, (int)rows, n});
+    }
+    DBuf dq(dev, qs.size() * sizeof(QRMat));
+    dev->upload(dq.p, qs.data(), qs.size() * sizeof(QRMat));
+    launch_qr(dq.as<QRMat>(), P, n, M, T.as<double>(), S.as<double>(), dev->stream);
+    dev->check(hipGetLastError(), "qr launch");
+    tsqr(dev, S.as<double>(), ls, n, R, rrs, rcs);
+    // Q = blockdiag(Q1_i) * Q2: chunk i of Q is Q1_i Q2[i n .. (i+1) n)
+    Plan pl;
+    pl.dtype = QED_FP64;
+    pl.jobs.emplace_back();
+    pl.prods.emplace_back();
+    pl.stage_flops.push_back(0.0);
+    for (int i = 0; i < P; ++i) {
+        const int64_t r0 = (int64_t)i * b;
+        const int rows = qs[i].rows;
+        GProd pr{};
+        pr.A = GRef{S.as<double>() + (int64_t)i * n, 0, TAG_ABS, 0};
+        pr.lda = (int)ls;
+        pr.B = GRef{M + r0, 0, TAG_ABS, 0};
+        pr.ldb = (int)m;
+        pr.K = n;
+        pr.alpha = 1.0;
+        pr.nred = 1;
+        GJob j{};
+        j.C = GRef{T.as<double>() + r0, 0, TAG_ABS, 0};
+        j.M = n;
+        j.N = rows;
+        j.ldc = (int)m;
+        j.batch = 1;
+        j.p0 = (int)pl.prods[0].size();
+        pl.prods[0].push_back(pr);
+        j.p1 = j.p0 + 1;
+        pl.jobs[0].push_back(j);
+    }
+    pl.upload(dev);
+    pl.run(dev, nullptr, nullptr, nullptr);
+    dev->check(hipMemcpyAsync(M, T.p, (size_t)m * n * sizeof(double), hipMemcpyDeviceToDevice,
+                              dev->stream), "tsqr copy");
 }
 
 // ---------------------------------------------------------------------

@@ -160,6 +160,16 @@ Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
 // out_tensor = op applied on leg e of in_tensor (sector preserving op)
 Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out);
 
+// Split the jobs of stage s that have few output tiles and a long
+// reduction into K-chunk partial products (stage s) summed in stage s+1.
+void split_long_reductions(Plan& P, int s);
+
+// In-place QR of the contiguous column-major m x n matrix M (m >= n):
+// M := Q (orthonormal columns), R(r, c) written at R[r*rrs + c*rcs],
+// diag(R) >= 0.  Tall matrices use a tree of Householder QRs over row
+// chunks (TSQR) with a block GEMM assembling Q.
+void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs);
+
 // ---- Lanczos -----------------------------------------------------------
 struct LanczosWS {
     int m = 0;

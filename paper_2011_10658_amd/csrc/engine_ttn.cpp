@@ -135,12 +135,10 @@ OpP Engine::qr_toward(int n, int which) {
     }
     std::vector<int64_t> mat(ns, 0);
     int64_t tot = 0;
-    int maxcols = 0;
     for (int s = 0; s < ns; ++s) {
         if (rows[s] < L.n[s]) fail(QED_ERR_BAD_STATE, "a sector is wider than its rows (QR)");
         mat[s] = tot;
         tot += rows[s] * L.n[s];
-        maxcols = std::max(maxcols, L.n[s]);
     }
     OpP R = make_op(dev, L, 0, false);
     std::vector<PackBlk> pb;
@@ -160,15 +158,30 @@ OpP Engine::qr_toward(int n, int which) {
         maxsize = std::max(maxsize, sz);
         pb.push_back(B);
     }
-    std::vector<QRMat> qm;
-    for (int s = 0; s < ns; ++s) qm.push_back(QRMat{mat[s], R->lay.off[s], (int)rows[s], L.n[s]});
-    DBuf dpb(dev, pb.size() * sizeof(PackBlk)), dqm(dev, qm.size() * sizeof(QRMat));
+    DBuf dpb(dev, pb.size() * sizeof(PackBlk));
     dev->upload(dpb.p, pb.data(), pb.size() * sizeof(PackBlk));
-    dev->upload(dqm.p, qm.data(), qm.size() * sizeof(QRMat));
-    DBuf packed(dev, tot * sizeof(double)), qbuf(dev, tot * sizeof(double));
+    DBuf packed(dev, tot * sizeof(double));
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 0, dev->stream);
-    launch_qr(dqm.as<QRMat>(), ns, maxcols, packed.as<double>(), qbuf.as<double>(),
-              (double*)R->d64->p, dev->stream);
+    // sectors with few rows: one batched launch; tall sectors: TSQR each
+    std::vector<QRMat> small;
+    int64_t small_cols = 0;
+    for (int s = 0; s < ns; ++s) {
+        const int n_s = L.n[s];
+        if (rows[s] <= std::max<int64_t>(4096, 16 * (int64_t)n_s)) {
+            small.push_back(QRMat{mat[s], R->lay.off[s], rows[s], n_s, 1, (int)rows[s], n_s});
+            small_cols = std::max<int64_t>(small_cols, n_s);
+        } else {
+            tsqr(dev, packed.as<double>() + mat[s], rows[s], n_s, (double*)R->d64->p + R->lay.off[s],
+                 n_s, 1);
+        }
+    }
+    if (!small.empty()) {
+        DBuf dqm(dev, small.size() * sizeof(QRMat));
+        dev->upload(dqm.p, small.data(), small.size() * sizeof(QRMat));
+        DBuf qbuf(dev, tot * sizeof(double));
+        launch_qr(dqm.as<QRMat>(), (int)small.size(), (int)small_cols, packed.as<double>(),
+                  qbuf.as<double>(), (double*)R->d64->p, dev->stream);
+    }
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 1, dev->stream);
     dev->check(hipGetLastError(), "qr launch");
     return R;

@@ -61,10 +61,14 @@ struct PackBlk {
     int row0;          // first row of this block inside the sector matrix
 };
 
-// One sector matrix for the QR kernel.
+// One matrix for the QR kernel: column-major rows x cols with leading
+// dimension ld at `mat` (in the packed buffer and, for the scratch copy of
+// Q, in the scratch buffer); R(r, c) is written at rout + r*rrs + c*rcs.
 struct QRMat {
-    int64_t mat;       // offset in the packed buffer (column-major)
-    int64_t rout;      // offset of the R block (row-major cols x cols)
+    int64_t mat;
+    int64_t rout;
+    int64_t ld;
+    int64_t rrs, rcs;
     int rows, cols;
 };
 

@@ -232,16 +232,24 @@ __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ 
     }
 }
 
-// out[r] = sum_b partial[r * G + b] (sequential in b); mode 1: sqrt
-__global__ void k_dot_final(const double* __restrict__ partial, int G, int nrows,
-                            double* __restrict__ out, int mode, const LState* st,
-                            int skip_if_broken) {
+// out[r] = sum_b partial[r * G + b]; one workgroup per row, fixed
+// strided partition and fixed reduction tree; mode 1: sqrt
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ partial, int G,
+                                                   int nrows, double* __restrict__ out, int mode,
+                                                   const LState* st, int skip_if_broken) {
     if (skip_if_broken && st && st->broken) return;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
     if (r >= nrows) return;
     double s = 0.0;
-    for (int b = 0; b < G; ++b) s += partial[(int64_t)r * G + b];
-    out[r] = mode == 1 ? sqrt(s) : s;
+    for (int b = threadIdx.x; b < G; b += 256) s += partial[(int64_t)r * G + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        out[r] = mode == 1 ? sqrt(t) : t;
+    }
 }
 
 void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64_t n,
@@ -250,8 +258,8 @@ void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64
     const int G = dot_grid(n);
     hipLaunchKernelGGL(k_dot_partial, dim3(G), dim3(256), 0, stream, V, ldv, nrows, w, n, partial,
                        st, skip);
-    hipLaunchKernelGGL(k_dot_final, dim3((nrows + 63) / 64), dim3(64), 0, stream, partial, G, nrows,
-                       out, mode, st, skip);
+    hipLaunchKernelGGL(k_dot_final, dim3(nrows), dim3(256), 0, stream, partial, G, nrows, out,
+                       mode, st, skip);
 }
 
 // ---------------------------------------------------------------------
@@ -562,11 +570,12 @@ void launch_pack(const PackBlk* blks, int nblk, int64_t maxsize, double* tensor,
     hipLaunchKernelGGL(k_pack, dim3(nblk, (int)gy), dim3(256), 0, s, blks, tensor, packed, dir);
 }
 
-// Householder QR of one column-major rows x cols matrix per workgroup
-// (rows >= cols).  On exit the packed matrix holds the explicit Q with
-// orthonormal columns and R (row-major cols x cols) is written at
-// rbuf + rout; signs are fixed so that diag(R) >= 0.  `qbuf` is a
-// scratch matrix of the same shape as the input.
+// Householder QR of one column-major rows x cols matrix (leading dimension
+// ld) per workgroup, rows >= cols.  On exit the matrix holds the explicit Q
+// with orthonormal columns and R is written through (rout, rrs, rcs); signs
+// are fixed so that diag(R) >= 0.  `qbuf` is scratch with the same layout
+// as the input.  Zero columns (rank deficiency) get tau = 0 and R_jj = 0,
+// and Q still has orthonormal columns.
 __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict__ mats,
                                                         double* __restrict__ packed,
                                                         double* __restrict__ qbuf,
@@ -574,6 +583,7 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
     extern __shared__ double lds[];
     const QRMat Mt = mats[blockIdx.x];
     const int m = Mt.rows, n = Mt.cols;
+    const int64_t ld = Mt.ld;
     double* A = packed + Mt.mat;
     double* Qm = qbuf + Mt.mat;
     double* R = rbuf + Mt.rout;
@@ -582,15 +592,14 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
     double* red = lds + 2 * n;  // 4
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j = 0; j < n; ++j) {
-        // norm of A[j:, j]
         double s = 0.0;
-        for (int i = j + tid; i < m; i += 256) s += A[(int64_t)j * m + i] * A[(int64_t)j * m + i];
+        for (int i = j + tid; i < m; i += 256) s += A[(int64_t)j * ld + i] * A[(int64_t)j * ld + i];
         s = wave_sum(s);
         if (lane == 0) red[wave] = s;
         __syncthreads();
         if (tid == 0) {
             const double norm2 = ((red[0] + red[1]) + red[2]) + red[3];
-            const double x0 = A[(int64_t)j * m + j];
+            const double x0 = A[(int64_t)j * ld + j];
             const double nrm = sqrt(norm2);
             if (nrm == 0.0) {
                 tau[j] = 0.0;
@@ -601,33 +610,30 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
                 const double vtv = v0 * v0 + (norm2 - x0 * x0);
                 tau[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
                 diag[j] = al;
-                A[(int64_t)j * m + j] = v0;
+                A[(int64_t)j * ld + j] = v0;
             }
         }
         __syncthreads();
         const double tj = tau[j];
         if (tj != 0.0) {
-            // trailing columns: each wave owns columns j+1+wave, +4, ...
             for (int k = j + 1 + wave; k < n; k += 4) {
                 double d = 0.0;
-                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * m + i] * A[(int64_t)k * m + i];
+                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * ld + i] * A[(int64_t)k * ld + i];
                 d = wave_sum(d);
                 d = __shfl(d, 0, 64);
                 const double f = tj * d;
-                for (int i = j + lane; i < m; i += 64) A[(int64_t)k * m + i] -= f * A[(int64_t)j * m + i];
+                for (int i = j + lane; i < m; i += 64) A[(int64_t)k * ld + i] -= f * A[(int64_t)j * ld + i];
             }
         }
         __syncthreads();
     }
-    // R (before the sign fix): strict upper part from A, diagonal from diag
     for (int e = tid; e < n * n; e += 256) {
         const int r = e / n, c = e % n;
-        R[e] = c > r ? A[(int64_t)c * m + r] : (c == r ? diag[r] : 0.0);
+        R[r * Mt.rrs + c * Mt.rcs] = c > r ? A[(int64_t)c * ld + r] : (c == r ? diag[r] : 0.0);
     }
-    // explicit Q = H_0 ... H_{n-1} [I; 0]
     for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
         const int c = (int)(e / m), r = (int)(e % m);
-        Qm[e] = r == c ? 1.0 : 0.0;
+        Qm[(int64_t)c * ld + r] = r == c ? 1.0 : 0.0;
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
@@ -635,23 +641,23 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
         if (tj != 0.0) {
             for (int k = j + wave; k < n; k += 4) {
                 double d = 0.0;
-                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * m + i] * Qm[(int64_t)k * m + i];
+                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * ld + i] * Qm[(int64_t)k * ld + i];
                 d = wave_sum(d);
                 d = __shfl(d, 0, 64);
                 const double f = tj * d;
-                for (int i = j + lane; i < m; i += 64) Qm[(int64_t)k * m + i] -= f * A[(int64_t)j * m + i];
+                for (int i = j + lane; i < m; i += 64) Qm[(int64_t)k * ld + i] -= f * A[(int64_t)j * ld + i];
             }
         }
         __syncthreads();
     }
-    // sign fix diag(R) >= 0, copy Q back over the packed matrix
     for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
-        const int c = (int)(e / m);
-        A[e] = diag[c] < 0.0 ? -Qm[e] : Qm[e];
+        const int c = (int)(e / m), r = (int)(e % m);
+        const double q = Qm[(int64_t)c * ld + r];
+        A[(int64_t)c * ld + r] = diag[c] < 0.0 ? -q : q;
     }
     for (int e = tid; e < n * n; e += 256) {
-        const int r = e / n;
-        if (diag[r] < 0.0) R[e] = -R[e];
+        const int r = e / n, c = e % n;
+        if (diag[r] < 0.0) R[r * Mt.rrs + c * Mt.rcs] = -R[r * Mt.rrs + c * Mt.rcs];
     }
 }
 
