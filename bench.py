@@ -56,11 +56,20 @@ def make_ctx(lib, dtype):
 
 
 def run_path(lib, torch, dtype, steps, warmup):
+    """Warm-up sweeps (with per-sweep records: energy, library-timed sweep
+    seconds) then `steps` timed sweeps bracketed by device syncs."""
     ctx = make_ctx(lib, dtype)
     t0 = time.perf_counter()
-    ctx.sweep(warmup, report=False)
+    reps = ctx.sweep(warmup, report=True) if warmup else []
     torch.cuda.synchronize()
     log(f"  warmup {warmup} sweeps: {time.perf_counter() - t0:.2f} s")
+    # time to convergence: first sweep s with |E_s - E_{s-1}| <= 1e-8 |E_s|
+    conv, t_conv = None, 0.0
+    for i, r in enumerate(reps):
+        t_conv += r["seconds"]
+        if i and abs(r["energy"] - reps[i - 1]["energy"]) <= 1e-8 * abs(r["energy"]):
+            conv = i
+            break
     ctx.set_profiling(True)
     s0 = ctx.stats()
     torch.cuda.synchronize()
@@ -83,6 +92,9 @@ def run_path(lib, torch, dtype, steps, warmup):
         energy=E,
         deltaL=ob["deltaL"],
         Q=ob["Q"],
+        converged_sweep=conv,
+        seconds_to_converge=t_conv if conv is not None else None,
+        warmup_energies=[r["energy"] for r in reps],
     )
     out["tflops"] = out["flops"] / wall / 1e12
     out["gemm_tflops"] = out["gemm_flops"] / (out["gemm_ms"] / 1e3) / 1e12 if out["gemm_ms"] else 0.0
@@ -248,14 +260,23 @@ def main():
             "workload": "TTN sweep, 2x2x2 open-lattice compact QED, free-flux boundary "
                         "(d=267 per site), Q=0, m=t=1, g^2=1 (g_e^2=1, g_m^2=8), chi=64",
             "lattice": "2x2x2", "bond_dim": CHI, "charge": 0, "seed": SEED,
-            "lanczos": "24 steps x <=4 cycles, tol 1e-10, FP64 Rayleigh quotient",
+            "lanczos": "24 steps x <=4 cycles, tol 1e-10 (FP32 path: floor 2e-6), "
+                       "FP64 Rayleigh quotient per update",
+            "convergence": "|E_s - E_{s-1}| <= 1e-8 |E_s| within the warm-up sweeps",
         },
         "sweep_s": r32["ms_per_step"] / 1e3,
         "energy": r32["energy"],
         "dE_rel_vs_fp64": dE,
         "dE_within_1e-8": bool(dE <= 1e-8),
         "fp64_path": {"ms_per_step": r64["ms_per_step"], "tflops": r64["tflops"],
-                      "energy": r64["energy"], "gemm_tflops": r64["gemm_tflops"]},
+                      "energy": r64["energy"], "gemm_tflops": r64["gemm_tflops"],
+                      "converged_sweep": r64["converged_sweep"],
+                      "seconds_to_converge": r64["seconds_to_converge"]},
+        "converged_sweep": r32["converged_sweep"],
+        "seconds_to_converge": r32["seconds_to_converge"],
+        "speedup_vs_fp64": {"sweep": r64["ms_per_step"] / r32["ms_per_step"],
+                            "to_converge": (r64["seconds_to_converge"] / r32["seconds_to_converge"])
+                            if r64["seconds_to_converge"] and r32["seconds_to_converge"] else None},
         "deltaL": r32["deltaL"],
         "roofline": {
             "bound": "mfma",

@@ -196,11 +196,26 @@ void Plan::upload(Dev* dev) {
     dp.clear();
     dt.clear();
     ntiles.clear();
+    shape.clear();
     for (size_t s = 0; s < jobs.size(); ++s) {
+        // the tile shape that pads the stage's jobs least
+        int best = GEMM_SHAPE_SQUARE;
+        double best_area = -1.0;
+        for (int sh : {GEMM_SHAPE_SQUARE, GEMM_SHAPE_TALL, GEMM_SHAPE_WIDE}) {
+            const int TM = gemm_tm(sh), TN = gemm_tn(sh);
+            double area = 0.0;
+            for (const GJob& J : jobs[s])
+                area += (double)J.batch * ((J.M + TM - 1) / TM) * TM * ((J.N + TN - 1) / TN) * TN;
+            if (best_area < 0 || area < best_area * 0.999) {
+                best_area = area;
+                best = sh;
+            }
+        }
+        const int TM = gemm_tm(best), TN = gemm_tn(best);
         std::vector<GTile> tiles;
         for (size_t j = 0; j < jobs[s].size(); ++j) {
             const GJob& J = jobs[s][j];
-            const int tm = (J.M + GEMM_TM - 1) / GEMM_TM, tn = (J.N + GEMM_TN - 1) / GEMM_TN;
+            const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
             for (int b = 0; b < J.batch; ++b)
                 for (int a = 0; a < tm; ++a)
                     for (int c = 0; c < tn; ++c) tiles.push_back(GTile{(int)j, b, a, c});
@@ -219,6 +234,7 @@ void Plan::upload(Dev* dev) {
         dp.push_back(bp);
         dt.push_back(bt);
         ntiles.push_back((int)tiles.size());
+        shape.push_back(best);
     }
     dev->sync();  // host vectors of this plan may change afterwards
 }
@@ -266,10 +282,10 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
         if (timed) prof->record_begin(dev->stream, e0);
         if (dtype == QED_FP64)
             launch_brgemm<double>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(),
-                                  ntiles[s], b, dev->stream);
+                                  ntiles[s], b, shape[s], dev->stream);
         else
             launch_brgemm<float>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(),
-                                 ntiles[s], b, dev->stream);
+                                 ntiles[s], b, shape[s], dev->stream);
         if (timed) {
             prof->record_begin(dev->stream, e1);
             prof->ev.push_back({e0, e1});
@@ -495,7 +511,7 @@ GRef gshift(GRef r, int64_t elems, int esize) {
 
 void split_long_reductions(Plan& P, int s) {
     const int64_t KCHUNK = 1024;
-    const int MIN_TILES = 32;
+    const int MIN_TILES = 16;
     const int esize = P.dtype == QED_FP64 ? 8 : 4;
     if ((int)P.jobs.size() <= s) return;
     while ((int)P.jobs.size() <= s + 1) {
@@ -508,7 +524,7 @@ void split_long_reductions(Plan& P, int s) {
     P.jobs[s].clear();
     P.prods[s].clear();
     for (const GJob& J : old) {
-        const int64_t tiles = (int64_t)((J.M + GEMM_TM - 1) / GEMM_TM) * ((J.N + GEMM_TN - 1) / GEMM_TN) * J.batch;
+        const int64_t tiles = (int64_t)((J.M + 63) / 64) * ((J.N + 63) / 64) * J.batch;
         int64_t W = 0;
         for (int p = J.p0; p < J.p1; ++p)
             if (!oldp[p].ident) W += (int64_t)oldp[p].K * oldp[p].nred;

@@ -19,7 +19,8 @@ namespace qed {
 
 // ---- kernel launchers (kernels.hip) ----------------------------------
 template <typename T>
-void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
+void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape,
+                   hipStream_t);
 void launch_fill(double*, int64_t, double, hipStream_t);
 void launch_f64_to_f32(const double*, float*, int64_t, hipStream_t);
 void launch_f32_to_f64(const float*, double*, int64_t, hipStream_t);
@@ -135,6 +136,7 @@ struct Plan {
     // device copies
     std::vector<BufP> dj, dp, dt;
     std::vector<int> ntiles;
+    std::vector<int> shape;   // workgroup tile shape per stage
     void upload(Dev* dev);
     void run(Dev* dev, void* ws, void* x, void* y);
 };

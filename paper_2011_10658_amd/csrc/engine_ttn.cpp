@@ -18,6 +18,8 @@
 
 namespace qed {
 
+constexpr double LZ_TOL_FLOOR_FP32 = 2e-6;
+
 namespace {
 
 uint64_t mix64(uint64_t z) {
@@ -419,7 +421,11 @@ double Engine::update(int n, double nu) {
             launch_f32_to_f64(yc->as<float>(), y, n_el, dev->stream);
         }
     };
-    LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, P.lz_tol);
+    // an FP32 Krylov recurrence cannot resolve residuals below ~eps32 |H|:
+    // restarts past that point only repeat work (the FP64 Rayleigh quotient
+    // below fixes the energy)
+    const double tol = dtype == QED_FP64 ? P.lz_tol : std::max(P.lz_tol, LZ_TOL_FLOOR_FP32);
+    LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol);
     matvecs += R.matvecs;
     flops += R.matvecs * plan.flops;
     ctx->mv_count += R.matvecs;

@@ -45,9 +45,10 @@ struct GTile {
     int job, b, tm, tn;
 };
 
-constexpr int GEMM_TM = 32;
-constexpr int GEMM_TN = 32;
-constexpr int GEMM_KC = 16;
+// Workgroup tile shapes of the block GEMM (rows x cols of the output).
+enum { GEMM_SHAPE_SQUARE = 0, GEMM_SHAPE_TALL = 1, GEMM_SHAPE_WIDE = 2 };
+inline int gemm_tm(int shape) { return shape == GEMM_SHAPE_TALL ? 128 : shape == GEMM_SHAPE_WIDE ? 32 : 64; }
+inline int gemm_tn(int shape) { return shape == GEMM_SHAPE_TALL ? 32 : shape == GEMM_SHAPE_WIDE ? 128 : 64; }
 constexpr int GEMM_THREADS = 256;
 
 // Per-block description for packing a node tensor into the column-major

@@ -46,96 +46,160 @@ __device__ __forceinline__ T* resolve(const GRef& r, const Bases& bs) {
 // ---------------------------------------------------------------------
 // grouped batch-reduce GEMM
 // ---------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(GEMM_THREADS) void k_brgemm(const GJob* __restrict__ jobs,
-                                                         const GProd* __restrict__ prods,
-                                                         const GTile* __restrict__ tiles,
-                                                         Bases bases) {
+// Workgroup tile (32 WM) x (32 WN) on 4 waves in a WM x WN grid; every wave
+// owns a 32 x 32 sub-tile = 2 x 2 MFMA 16x16 blocks.  K advances in chunks
+// of KC staged k-major in LDS (As[k][m], Bs[k][n]: the MFMA operand reads
+// of a wave hit 16 consecutive words); the next chunk is fetched into
+// registers while the current one is multiplied.
+constexpr int KC = 16;
+
+template <typename T, int WM, int WN>
+__global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
+                                                const GProd* __restrict__ prods,
+                                                const GTile* __restrict__ tiles, Bases bases) {
     typedef typename Mfma<T>::v4 v4;
-    __shared__ T As[GEMM_TM][GEMM_KC + 1];
-    __shared__ T Bs[GEMM_KC][GEMM_TN + 1];
+    constexpr int TM = 32 * WM, TN = 32 * WN;
+    constexpr int PAD = 4;
+    constexpr int AE = TM * KC / 256;   // A elements per thread per chunk
+    constexpr int BE = TN * KC / 256;
+    __shared__ T As[KC][TM + PAD];
+    __shared__ T Bs[KC][TN + PAD];
     const GTile tl = tiles[blockIdx.x];
     const GJob J = jobs[tl.job];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 16;
-    const int wn = (wave & 1) * 16;
-    const int m0 = tl.tm * GEMM_TM;
-    const int n0 = tl.tn * GEMM_TN;
-    v4 acc = {0, 0, 0, 0};
+    const int wm0 = (wave / WN) * 32;
+    const int wn0 = (wave % WN) * 32;
+    const int m0 = tl.tm * TM;
+    const int n0 = tl.tn * TN;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    T ra[AE], rb[BE];
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
         const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
         const T alpha = (T)P.alpha;
         if (P.ident) {
-            const int col = n0 + wn + (lane & 15);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = m0 + wm + Mfma<T>::row(lane, i);
-                if (row < J.M && col < J.N) acc[i] += alpha * Bb[(int64_t)row * P.ldb + col];
-            }
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    const int col = n0 + wn0 + bj * 16 + lr;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
+                        if (row < J.M && col < J.N)
+                            acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + col];
+                    }
+                }
             continue;
         }
         const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        const int nchunk = (P.K + KC - 1) / KC;
         for (int r = 0; r < P.nred; ++r) {
             const T* A = Ab + (int64_t)r * P.rsA;
             const T* B = Bb + (int64_t)r * P.rsB;
-            for (int k0 = 0; k0 < P.K; k0 += GEMM_KC) {
-                __syncthreads();
-                for (int e = tid; e < GEMM_TM * GEMM_KC; e += GEMM_THREADS) {
+            auto fetch = [&](int k0) {
+#pragma unroll
+                for (int e = 0; e < AE; ++e) {
+                    const int idx = tid + e * 256;
                     int m, k;
-                    if (P.tA) { m = e % GEMM_TM; k = e / GEMM_TM; }
-                    else { k = e % GEMM_KC; m = e / GEMM_KC; }
+                    if (P.tA) { m = idx % TM; k = idx / TM; }
+                    else { k = idx % KC; m = idx / KC; }
                     const int gm = m0 + m, gk = k0 + k;
                     T v = (T)0;
                     if (gm < J.M && gk < P.K)
                         v = P.tA ? A[(int64_t)gk * P.lda + gm] : A[(int64_t)gm * P.lda + gk];
-                    As[m][k] = v * alpha;
+                    ra[e] = v * alpha;
                 }
-                for (int e = tid; e < GEMM_KC * GEMM_TN; e += GEMM_THREADS) {
+#pragma unroll
+                for (int e = 0; e < BE; ++e) {
+                    const int idx = tid + e * 256;
                     int k, n;
-                    if (P.tB) { k = e % GEMM_KC; n = e / GEMM_KC; }
-                    else { n = e % GEMM_TN; k = e / GEMM_TN; }
+                    if (P.tB) { k = idx % KC; n = idx / KC; }
+                    else { n = idx % TN; k = idx / TN; }
                     const int gn = n0 + n, gk = k0 + k;
                     T v = (T)0;
                     if (gn < J.N && gk < P.K)
                         v = P.tB ? B[(int64_t)gn * P.ldb + gk] : B[(int64_t)gk * P.ldb + gn];
-                    Bs[k][n] = v;
+                    rb[e] = v;
                 }
-                __syncthreads();
+            };
+            auto stash = [&]() {
 #pragma unroll
-                for (int kk = 0; kk < GEMM_KC; kk += 4) {
-                    const T a = As[wm + (lane & 15)][kk + (lane >> 4)];
-                    const T b = Bs[kk + (lane >> 4)][wn + (lane & 15)];
-                    acc = Mfma<T>::step(a, b, acc);
+                for (int e = 0; e < AE; ++e) {
+                    const int idx = tid + e * 256;
+                    int m, k;
+                    if (P.tA) { m = idx % TM; k = idx / TM; }
+                    else { k = idx % KC; m = idx / KC; }
+                    As[k][m] = ra[e];
+                }
+#pragma unroll
+                for (int e = 0; e < BE; ++e) {
+                    const int idx = tid + e * 256;
+                    int k, n;
+                    if (P.tB) { k = idx % KC; n = idx / KC; }
+                    else { n = idx % TN; k = idx / TN; }
+                    Bs[k][n] = rb[e];
+                }
+            };
+            fetch(0);
+            for (int c = 0; c < nchunk; ++c) {
+                __syncthreads();
+                stash();
+                __syncthreads();
+                if (c + 1 < nchunk) fetch((c + 1) * KC);
+#pragma unroll
+                for (int kk = 0; kk < KC; kk += 4) {
+                    const T a0 = As[kk + lk][wm0 + lr];
+                    const T a1 = As[kk + lk][wm0 + 16 + lr];
+                    const T b0 = Bs[kk + lk][wn0 + lr];
+                    const T b1 = Bs[kk + lk][wn0 + 16 + lr];
+                    acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
+                    acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
+                    acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
+                    acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
                 }
             }
         }
     }
     T* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
-    const int col = n0 + wn + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = m0 + wm + Mfma<T>::row(lane, i);
-        if (row < J.M && col < J.N) {
-            T* c = C + (int64_t)row * J.ldc + col;
-            *c = J.acc ? *c + acc[i] : acc[i];
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = n0 + wn0 + bj * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
+                if (row < J.M && col < J.N) {
+                    T* c = C + (int64_t)row * J.ldc + col;
+                    *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
+                }
+            }
         }
-    }
 }
 
 template <typename T>
 void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
-                   const Bases& bases, hipStream_t st) {
+                   const Bases& bases, int shape, hipStream_t st) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_brgemm<T>, dim3(ntiles), dim3(GEMM_THREADS), 0, st, jobs, prods, tiles,
-                       bases);
+    if (shape == GEMM_SHAPE_TALL)
+        hipLaunchKernelGGL((k_brgemm<T, 4, 1>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+    else if (shape == GEMM_SHAPE_WIDE)
+        hipLaunchKernelGGL((k_brgemm<T, 1, 4>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+    else
+        hipLaunchKernelGGL((k_brgemm<T, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
 }
 
-template void launch_brgemm<double>(const GJob*, const GProd*, const GTile*, int, const Bases&,
+template void launch_brgemm<double>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
                                     hipStream_t);
-template void launch_brgemm<float>(const GJob*, const GProd*, const GTile*, int, const Bases&,
+template void launch_brgemm<float>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
                                    hipStream_t);
 
 // ---------------------------------------------------------------------
