@@ -266,6 +266,56 @@ int qed_heff_lanczos(qed_heff* h, double* x_inout, int steps, double* eval, doub
  * operator blocks in the GEMM dtype. */
 int qed_heff_flops(qed_heff* h, double* flops, double* bytes);
 
+/* ---------------------------------------------------------------- */
+/* batched node updates                                              */
+/* ---------------------------------------------------------------- */
+
+/* One node of a batch: its three legs and its terms (as in
+ * qed_heff_create; operators are copied at create time). */
+typedef struct {
+    const int* ch[3];
+    const int* n[3];
+    int nsec[3];
+    int K;
+    const qed_term* terms;
+} qed_heff_desc;
+
+/* Many independent node-level effective Hamiltonians in one object: every
+ * contraction stage of all nodes is one grouped block-GEMM launch, and the
+ * Lanczos recurrences of all nodes advance together (one per node).  The
+ * batch works on the concatenation of the nodes' flat vectors (node i at
+ * offset offs[i]). */
+int qed_heff_batch_create(qed_ctx* ctx, int nnodes, const qed_heff_desc* nodes,
+                          qed_heff_batch** out);
+int qed_heff_batch_destroy(qed_heff_batch* b);
+
+/* Total length of the concatenated vector and (optional, nnodes + 1)
+ * per-node offsets. */
+int qed_heff_batch_size(qed_heff_batch* b, int64_t* total, int64_t* offs);
+
+/* y = blockdiag(H_eff,i) x on device FP64 concatenated vectors. */
+int qed_heff_batch_matvec(qed_heff_batch* b, const double* x, double* y);
+
+/* Lowest eigenpair of every node: x (device FP64, concatenated) holds the
+ * start vectors and receives the normalised Ritz vectors; evals[nnodes]
+ * and resids[nnodes] (may be NULL) receive theta and the residual
+ * estimates.  use_graph != 0 replays a HIP graph of one whole cycle
+ * (captured on first use for this step count).  Cycles and tolerance as
+ * set by qed_set_lanczos (a cycle ends for all nodes when every node has
+ * converged). */
+int qed_heff_batch_lanczos(qed_heff_batch* b, double* x_inout, int steps, double* evals,
+                           double* resids, int use_graph);
+
+/* Algorithmic flops and bytes of one batched matvec. */
+int qed_heff_batch_flops(qed_heff_batch* b, double* flops, double* bytes);
+
+/* Autotuner: from now on, node-level and batched H_eff objects time the
+ * three workgroup tile shapes of every GEMM stage and keep the fastest.
+ * Decisions are cached per stage signature and, if cache_path is not
+ * NULL, loaded from and saved to that text file.  cache_path = "" turns
+ * tuning off. */
+int qed_autotune(qed_ctx* ctx, const char* cache_path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,11 @@ struct qed_heff {
     qed_ctx* owner = nullptr;
 };
 
+struct qed_heff_batch {
+    HeffBatch b;
+    qed_ctx* owner = nullptr;
+};
+
 namespace {
 
 template <typename F>
@@ -482,6 +487,12 @@ int qed_heff_create(qed_ctx* ctx, const int* ch_l, const int* n_l, int s_l, cons
             H.xc = std::make_shared<DBuf>(dev, H.tab.size() * sizeof(float));
             H.yc = std::make_shared<DBuf>(dev, H.tab.size() * sizeof(float));
         }
+        if (C(ctx).tuner.on) {
+            const size_t es = dtype == QED_FP64 ? 8 : 4;
+            void* w = H.ws.get(dev, std::max<int64_t>(1, H.plan.ws_elems) * es);
+            DBuf tx(dev, H.tab.size() * es), ty(dev, H.tab.size() * es);
+            C(ctx).tuner.tune(dev, H.plan, w, tx.p, ty.p);
+        }
         dev->sync();
         *out = h.release();
         return QED_OK;
@@ -538,6 +549,177 @@ int qed_heff_flops(qed_heff* h, double* flops, double* bytes) {
     if (!h) return QED_ERR_INVALID_ARG;
     if (flops) *flops = h->h.plan.flops;
     if (bytes) *bytes = h->h.plan.bytes;
+    return QED_OK;
+}
+
+int qed_autotune(qed_ctx* ctx, const char* cache_path) {
+    return guard(ctx, [&] {
+        Tuner& t = C(ctx).tuner;
+        if (cache_path && cache_path[0] == '\0') {
+            t.on = false;
+            return (int)QED_OK;
+        }
+        t.on = true;
+        t.path = cache_path ? cache_path : "";
+        t.load();
+        return (int)QED_OK;
+    });
+}
+
+int qed_heff_batch_create(qed_ctx* ctx, int nnodes, const qed_heff_desc* nodes,
+                          qed_heff_batch** out) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        if (!out || nnodes <= 0 || !nodes) fail(QED_ERR_INVALID_ARG, "bad arguments");
+        *out = nullptr;
+        auto hb = std::make_unique<qed_heff_batch>();
+        hb->owner = ctx;
+        HeffBatch& B = hb->b;
+        B.ctx = &C(ctx);
+        Dev* dev = &C(ctx).dev;
+        const int dtype = C(ctx).prm.dtype;
+        B.nn = nnodes;
+        B.off.push_back(0);
+        B.plan.dtype = dtype;
+        for (int i = 0; i < nnodes; ++i) {
+            const qed_heff_desc& d = nodes[i];
+            std::array<Leg, 3> lg;
+            for (int e = 0; e < 3; ++e) lg[e] = make_leg(d.ch[e], d.n[e], d.nsec[e]);
+            BlockTable tab = make_table(lg[0], lg[1], lg[2], 0);
+            if (tab.nblk() == 0) fail(QED_ERR_INVALID_ARG, "a node has no allowed block");
+            if (d.K < 0 || (d.K > 0 && !d.terms)) fail(QED_ERR_INVALID_ARG, "bad terms");
+            std::vector<HTerm> ts;
+            for (int k = 0; k < d.K; ++k) {
+                const qed_term& t = d.terms[k];
+                if (!std::isfinite(t.coef)) fail(QED_ERR_INVALID_ARG, "non-finite coefficient");
+                int sh[3];
+                for (int e = 0; e < 3; ++e) sh[e] = t.op[e] ? t.shift[e] : 0;
+                if (sh[0] + sh[1] != sh[2]) fail(QED_ERR_INVALID_ARG, "term shifts must obey shift_l + shift_r = shift_p");
+                HTerm ht{t.coef, {nullptr, nullptr, nullptr}};
+                for (int e = 0; e < 3; ++e) {
+                    if (!t.op[e]) continue;
+                    OpP o = make_op(dev, lg[e], sh[e], false);
+                    if (o->lay.size)
+                        dev->check(hipMemcpyAsync(o->d64->p, t.op[e], o->lay.size * sizeof(double),
+                                                  hipMemcpyDeviceToDevice, dev->stream), "operator copy");
+                    ht.op[e] = o;
+                }
+                ts.push_back(ht);
+            }
+            B.legs.push_back(lg);
+            B.tabs.push_back(tab);
+            B.terms.push_back(ts);
+            append_matvec(B.plan, lg.data(), tab, ts, B.off.back());
+            B.off.push_back(B.off.back() + tab.size());
+        }
+        const int64_t N = B.off.back();
+        B.plan.upload(dev);
+        B.ws = std::make_shared<DBuf>(dev, std::max<int64_t>(1, B.plan.ws_elems) * (dtype == QED_FP64 ? 8 : 4));
+        if (dtype != QED_FP64) {
+            B.xc = std::make_shared<DBuf>(dev, N * sizeof(float));
+            B.yc = std::make_shared<DBuf>(dev, N * sizeof(float));
+        }
+        dev->check(hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking), "stream");
+        if (C(ctx).tuner.on) {
+            DBuf tx(dev, N * (dtype == QED_FP64 ? 8 : 4)), ty(dev, N * (dtype == QED_FP64 ? 8 : 4));
+            C(ctx).tuner.tune(dev, B.plan, B.ws->p, tx.p, ty.p);
+        }
+        dev->sync();
+        *out = hb.release();
+        return (int)QED_OK;
+    });
+}
+
+int qed_heff_batch_destroy(qed_heff_batch* b) {
+    if (!b) return QED_ERR_INVALID_ARG;
+    try {
+        (void)hipStreamSynchronize(b->b.ctx->dev.stream);
+    } catch (...) {
+    }
+    delete b;
+    return QED_OK;
+}
+
+int qed_heff_batch_size(qed_heff_batch* b, int64_t* total, int64_t* offs) {
+    if (!b) return QED_ERR_INVALID_ARG;
+    if (total) *total = b->b.off.back();
+    if (offs)
+        for (size_t i = 0; i < b->b.off.size(); ++i) offs[i] = b->b.off[i];
+    return QED_OK;
+}
+
+int qed_heff_batch_matvec(qed_heff_batch* b, const double* x, double* y) {
+    if (!b) return QED_ERR_INVALID_ARG;
+    return guard(b->owner, [&] {
+        if (!x || !y || x == y) fail(QED_ERR_INVALID_ARG, "x and y must be distinct device buffers");
+        Dev& dev = b->b.ctx->dev;
+        b->b.matvec(x, y, dev.stream);
+        dev.check(hipGetLastError(), "batch matvec");
+        Ctx& c = *b->b.ctx;
+        c.mv_flops += b->b.plan.flops;
+        c.mv_count += 1;
+        return (int)QED_OK;
+    });
+}
+
+int qed_heff_batch_lanczos(qed_heff_batch* b, double* x, int steps, double* evals, double* resids,
+                           int use_graph) {
+    if (!b) return QED_ERR_INVALID_ARG;
+    return guard(b->owner, [&] {
+        if (!x || !evals) fail(QED_ERR_INVALID_ARG, "x and evals are required");
+        HeffBatch& B = b->b;
+        Ctx& c = *B.ctx;
+        Dev& dev = c.dev;
+        const Params& P = c.prm;
+        const int m = steps > 0 ? steps : P.lz_steps;
+        if (m < 1 || m > 64) fail(QED_ERR_INVALID_ARG, "1 .. 64 Lanczos steps");
+        if (B.lz.m != m || B.lz.nseg != B.nn) B.lz.setup(&dev, B.off, B.off.back(), m);
+        // the batch runs on its own stream (graph capture needs one)
+        dev.sync();
+        auto apply = [&](const double* v, double* y) { B.matvec(v, y, B.stream); };
+        if (use_graph && (!B.gexec || B.gm != m || B.gx != x)) {
+            if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
+            if (B.graph) (void)hipGraphDestroy(B.graph);
+            B.gexec = nullptr;
+            B.graph = nullptr;
+            dev.check(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal), "capture");
+            B.lz.cycle(apply, x, B.stream);
+            dev.check(hipStreamEndCapture(B.stream, &B.graph), "capture");
+            dev.check(hipGraphInstantiate(&B.gexec, B.graph, nullptr, nullptr, 0), "graph instantiate");
+            B.gm = m;
+            B.gx = x;
+        }
+        std::vector<LState> hs(B.nn);
+        int rc = QED_OK;
+        for (int cyc = 0; cyc < std::max(1, P.lz_cycles); ++cyc) {
+            if (use_graph) dev.check(hipGraphLaunch(B.gexec, B.stream), "graph launch");
+            else B.lz.cycle(apply, x, B.stream);
+            dev.check(hipGetLastError(), "batch lanczos");
+            dev.check(hipMemcpyAsync(hs.data(), B.lz.st->p, B.nn * sizeof(LState),
+                                     hipMemcpyDeviceToHost, B.stream), "state copy");
+            dev.check(hipStreamSynchronize(B.stream), "sync");
+            c.mv_count += m;
+            c.mv_flops += (double)m * B.plan.flops;
+            bool all = true;
+            for (int i = 0; i < B.nn; ++i) {
+                if (!std::isfinite(hs[i].theta)) fail(QED_ERR_NONFINITE, "non-finite Ritz value");
+                if (hs[i].resid > P.lz_tol * std::fabs(hs[i].theta)) all = false;
+            }
+            if (all) break;
+            if (cyc + 1 == std::max(1, P.lz_cycles) && P.lz_tol > 0) rc = QED_NOT_CONVERGED;
+        }
+        for (int i = 0; i < B.nn; ++i) {
+            evals[i] = hs[i].theta;
+            if (resids) resids[i] = hs[i].resid;
+        }
+        return rc;
+    });
+}
+
+int qed_heff_batch_flops(qed_heff_batch* b, double* flops, double* bytes) {
+    if (!b) return QED_ERR_INVALID_ARG;
+    if (flops) *flops = b->b.plan.flops;
+    if (bytes) *bytes = b->b.plan.bytes;
     return QED_OK;
 }
 

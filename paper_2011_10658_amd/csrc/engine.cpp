@@ -191,6 +191,19 @@ int64_t key3(int a, int b, int c) { return ((int64_t)a * 4096 + b) * 4096 + c; }
 
 }  // namespace
 
+static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, int sh) {
+    const int TM = gemm_tm(sh), TN = gemm_tn(sh);
+    std::vector<GTile> tiles;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const GJob& J = jobs[j];
+        const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
+        for (int b = 0; b < J.batch; ++b)
+            for (int a = 0; a < tm; ++a)
+                for (int c = 0; c < tn; ++c) tiles.push_back(GTile{(int)j, b, a, c});
+    }
+    return tiles;
+}
+
 void Plan::upload(Dev* dev) {
     dj.clear();
     dp.clear();
@@ -211,15 +224,7 @@ void Plan::upload(Dev* dev) {
                 best = sh;
             }
         }
-        const int TM = gemm_tm(best), TN = gemm_tn(best);
-        std::vector<GTile> tiles;
-        for (size_t j = 0; j < jobs[s].size(); ++j) {
-            const GJob& J = jobs[s][j];
-            const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
-            for (int b = 0; b < J.batch; ++b)
-                for (int a = 0; a < tm; ++a)
-                    for (int c = 0; c < tn; ++c) tiles.push_back(GTile{(int)j, b, a, c});
-        }
+        std::vector<GTile> tiles = make_tiles(jobs[s], best);
         auto bj = std::make_shared<DBuf>(dev, jobs[s].size() * sizeof(GJob));
         auto bp = std::make_shared<DBuf>(dev, std::max<size_t>(1, prods[s].size()) * sizeof(GProd));
         auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
@@ -237,6 +242,31 @@ void Plan::upload(Dev* dev) {
         shape.push_back(best);
     }
     dev->sync();  // host vectors of this plan may change afterwards
+}
+
+void Plan::set_shape(Dev* dev, int s, int sh) {
+    if (shape[s] == sh) return;
+    std::vector<GTile> tiles = make_tiles(jobs[s], sh);
+    auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
+    dev->upload(bt->p, tiles.data(), tiles.size() * sizeof(GTile));
+    dt[s] = bt;
+    ntiles[s] = (int)tiles.size();
+    shape[s] = sh;
+}
+
+void Plan::run_stage(Dev* dev, int s, void* ws, void* x, void* y) {
+    Bases b;
+    b.b[TAG_ABS] = nullptr;
+    b.b[TAG_WS] = ws;
+    b.b[TAG_X] = x;
+    b.b[TAG_Y] = y;
+    if (!ntiles[s]) return;
+    if (dtype == QED_FP64)
+        launch_brgemm<double>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(), ntiles[s],
+                              b, shape[s], dev->stream);
+    else
+        launch_brgemm<float>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(), ntiles[s],
+                             b, shape[s], dev->stream);
 }
 
 void Prof::record_begin(hipStream_t s, hipEvent_t& a) {
@@ -296,10 +326,8 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
     dev->check(hipGetLastError(), "brgemm launch");
 }
 
-Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
-                 int dtype) {
-    Plan P;
-    P.dtype = dtype;
+void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
+                   const std::vector<HTerm>& terms, int64_t xoff) {
     Builder B(P);
     B.stage(2);
     std::map<int64_t, int> bidx;
@@ -309,7 +337,7 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
         if (t.coef == 0.0) continue;
         for (int b = 0; b < tab.nblk(); ++b) {
             BV cur;
-            cur.p = gtag(TAG_X, tab.off[b]);
+            cur.p = gtag(TAG_X, xoff + tab.off[b]);
             for (int e = 0; e < 3; ++e) {
                 cur.s[e] = tab.s[e][b];
                 cur.n[e] = legs[e].n[cur.s[e]];
@@ -338,7 +366,7 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
             GProd p{};
             if (t.op[0]) {
                 const int nout = legs[0].n[os[0]];
-                GRef opblk = gabs((const char*)t.op[0]->data(dtype) +
+                GRef opblk = gabs((const char*)t.op[0]->data(P.dtype) +
                                   t.op[0]->lay.off[cur.s[0]] * B.esize);
                 int M, N, ldc, batch;
                 int64_t bsC;
@@ -356,7 +384,7 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
     }
     for (int b = 0; b < tab.nblk(); ++b) {
         GJob j{};
-        j.C = gtag(TAG_Y, tab.off[b]);
+        j.C = gtag(TAG_Y, xoff + tab.off[b]);
         const int n0 = legs[0].n[tab.s[0][b]], n1 = legs[1].n[tab.s[1][b]],
                   n2 = legs[2].n[tab.s[2][b]];
         j.M = n0;
@@ -371,10 +399,17 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
     }
     // algorithmic bytes: x, y and the operator blocks in the GEMM dtype
     const double es = B.esize;
-    P.bytes = 2.0 * tab.size() * es;
+    P.bytes += 2.0 * tab.size() * es;
     for (const HTerm& t : terms)
         for (int e = 0; e < 3; ++e)
             if (t.op[e] && t.coef != 0.0) P.bytes += t.op[e]->lay.size * es;
+}
+
+Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
+                 int dtype) {
+    Plan P;
+    P.dtype = dtype;
+    append_matvec(P, legs, tab, terms, 0);
     return P;
 }
 

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <functional>
 #include <map>
 #include <memory>
@@ -45,6 +46,23 @@ void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_
 void launch_qr(const QRMat*, int, int, double*, double*, double*, hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
+
+void seg_dots(const double*, int64_t, int, const double*, const SegChunk*, int, const int*, int,
+              double*, double*, int, int, const LState*, int, hipStream_t);
+void seg_init(LState*, int, int, const double*, int, hipStream_t);
+void seg_start(double*, const double*, const double*, int, const SegChunk*, int, hipStream_t);
+void seg_three_term(double*, const double*, int64_t, int, const double*, const double*, int,
+                    const SegChunk*, int, const LState*, hipStream_t);
+void seg_subtract(double*, const double*, int64_t, int, const double*, int, const SegChunk*, int,
+                  const LState*, hipStream_t);
+void seg_beta(const double*, int, double*, double*, int, int, LState*, int, double, hipStream_t);
+void seg_next(double*, int64_t, int, const double*, const double*, int, const SegChunk*, int,
+              const LState*, hipStream_t);
+void seg_tridiag(const double*, const double*, int, double*, LState*, double*, int, hipStream_t);
+void seg_ritz(double*, const double*, int64_t, const double*, int, const SegChunk*, int,
+              const LState*, hipStream_t);
+void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const double*, int,
+                        double*, int64_t*, double*, hipStream_t);
 
 // ---- device memory ---------------------------------------------------
 struct Dev {
@@ -139,6 +157,8 @@ struct Plan {
     std::vector<int> shape;   // workgroup tile shape per stage
     void upload(Dev* dev);
     void run(Dev* dev, void* ws, void* x, void* y);
+    void run_stage(Dev* dev, int s, void* ws, void* x, void* y);
+    void set_shape(Dev* dev, int s, int sh);   // re-tile one stage
 };
 
 struct HTerm {
@@ -149,6 +169,10 @@ struct HTerm {
 // y = sum_k coef_k A_k (x) B_k (x) C_k  x on the canonical layout.
 Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
                  int dtype);
+// Append the jobs of one node's H_eff to P, with x and y at element offset
+// xoff of the bound vectors (batched plans concatenate nodes).
+void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
+                   const std::vector<HTerm>& terms, int64_t xoff);
 
 // Renormalised operators n^T (A (x) B) n on leg `which` of node tensor n.
 struct RTerm {
@@ -262,9 +286,53 @@ struct Engine {
     double update(int n, double nu);
 };
 
+// ---- segmented Lanczos: independent recurrences on segments of one
+// concatenated vector (batched node updates) ------------------------------
+struct SegLanczos {
+    static constexpr int LDS = 72;   // per-segment scalar stride
+    static constexpr int LDN = 8;    // per-segment norm slots
+    int nseg = 0, nch = 0, m = 0;
+    int64_t N = 0;
+    BufP chunks, seg_c0, V, w, alpha, beta, coef, sv, work, st, partial, pv, pi, nrm, fac;
+    void setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t N, int m);
+    // enqueue one cycle on `s` (no host synchronisation: capturable)
+    void cycle(const std::function<void(const double*, double*)>& apply, double* x, hipStream_t s);
+};
+
+// ---- autotuner of the GEMM tile shape per plan stage --------------------
+struct Tuner {
+    bool on = false;
+    std::string path;
+    std::map<std::string, int> cache;
+    void load();
+    void save() const;
+    void tune(Dev* dev, Plan& P, void* ws, void* x, void* y);
+};
+
+// ---- batched node-level H_eff -------------------------------------------
+struct HeffBatch {
+    Ctx* ctx = nullptr;
+    int nn = 0;
+    std::vector<std::array<Leg, 3>> legs;
+    std::vector<BlockTable> tabs;
+    std::vector<int64_t> off;      // nn + 1 offsets into the concatenated vector
+    std::vector<std::vector<HTerm>> terms;
+    Plan plan;
+    BufP ws, xc, yc;
+    SegLanczos lz;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    double* gx = nullptr;
+    int gm = 0;
+    void matvec(const double* x, double* y, hipStream_t s);
+    ~HeffBatch();
+};
+
 struct Ctx {
     Dev dev;
     Prof prof;
+    Tuner tuner;
     double mv_flops = 0.0;
     long long mv_count = 0;
     bool host_only = true;

@@ -73,6 +73,13 @@ struct QRMat {
     int rows, cols;
 };
 
+// A chunk of a segmented vector (never straddles a segment boundary).
+struct SegChunk {
+    int seg;
+    int pad;
+    int64_t lo, hi;
+};
+
 // Lanczos state living on the device.
 struct LState {
     int k;             // number of valid steps (== m unless broken down)

@@ -50,6 +50,11 @@ class Term(C.Structure):
     _fields_ = [("coef", C.c_double), ("op", C.c_void_p * 3), ("shift", C.c_int * 3)]
 
 
+class HeffDesc(C.Structure):
+    _fields_ = [("ch", C.POINTER(C.c_int) * 3), ("n", C.POINTER(C.c_int) * 3),
+                ("nsec", C.c_int * 3), ("K", C.c_int), ("terms", C.POINTER(Term))]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
@@ -88,6 +93,13 @@ SIGNATURES = {
     "qed_sweep": [_P, _I, C.POINTER(SweepReport)],
     "qed_get_energy": [_P, _DP],
     "qed_get_observables": [_P, _DP, _DP, _DP, _DP, _DP],
+    "qed_heff_batch_create": [_P, _I, C.POINTER(HeffDesc), C.POINTER(_P)],
+    "qed_heff_batch_destroy": [_P],
+    "qed_heff_batch_size": [_P, _LP, _LP],
+    "qed_heff_batch_matvec": [_P, _P, _P],
+    "qed_heff_batch_lanczos": [_P, _P, _I, _DP, _DP, _I],
+    "qed_heff_batch_flops": [_P, _DP, _DP],
+    "qed_autotune": [_P, C.c_char_p],
     "qed_set_profiling": [_P, _I],
     "qed_get_stats": [_P, C.POINTER(Stats)],
     "qed_node_blocks": [_IP, _IP, _I, _IP, _IP, _I, _IP, _IP, _I, _I, _I, _IP, _IP, _LP],
@@ -294,6 +306,16 @@ class Context:
         self._c(self.lib.qed_get_stats(self.h, C.byref(st)))
         return st.as_dict()
 
+    def autotune(self, cache_path=None):
+        """Enable the tile-shape autotuner (None: in-memory cache only;
+        "": disable)."""
+        arg = None if cache_path is None else cache_path.encode()
+        self._c(self.lib.qed_autotune(self.h, arg))
+
+    def heff_batch(self, nodes):
+        """nodes: [((l, r, p), terms)] with terms as in heff()."""
+        return HeffBatch(self, nodes)
+
     def heff(self, l, r, p, terms):
         """terms: [(coef, (ptr_l, ptr_r, ptr_p), (shift_l, shift_r, shift_p))]
         with device FP64 operator pointers (0 / None = identity)."""
@@ -345,4 +367,66 @@ class Heff:
     def flops(self):
         f, b = C.c_double(), C.c_double()
         _check(self.ctx.lib.qed_heff_flops(self.h, C.byref(f), C.byref(b)))
+        return f.value, b.value
+
+
+class HeffBatch:
+    def __init__(self, ctx, nodes):
+        self.ctx = ctx
+        lib = ctx.lib
+        self._keep = []
+        descs = (HeffDesc * len(nodes))()
+        for i, (legs, terms) in enumerate(nodes):
+            for e in range(3):
+                q = _ia([c for c, _ in legs[e]])
+                n = _ia([s for _, s in legs[e]])
+                self._keep += [q, n]
+                descs[i].ch[e] = C.cast(q, C.POINTER(C.c_int))
+                descs[i].n[e] = C.cast(n, C.POINTER(C.c_int))
+                descs[i].nsec[e] = len(legs[e])
+            arr = (Term * max(1, len(terms)))()
+            for k, (c, ptrs, shifts) in enumerate(terms):
+                arr[k].coef = c
+                for e in range(3):
+                    arr[k].op[e] = ptrs[e] or None
+                    arr[k].shift[e] = shifts[e]
+            self._keep.append(arr)
+            descs[i].K = len(terms)
+            descs[i].terms = C.cast(arr, C.POINTER(Term))
+        h = C.c_void_p()
+        ctx._c(lib.qed_heff_batch_create(ctx.h, len(nodes), descs, C.byref(h)))
+        self.h = h
+        self.nn = len(nodes)
+        ctx._children.add(self)
+        tot = C.c_int64()
+        offs = (C.c_int64 * (self.nn + 1))()
+        _check(lib.qed_heff_batch_size(h, C.byref(tot), offs))
+        self.size = tot.value
+        self.offsets = np.array(offs[:], dtype=np.int64)
+
+    def close(self):
+        if self.h and self.ctx.h:
+            self.ctx.lib.qed_heff_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matvec(self, x_ptr, y_ptr):
+        self.ctx._c(self.ctx.lib.qed_heff_batch_matvec(self.h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)))
+
+    def lanczos(self, x_ptr, steps=0, graph=True):
+        ev = np.zeros(self.nn)
+        res = np.zeros(self.nn)
+        rc = self.ctx._c(self.ctx.lib.qed_heff_batch_lanczos(
+            self.h, C.c_void_p(x_ptr), steps, ev.ctypes.data_as(_DP), res.ctypes.data_as(_DP),
+            1 if graph else 0), ok=(OK, NOT_CONVERGED))
+        return ev, res, rc
+
+    def flops(self):
+        f, b = C.c_double(), C.c_double()
+        _check(self.ctx.lib.qed_heff_batch_flops(self.h, C.byref(f), C.byref(b)))
         return f.value, b.value

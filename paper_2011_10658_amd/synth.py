@@ -97,11 +97,16 @@ def single_node_terms(seed, K, leg, streams_from=100):
 
 def random_composition(seed, stream, chi, S):
     """Sizes of S sectors summing to chi: S-1 distinct cut points drawn
-    uniformly from 1..chi-1 (by rejection in draw order)."""
+    uniformly from 1..chi-1 (by rejection in draw order).  S <= chi."""
+    if not 1 <= S <= chi:
+        raise ValueError("need 1 <= S <= chi")
     cuts = []
+    draws = integers(seed, stream, 64 * S + 64, 1, max(1, chi - 1))
     i = 0
     while len(cuts) < S - 1:
-        c = int(integers(seed, stream, i + 1, 1, chi - 1)[i])
+        if i == len(draws):
+            draws = integers(seed, stream, 2 * len(draws), 1, max(1, chi - 1))
+        c = int(draws[i])
         i += 1
         if c not in cuts:
             cuts.append(c)
@@ -112,7 +117,32 @@ def random_composition(seed, stream, chi, S):
 
 def batched_leg(seed, stream, chis=(32, 48, 64, 96, 128), smin=3, smax=9):
     chi = chis[int(integers(seed, stream, 1, 0, len(chis) - 1)[0])]
-    S = int(integers(seed, stream + 1, 1, smin, smax)[0])
+    S = min(chi, int(integers(seed, stream + 1, 1, smin, smax)[0]))
     sizes = random_composition(seed, stream + 2, chi, S)
     q0 = -((S - 1) // 2)
     return [(q0 + i, sizes[i]) for i in range(S)]
+
+
+def batched_nodes(seed, nnodes, chis=(32, 48, 64, 96, 128), kmin=12, kmax=24,
+                  allowed=None):
+    """Independent nodes of the batched workload: per leg chi ~ U(chis),
+    S ~ U{3..9} sectors (charges q0 .. q0+S-1, q0 = -floor((S-1)/2)) with a
+    random composition of chi; K ~ U{kmin..kmax} terms, each factor a
+    symmetric sector-preserving operator, coefficient 1.  A node whose legs
+    admit no block (checked by the caller-supplied `allowed(legs)`) is
+    redrawn from the next stream."""
+    out = []
+    stream = 0
+    while len(out) < nnodes:
+        base = 100000 + 1000 * stream
+        legs = [batched_leg(seed, base + 10 * e, chis) for e in range(3)]
+        stream += 1
+        if allowed is not None and not allowed(legs):
+            continue
+        K = int(integers(seed, base + 50, 1, kmin, kmax)[0])
+        terms = []
+        for k in range(K):
+            ops = [symmetric_sector_op(seed, base + 100 + 3 * k + e, legs[e]) for e in range(3)]
+            terms.append((1.0, ops[0], ops[1], ops[2]))
+        out.append((legs, terms))
+    return out

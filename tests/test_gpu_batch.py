@@ -1,0 +1,191 @@
+"""GPU parity of the batched node updates: many independent nodes in one
+grouped GEMM launch per stage and one segmented Lanczos, against the
+oracle node by node."""
+
+import numpy as np
+import pytest
+
+from oracle import blocks as oblocks
+from oracle import heff as oheff
+from oracle import lanczos as olanczos
+from paper_2011_10658_amd import lib, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def has_blocks(legs):
+    return len(oblocks.block_table(*legs)[0]) > 0
+
+
+def upload(nodes):
+    """[(legs, terms)] -> batch spec with device operators, oracle terms."""
+    keep, spec, dterms = [], [], []
+    for legs, terms in nodes:
+        ts, ds = [], []
+        for c, a, b, cc in terms:
+            ptrs = []
+            for e, o in enumerate((a, b, cc)):
+                t = dev(np.concatenate([o[q].reshape(-1) for q, _ in legs[e]]))
+                keep.append(t)
+                ptrs.append(t.data_ptr())
+            ts.append((c, tuple(ptrs), (0, 0, 0)))
+            ds.append((c, *(oblocks.op_to_dense(o, legs[e], 0) for e, o in enumerate((a, b, cc)))))
+        spec.append((tuple(legs), ts))
+        dterms.append(ds)
+    return spec, dterms, keep
+
+
+SMALL = synth.batched_nodes(21, 9, chis=(8, 12, 16, 20), kmin=3, kmax=6, allowed=has_blocks)
+
+
+@pytest.mark.parametrize("dtype,tol", [(lib.FP64, 1e-13), (lib.FP32, 3e-6)])
+def test_batch_matvec_each_node(ctx, dtype, tol):
+    ctx.set_precision(dtype)
+    spec, dterms, keep = upload(SMALL)
+    b = ctx.heff_batch(spec)
+    sizes = np.diff(b.offsets)
+    for i, (legs, _) in enumerate(SMALL):
+        assert sizes[i] == oblocks.block_table(*legs)[1][-1]
+    x = synth.normal(21, 1, b.size)
+    xd, yd = dev(x), torch.full((b.size,), np.nan, dtype=torch.float64, device="cuda")
+    b.matvec(xd.data_ptr(), yd.data_ptr())
+    y = yd.cpu().numpy()
+    for i, (legs, _) in enumerate(SMALL):
+        s0, s1 = b.offsets[i], b.offsets[i + 1]
+        yo = oheff.apply_flat(x[s0:s1], tuple(legs), dterms[i])
+        assert np.abs(y[s0:s1] - yo).max() <= tol * np.abs(yo).max(), i
+    f, _ = b.flops()
+    metas_total = sum(oheff.flops(tuple(legs), [(True, 0, True, 0, True, 0)] * len(t))
+                      for legs, t in SMALL)
+    assert f == metas_total
+    b.close()
+    ctx.set_precision(lib.FP64)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_lanczos_each_node(ctx, graph):
+    ctx.set_precision(lib.FP64)
+    ctx.set_lanczos(10, 1, 0.0)
+    spec, dterms, keep = upload(SMALL)
+    b = ctx.heff_batch(spec)
+    x0 = synth.normal(21, 2, b.size)
+    xd = dev(x0)
+    ev, res, rc = b.lanczos(xd.data_ptr(), 10, graph=graph)
+    u = xd.cpu().numpy()
+    for i, (legs, _) in enumerate(SMALL):
+        s0, s1 = b.offsets[i], b.offsets[i + 1]
+        th, uo, ro, _, _ = olanczos.lanczos_cycle(
+            lambda v: oheff.apply_flat(v, tuple(legs), dterms[i]), x0[s0:s1], 10)
+        assert abs(ev[i] - th) <= 1e-11 * abs(th), i
+        assert abs(res[i] - ro) <= 1e-8 * abs(th)
+        assert np.abs(u[s0:s1] - uo).max() < 1e-8
+    # a second call replays the captured graph from the new start vector
+    ev2, _, _ = b.lanczos(xd.data_ptr(), 10, graph=graph)
+    assert np.all(ev2 <= ev + 1e-10 * np.abs(ev))
+    b.close()
+
+
+def test_batch_restarts_until_converged(ctx):
+    ctx.set_precision(lib.FP64)
+    ctx.set_lanczos(32, 12, 1e-9)
+    spec, dterms, keep = upload(SMALL)
+    b = ctx.heff_batch(spec)
+    xd = dev(synth.normal(21, 3, b.size))
+    ev, res, rc = b.lanczos(xd.data_ptr(), 32, graph=True)
+    assert rc == 0
+    for i, (legs, _) in enumerate(SMALL):
+        lam = np.linalg.eigvalsh(oheff.matrix(tuple(legs), dterms[i]))[0]
+        assert abs(ev[i] - lam) <= 1e-8 * abs(lam), i
+        assert res[i] <= 1e-9 * abs(ev[i])
+    b.close()
+    ctx.set_lanczos(30, 1, 0.0)
+
+
+def test_autotuner_keeps_results(ctx, tmp_path):
+    ctx.set_precision(lib.FP32)
+    cache = str(tmp_path / "tiles.txt")
+    spec, dterms, keep = upload(SMALL)
+    ref = ctx.heff_batch(spec)
+    x = synth.normal(21, 4, ref.size)
+    xd = dev(x)
+    y0 = torch.zeros_like(xd)
+    ref.matvec(xd.data_ptr(), y0.data_ptr())
+    ref.close()
+    ctx.autotune(cache)
+    b = ctx.heff_batch(spec)
+    y1 = torch.zeros_like(xd)
+    b.matvec(xd.data_ptr(), y1.data_ptr())
+    ctx.autotune("")
+    # a different tile shape changes nothing but the tiling: same values
+    assert torch.equal(y0, y1)
+    assert len(open(cache).read().split()) >= 2
+    b.close()
+    ctx.set_precision(lib.FP64)
+
+
+def test_full_size_batch_sampled(ctx):
+    """The 512-node workload (chi in {32..128}, 3-9 sectors, 12-24 terms,
+    FP32 GEMMs): one graph-captured Lanczos cycle, checked node by node
+    on the sampled small nodes against the oracle and on all nodes by the
+    FP64 residual of the returned Ritz pairs."""
+    nodes = synth.batched_nodes(3, 512, allowed=has_blocks)
+    ctx.set_precision(lib.FP32)
+    ctx.set_lanczos(24, 1, 0.0)
+    keep, spec = [], []
+    for legs, terms in nodes:
+        ts = []
+        for c, a, bb, cc in terms:
+            ptrs = []
+            for e, o in enumerate((a, bb, cc)):
+                t = dev(np.concatenate([o[q].reshape(-1) for q, _ in legs[e]]))
+                keep.append(t)
+                ptrs.append(t.data_ptr())
+            ts.append((c, tuple(ptrs), (0, 0, 0)))
+        spec.append((tuple(legs), ts))
+    b = ctx.heff_batch(spec)
+    assert b.nn == 512
+    x0 = synth.normal(3, 9, b.size)
+    xd = dev(x0)
+    ev, res, rc = b.lanczos(xd.data_ptr(), 24, graph=True)
+    assert np.all(np.isfinite(ev))
+    u = xd.cpu().numpy()
+    # FP64 residuals of every Ritz pair (FP64 batched matvec of the same nodes)
+    ctx.set_precision(lib.FP64)
+    b64 = ctx.heff_batch(spec)
+    yd = torch.zeros_like(xd)
+    b64.matvec(xd.data_ptr(), yd.data_ptr())
+    y = yd.cpu().numpy()
+    for i in range(512):
+        s0, s1 = b.offsets[i], b.offsets[i + 1]
+        ui = u[s0:s1]
+        assert abs(np.linalg.norm(ui) - 1.0) < 1e-12
+        rq = ui @ y[s0:s1]
+        assert abs(rq - ev[i]) <= 1e-5 * max(1.0, abs(ev[i])), i
+    # sampled small nodes against the oracle's Lanczos from the same start
+    small = [i for i, (legs, _) in enumerate(nodes) if max(sum(n for _, n in g) for g in legs) <= 48][:3]
+    assert small
+    for i in small:
+        legs, terms = nodes[i]
+        d = [(c, *(oblocks.op_to_dense(o, legs[e], 0) for e, o in enumerate((a, bb, cc))))
+             for c, a, bb, cc in terms]
+        s0, s1 = b.offsets[i], b.offsets[i + 1]
+        th, _, _, _, _ = olanczos.lanczos_cycle(lambda v: oheff.apply_flat(v, tuple(legs), d),
+                                                 x0[s0:s1], 24)
+        assert abs(ev[i] - th) <= 1e-5 * abs(th), (i, ev[i], th)
+    b.close()
+    b64.close()
+    ctx.set_precision(lib.FP64)
