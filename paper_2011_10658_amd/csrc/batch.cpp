@@ -130,7 +130,7 @@ void Tuner::tune(Dev* dev, Plan& P, void* ws, void* x, void* y) {
         }
         int best = P.shape[s];
         float best_ms = -1.0f;
-        for (int sh : {GEMM_SHAPE_SQUARE, GEMM_SHAPE_TALL, GEMM_SHAPE_WIDE}) {
+        for (int sh = 0; sh < GEMM_NSHAPES; ++sh) {
             P.set_shape(dev, (int)s, sh);
             hipEvent_t a, b;
             dev->check(hipEventCreate(&a), "event");

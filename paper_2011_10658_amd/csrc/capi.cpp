@@ -653,7 +653,9 @@ int qed_heff_batch_matvec(qed_heff_batch* b, const double* x, double* y) {
     return guard(b->owner, [&] {
         if (!x || !y || x == y) fail(QED_ERR_INVALID_ARG, "x and y must be distinct device buffers");
         Dev& dev = b->b.ctx->dev;
+        b->b.plan.prof = &b->b.ctx->prof;
         b->b.matvec(x, y, dev.stream);
+        b->b.plan.prof = nullptr;
         dev.check(hipGetLastError(), "batch matvec");
         Ctx& c = *b->b.ctx;
         c.mv_flops += b->b.plan.flops;

@@ -130,6 +130,11 @@ struct Builder {
         GJob j{};
         j.C = C;
         j.bsC = bsC;
+        if (p.nsb) {   // split output columns like the input (mode on r)
+            j.nsc = p.nsb;
+            j.noc = bsC;
+            j.bsC = 0;
+        }
         j.M = M;
         j.N = N;
         j.ldc = ldc;
@@ -154,10 +159,12 @@ struct Builder {
             p.K = n2;
             M = n0 * n1; N = nout; ldc = nout; batch = 1; bsC = 0;
         } else if (e == 1) {
-            p.A = opblk; p.lda = n1; p.tA = 0; p.bsA = 0;
-            p.B = in.p; p.ldb = n2; p.tB = 0; p.bsB = (int64_t)n1 * n2;
+            // n0 matrices (n1 x n2) side by side: one GEMM over N = n0 n2
+            p.A = opblk; p.lda = n1; p.tA = 0;
+            p.B = in.p; p.ldb = n2; p.tB = 0;
+            p.nsb = n2; p.nob = (int64_t)n1 * n2;
             p.K = n1;
-            M = nout; N = n2; ldc = n2; batch = n0; bsC = (int64_t)nout * n2;
+            M = nout; N = n0 * n2; ldc = n2; batch = 1; bsC = (int64_t)nout * n2;
         } else {
             p.A = opblk; p.lda = n0; p.tA = 0;
             p.B = in.p; p.ldb = n1 * n2; p.tB = 0;
@@ -214,7 +221,7 @@ void Plan::upload(Dev* dev) {
         // the tile shape that pads the stage's jobs least
         int best = GEMM_SHAPE_SQUARE;
         double best_area = -1.0;
-        for (int sh : {GEMM_SHAPE_SQUARE, GEMM_SHAPE_TALL, GEMM_SHAPE_WIDE}) {
+        for (int sh = 0; sh < GEMM_NSHAPES; ++sh) {
             const int TM = gemm_tm(sh), TN = gemm_tn(sh);
             double area = 0.0;
             for (const GJob& J : jobs[s])

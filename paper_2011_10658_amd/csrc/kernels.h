@@ -25,19 +25,23 @@ struct Bases {
 // op(A) M x K, op(B) K x N.  tA = 1: op(A)[m][k] = A[k * lda + m];
 // tB = 1: op(B)[k][n] = B[n * ldb + k].  ident = 1: A is the identity and
 // op(B) (M x N, tB = 0) is added.  bsA/bsB: strides between batch items.
+// nsb > 0 splits the column index of op(B) (tB = 0 only): column n lives
+// at (n / nsb) * nob + (n % nsb) instead of n (a batch of matrices side by
+// side read as one wide matrix).
 struct GProd {
     GRef A, B;
-    int64_t rsA, rsB, bsA, bsB;
+    int64_t rsA, rsB, bsA, bsB, nob;
     double alpha;
-    int K, lda, ldb, tA, tB, nred, ident, pad;
+    int K, lda, ldb, tA, tB, nred, ident, nsb;
 };
 
 // Output C (M x N, row-major, ldc) of `batch` items (stride bsC), the sum
 // of products [p0, p1); acc = 1 adds into C, 0 overwrites.
+// nsc > 0 splits the output column index the same way (stride noc).
 struct GJob {
     GRef C;
-    int64_t bsC;
-    int M, N, ldc, batch, p0, p1, acc, pad;
+    int64_t bsC, noc;
+    int M, N, ldc, batch, p0, p1, acc, nsc;
 };
 
 // Work item of one workgroup: tile (tm, tn) of batch item b of job j.
@@ -46,9 +50,20 @@ struct GTile {
 };
 
 // Workgroup tile shapes of the block GEMM (rows x cols of the output).
-enum { GEMM_SHAPE_SQUARE = 0, GEMM_SHAPE_TALL = 1, GEMM_SHAPE_WIDE = 2 };
-inline int gemm_tm(int shape) { return shape == GEMM_SHAPE_TALL ? 128 : shape == GEMM_SHAPE_WIDE ? 32 : 64; }
-inline int gemm_tn(int shape) { return shape == GEMM_SHAPE_TALL ? 32 : shape == GEMM_SHAPE_WIDE ? 128 : 64; }
+enum {
+    GEMM_SHAPE_SQUARE = 0,   //  64 x  64
+    GEMM_SHAPE_TALL = 1,     // 128 x  32
+    GEMM_SHAPE_WIDE = 2,     //  32 x 128
+    GEMM_NSHAPES = 3
+};
+inline int gemm_tm(int s) {
+    const int t[GEMM_NSHAPES] = {64, 128, 32};
+    return t[s];
+}
+inline int gemm_tn(int s) {
+    const int t[GEMM_NSHAPES] = {64, 32, 128};
+    return t[s];
+}
 constexpr int GEMM_THREADS = 256;
 
 // Per-block description for packing a node tensor into the column-major

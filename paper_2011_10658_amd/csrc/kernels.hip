@@ -46,19 +46,19 @@ __device__ __forceinline__ T* resolve(const GRef& r, const Bases& bs) {
 // ---------------------------------------------------------------------
 // grouped batch-reduce GEMM
 // ---------------------------------------------------------------------
-// Workgroup tile (32 WM) x (32 WN) on 4 waves in a WM x WN grid; every wave
-// owns a 32 x 32 sub-tile = 2 x 2 MFMA 16x16 blocks.  K advances in chunks
-// of KC staged k-major in LDS (As[k][m], Bs[k][n]: the MFMA operand reads
-// of a wave hit 16 consecutive words); the next chunk is fetched into
+// Workgroup tile (16 WM BM) x (16 WN BN) on 4 waves in a WM x WN grid;
+// every wave owns BM x BN MFMA 16x16 blocks.  K advances in chunks of KC
+// staged k-major in LDS (As[k][m], Bs[k][n]: the MFMA operand reads of a
+// wave hit 16 consecutive words); the next chunk is fetched into
 // registers while the current one is multiplied.
 constexpr int KC = 16;
 
-template <typename T, int WM, int WN>
+template <typename T, int WM, int WN, int BM, int BN>
 __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
                                                 const GProd* __restrict__ prods,
                                                 const GTile* __restrict__ tiles, Bases bases) {
     typedef typename Mfma<T>::v4 v4;
-    constexpr int TM = 32 * WM, TN = 32 * WN;
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
     constexpr int PAD = 4;
     constexpr int AE = TM * KC / 256;   // A elements per thread per chunk
     constexpr int BE = TN * KC / 256;
@@ -69,38 +69,48 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm0 = (wave / WN) * 32;
-    const int wn0 = (wave % WN) * 32;
+    const int wm0 = (wave / WN) * 16 * BM;
+    const int wn0 = (wave % WN) * 16 * BN;
     const int m0 = tl.tm * TM;
     const int n0 = tl.tn * TN;
     const int lr = lane & 15, lk = lane >> 4;
-    v4 acc[2][2];
+    v4 acc[BM][BN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
+        for (int j = 0; j < BN; ++j) acc[i][j] = v4{0, 0, 0, 0};
     T ra[AE], rb[BE];
+    int bcol[BE];       // column offsets of this thread's B elements (tB = 0)
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
         const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
         const T alpha = (T)P.alpha;
         if (P.ident) {
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
+                for (int bj = 0; bj < BN; ++bj) {
                     const int col = n0 + wn0 + bj * 16 + lr;
+                    const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
                         if (row < J.M && col < J.N)
-                            acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + col];
+                            acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + co];
                     }
                 }
             continue;
         }
         const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
         const int nchunk = (P.K + KC - 1) / KC;
+        if (!P.tB) {
+#pragma unroll
+            for (int e = 0; e < BE; ++e) {
+                const int n = (tid + e * 256) % TN;
+                const int gn = n0 + n;
+                bcol[e] = P.nsb ? (int)((gn / P.nsb) * P.nob + gn % P.nsb) : gn;
+            }
+        }
         for (int r = 0; r < P.nred; ++r) {
             const T* A = Ab + (int64_t)r * P.rsA;
             const T* B = Bb + (int64_t)r * P.rsB;
@@ -126,7 +136,7 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
                     const int gn = n0 + n, gk = k0 + k;
                     T v = (T)0;
                     if (gn < J.N && gk < P.K)
-                        v = P.tB ? B[(int64_t)gn * P.ldb + gk] : B[(int64_t)gk * P.ldb + gn];
+                        v = P.tB ? B[(int64_t)gn * P.ldb + gk] : B[(int64_t)gk * P.ldb + bcol[e]];
                     rb[e] = v;
                 }
             };
@@ -156,29 +166,31 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
                 if (c + 1 < nchunk) fetch((c + 1) * KC);
 #pragma unroll
                 for (int kk = 0; kk < KC; kk += 4) {
-                    const T a0 = As[kk + lk][wm0 + lr];
-                    const T a1 = As[kk + lk][wm0 + 16 + lr];
-                    const T b0 = Bs[kk + lk][wn0 + lr];
-                    const T b1 = Bs[kk + lk][wn0 + 16 + lr];
-                    acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
-                    acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
-                    acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
-                    acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
+                    T a[BM], bb[BN];
+#pragma unroll
+                    for (int i = 0; i < BM; ++i) a[i] = As[kk + lk][wm0 + i * 16 + lr];
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) bb[j] = Bs[kk + lk][wn0 + j * 16 + lr];
+#pragma unroll
+                    for (int i = 0; i < BM; ++i)
+#pragma unroll
+                        for (int j = 0; j < BN; ++j) acc[i][j] = Mfma<T>::step(a[i], bb[j], acc[i][j]);
                 }
             }
         }
     }
     T* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
+        for (int bj = 0; bj < BN; ++bj) {
             const int col = n0 + wn0 + bj * 16 + lr;
+            const int64_t co = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
                 if (row < J.M && col < J.N) {
-                    T* c = C + (int64_t)row * J.ldc + col;
+                    T* c = C + (int64_t)row * J.ldc + co;
                     *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
                 }
             }
@@ -189,12 +201,16 @@ template <typename T>
 void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
                    const Bases& bases, int shape, hipStream_t st) {
     if (ntiles <= 0) return;
-    if (shape == GEMM_SHAPE_TALL)
-        hipLaunchKernelGGL((k_brgemm<T, 4, 1>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
-    else if (shape == GEMM_SHAPE_WIDE)
-        hipLaunchKernelGGL((k_brgemm<T, 1, 4>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
-    else
-        hipLaunchKernelGGL((k_brgemm<T, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+    switch (shape) {
+        case GEMM_SHAPE_TALL:
+            hipLaunchKernelGGL((k_brgemm<T, 4, 1, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+            break;
+        case GEMM_SHAPE_WIDE:
+            hipLaunchKernelGGL((k_brgemm<T, 1, 4, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+            break;
+        default:
+            hipLaunchKernelGGL((k_brgemm<T, 2, 2, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+    }
 }
 
 template void launch_brgemm<double>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
