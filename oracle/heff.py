@@ -8,7 +8,10 @@ U(1) shift delta, delta_A + delta_B = delta_C.
 
 `apply_dense` is the plain definition: embed the node tensor densely and
 contract  y_ijk = sum_k c_k A_ia B_jb C_kc x_abc  (einsum).  `matrix`
-builds the explicit |x| x |x| operator for tiny nodes.  A term is
+builds the explicit |x| x |x| operator for tiny nodes.  `adjoint_dense`
+is the reverse-mode derivative of <ybar, y> with respect to x, every
+factor and every coefficient (the derivative of the energy with respect
+to the node tensor and to the couplings, by the chain rule).  A term is
 (c, A, B, C) with dense chi x chi matrices or None for the identity.
 """
 
@@ -100,3 +103,49 @@ def flops(legs, metas):
             if hasA:
                 total += 2 * na * na2 * nb2 * nc2
     return total
+
+
+def adjoint_dense(xd, ybd, terms):
+    """Reverse mode of y = apply_dense(x, terms) for the scalar <ybar, y>.
+
+    Since y is linear in x, in every factor and in every coefficient, the
+    derivatives follow from the definition term by term:
+      xbar           = sum_k c_k (A_k^T x_l B_k^T x_r C_k^T x_p ybar)
+      Abar_k[i, a]   = c_k sum_{j,k'} ybar[i,j,k'] (B_k x_r C_k x_p x)[a,j,k']
+      Bbar_k[j, b]   = c_k sum_{i,k'} ybar[i,j,k'] (A_k x_l C_k x_p x)[i,b,k']
+      Cbar_k[k', c]  = c_k sum_{i,j}  ybar[i,j,k'] (A_k x_l B_k x_r x)[i,j,c]
+      cbar_k         = <ybar, A_k x_l B_k x_r C_k x_p x>
+    Identity factors have no gradient (None).  Returns
+    (xbar, [(Abar, Bbar, Cbar)], cbar) with dense arrays."""
+    xbar = np.zeros_like(xd)
+    grads, cbar = [], []
+    for c, A, B, C in terms:
+        t = ybd
+        if A is not None:
+            t = mode_l(A.T, t)
+        if B is not None:
+            t = mode_r(B.T, t)
+        if C is not None:
+            t = mode_p(C.T, t)
+        xbar += c * t
+
+        def part(skip):
+            u = xd
+            if A is not None and skip != 0:
+                u = mode_l(A, u)
+            if B is not None and skip != 1:
+                u = mode_r(B, u)
+            if C is not None and skip != 2:
+                u = mode_p(C, u)
+            return u
+
+        g = [None, None, None]
+        if A is not None:
+            g[0] = c * np.einsum("ijk,ajk->ia", ybd, part(0))
+        if B is not None:
+            g[1] = c * np.einsum("ijk,ibk->jb", ybd, part(1))
+        if C is not None:
+            g[2] = c * np.einsum("ijk,ijc->kc", ybd, part(2))
+        grads.append(tuple(g))
+        cbar.append(float(np.sum(ybd * part(-1))))
+    return xbar, grads, np.array(cbar)

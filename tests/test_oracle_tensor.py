@@ -114,6 +114,98 @@ def test_heff_shifted_factors_stay_in_blocks():
     assert y.shape == x.shape and np.abs(y).max() > 0
 
 
+def _shifted_terms(rng, leg):
+    """Non-symmetric factors with charge shifts (dA + dB = dC), identities
+    included, so that transposes and index orders all matter."""
+    sizes = dict(leg)
+
+    def op(delta):
+        blk = {q: rng.standard_normal((sizes[q + delta], n)) for q, n in leg if q + delta in sizes}
+        return blocks.op_to_dense(blk, leg, delta), delta
+
+    specs = [((1, 0, 1), 0.7), ((0, 0, 0), -1.3), ((None, -1, -1), 0.4), ((0, None, None), 2.0),
+             ((-1, 1, None), 0.9)]
+    terms, shifts = [], []
+    for sh, c in specs:
+        fs = [None if d is None else op(d)[0] for d in sh]
+        terms.append((c, *fs))
+        shifts.append(sh)
+    return terms, shifts
+
+
+def _adjoint_case(seed=2):
+    leg = [(-1, 2), (0, 3), (1, 2)]
+    legs = (leg, leg, leg)
+    rng = np.random.default_rng(seed)
+    terms, shifts = _shifted_terms(rng, leg)
+    mask = blocks.allowed_mask(*legs)
+    size = int(mask.sum())
+    x, yb = rng.standard_normal(size), rng.standard_normal(size)
+    return leg, legs, terms, shifts, x, yb
+
+
+def test_adjoint_x_is_the_transposed_matrix():
+    leg, legs, terms, _, x, yb = _adjoint_case()
+    H = heff.matrix(legs, terms)
+    assert np.abs(H - H.T).max() > 1e-3          # a genuinely non-symmetric case
+    xbar, _, _ = heff.adjoint_dense(blocks.to_dense(x, *legs), blocks.to_dense(yb, *legs), terms)
+    assert np.abs(blocks.from_dense(xbar, *legs) - H.T @ yb).max() < 1e-12
+
+
+def test_adjoint_factor_and_coefficient_grads_by_linearity():
+    """<ybar, y> is linear in each factor and coefficient, so the change
+    along a direction equals the directional derivative exactly."""
+    leg, legs, terms, shifts, x, yb = _adjoint_case(5)
+    xd, ybd = blocks.to_dense(x, *legs), blocks.to_dense(yb, *legs)
+    _, grads, cbar = heff.adjoint_dense(xd, ybd, terms)
+    f0 = float(np.sum(ybd * heff.apply_dense(xd, terms)))
+    rng = np.random.default_rng(9)
+    checked = 0
+    for k, (c, *fs) in enumerate(terms):
+        for e in range(3):
+            if fs[e] is None:
+                assert grads[k][e] is None
+                continue
+            d = shifts[k][e]
+            D = blocks.op_to_dense({q: rng.standard_normal(M.shape) for q, M in
+                                    blocks.op_from_dense(fs[e], leg, d).items()}, leg, d)
+            moved = list(terms)
+            nf = list(fs)
+            nf[e] = fs[e] + D
+            moved[k] = (c, *nf)
+            f1 = float(np.sum(ybd * heff.apply_dense(xd, moved)))
+            assert abs((f1 - f0) - np.sum(grads[k][e] * D)) < 1e-11 * max(1.0, abs(f1))
+            # the gradient lives on the factor's own charge-shift blocks
+            G = grads[k][e]
+            assert np.abs(G - blocks.op_to_dense(blocks.op_from_dense(G, leg, d), leg, d)).max() == 0
+            checked += 1
+        moved = list(terms)
+        moved[k] = (c + 1.0, *fs)
+        f1 = float(np.sum(ybd * heff.apply_dense(xd, moved)))
+        assert abs((f1 - f0) - cbar[k]) < 1e-11 * max(1.0, abs(f1))
+    assert checked == 11
+
+
+def test_adjoint_hellmann_feynman_on_lowest_eigenvalue():
+    """dE0/dc_k = <v|H_k|v> for the normalised ground state v of a
+    symmetric H_eff; the adjoint with x = ybar = v gives it, and central
+    differences of the dense eigenvalue agree to O(h^2)."""
+    legs = (C1, C1, C1)
+    terms = _dense_terms(synth.single_node_terms(4, 3, C1), C1)
+    H = heff.matrix(legs, terms)
+    w, V = np.linalg.eigh(H)
+    v = V[:, 0]
+    vd = blocks.to_dense(v, *legs)
+    _, _, cbar = heff.adjoint_dense(vd, vd, terms)
+    h = 1e-4
+    for k in range(3):
+        hi = [(c + (h if i == k else 0.0), *f) for i, (c, *f) in enumerate(terms)]
+        lo = [(c - (h if i == k else 0.0), *f) for i, (c, *f) in enumerate(terms)]
+        fd = (np.linalg.eigvalsh(heff.matrix(legs, hi))[0] -
+              np.linalg.eigvalsh(heff.matrix(legs, lo))[0]) / (2 * h)
+        assert abs(fd - cbar[k]) < 1e-6
+
+
 # -- Lanczos -------------------------------------------------------------
 def test_lanczos_interlacing_and_convergence():
     terms = synth.single_node_terms(1, 8, C1)
