@@ -266,6 +266,22 @@ int qed_heff_lanczos(qed_heff* h, double* x_inout, int steps, double* eval, doub
  * operator blocks in the GEMM dtype. */
 int qed_heff_flops(qed_heff* h, double* flops, double* bytes);
 
+/* Reverse mode of y = H_eff x (the effective Hamiltonian of Methods step
+ * (i) as a differentiable function of the node tensor, of every factor
+ * and of every coefficient), given the cotangent ybar:
+ *   xbar = sum_k c_k (A_k^T (x) B_k^T (x) C_k^T) ybar,
+ *   opbar[3k+e] = d<ybar, y>/d(factor e of term k), in that factor's
+ *                 operator layout (shift unchanged),
+ *   coefbar[k]  = <ybar, A_k (x) B_k (x) C_k x>.
+ * x, ybar: device FP64 (length qed_heff_size); xbar: device FP64 or NULL;
+ * opbar: NULL or 3K device FP64 pointers (NULL entries skipped; entries
+ * for identity factors ignored); coefbar: host double[K] or NULL.  The
+ * contractions run in the context's GEMM precision; intermediates are
+ * recomputed, nothing from a forward call is stored.  The first call
+ * builds the transposed factors and the contraction schedule. */
+int qed_heff_matvec_adjoint(qed_heff* h, const double* x, const double* ybar, double* xbar,
+                            double* const* opbar, double* coefbar);
+
 /* ---------------------------------------------------------------- */
 /* batched node updates                                              */
 /* ---------------------------------------------------------------- */

@@ -545,6 +545,17 @@ int qed_heff_lanczos(qed_heff* h, double* x, int steps, double* eval, double* re
     });
 }
 
+int qed_heff_matvec_adjoint(qed_heff* h, const double* x, const double* ybar, double* xbar,
+                            double* const* opbar, double* coefbar) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    return guard(h->owner, [&] {
+        if (!x || !ybar) fail(QED_ERR_INVALID_ARG, "x and ybar are required");
+        if (xbar && (xbar == x || xbar == ybar)) fail(QED_ERR_INVALID_ARG, "xbar must not alias");
+        h->h.adjoint(x, ybar, xbar, opbar, coefbar);
+        return (int)QED_OK;
+    });
+}
+
 int qed_heff_flops(qed_heff* h, double* flops, double* bytes) {
     if (!h) return QED_ERR_INVALID_ARG;
     if (flops) *flops = h->h.plan.flops;

@@ -420,40 +420,43 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
     return P;
 }
 
-Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
-                 const std::vector<OpP>& outs) {
-    Plan P;
-    P.dtype = QED_FP64;
+void append_contract(Plan& P, const Leg legs[3], const BlockTable& tab, GRef in_base,
+                     GRef partner_base, int which, const std::vector<RTerm>& terms,
+                     const std::vector<ContractOut>& outs, bool split) {
     Builder B(P);
-    B.stage(2);
-    const Leg* legs = n.legs;
-    const BlockTable& tab = n.tab;
+    const int s0 = (int)P.jobs.size();   // mode stages s0, s0+1; contraction s0+2
+    B.stage(s0 + 2);
+    const int es = B.esize;
     int f1 = which == 0 ? 1 : 0;
     int f2 = which == 2 ? 1 : 2;
     std::map<int64_t, int> bidx;
     for (int b = 0; b < tab.nblk(); ++b) bidx[key3(tab.s[0][b], tab.s[1][b], tab.s[2][b])] = b;
-    // groups keyed by (output, input sector of the output operator)
     std::map<std::pair<int, int>, std::vector<GProd>> groups;
+    auto shift = [&](GRef r, int64_t elems) {
+        if (r.tag == TAG_ABS) r.abs = (const char*)r.abs + elems * es;
+        else r.off += elems;
+        return r;
+    };
     for (const RTerm& t : terms) {
         if (t.coef == 0.0) continue;
         for (int b = 0; b < tab.nblk(); ++b) {
             BV cur;
-            cur.p = gabs(n.ptr() + tab.off[b]);
+            cur.p = shift(in_base, tab.off[b]);
             for (int e = 0; e < 3; ++e) {
                 cur.s[e] = tab.s[e][b];
                 cur.n[e] = legs[e].n[cur.s[e]];
             }
             if (t.a) {
                 BV nx;
-                if (!B.mode(0, cur, f1, *t.a, legs[f1], nx)) continue;
+                if (!B.mode(s0, cur, f1, *t.a, legs[f1], nx)) continue;
                 cur = nx;
             }
             if (t.b) {
                 BV nx;
-                if (!B.mode(1, cur, f2, *t.b, legs[f2], nx)) continue;
+                if (!B.mode(s0 + 1, cur, f2, *t.b, legs[f2], nx)) continue;
                 cur = nx;
             }
-            // partner block of the isometry: same sectors on f1, f2
+            // partner block: same sectors on f1, f2, flux 0
             int ps[3] = {cur.s[0], cur.s[1], cur.s[2]};
             if (which == 2) ps[2] = legs[2].find(legs[0].q[ps[0]] + legs[1].q[ps[1]]);
             else if (which == 0) ps[0] = legs[0].find(legs[2].q[ps[2]] - legs[1].q[ps[1]]);
@@ -462,11 +465,11 @@ Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
             auto it = bidx.find(key3(ps[0], ps[1], ps[2]));
             if (it == bidx.end()) continue;
             const int pb = it->second;
-            const OpP& out = outs[t.out];
+            const ContractOut& out = outs[t.out];
             const int sin = cur.s[which], sout = ps[which];
-            if (out->lay.out_of_in[sin] != sout)
-                fail(QED_ERR_BAD_STATE, "renormalised operator: charge shift mismatch");
-            GRef nb = gabs(n.ptr() + tab.off[pb]);
+            if (out.lay.out_of_in[sin] != sout)
+                fail(QED_ERR_BAD_STATE, "contraction output: charge shift mismatch");
+            GRef nb = shift(partner_base, tab.off[pb]);
             const int no = legs[which].n[sout], ni = cur.n[which];
             GProd p{};
             p.alpha = t.coef;
@@ -476,44 +479,53 @@ Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
                 p.A = nb; p.tA = 1; p.lda = no;
                 p.B = cur.p; p.tB = 0; p.ldb = ni;
                 p.K = K;
-                P.flops += 2.0 * K * no * ni;
+                B.add_flops(s0 + 2, 2.0 * K * no * ni);
             } else if (which == 0) {
                 const int K = cur.n[1] * cur.n[2];
                 p.A = nb; p.tA = 0; p.lda = K;
                 p.B = cur.p; p.tB = 1; p.ldb = K;
                 p.K = K;
-                P.flops += 2.0 * K * no * ni;
+                B.add_flops(s0 + 2, 2.0 * K * no * ni);
             } else {
                 const int na = cur.n[0], nc = cur.n[2];
                 p.A = nb; p.tA = 0; p.lda = nc; p.rsA = (int64_t)no * nc;
                 p.B = cur.p; p.tB = 1; p.ldb = nc; p.rsB = (int64_t)ni * nc;
                 p.K = nc;
                 p.nred = na;
-                P.flops += 2.0 * na * nc * no * ni;
+                B.add_flops(s0 + 2, 2.0 * na * nc * no * ni);
             }
             groups[{t.out, sin}].push_back(p);
         }
     }
     for (int o = 0; o < (int)outs.size(); ++o) {
-        const OpP& out = outs[o];
-        for (int s = 0; s < out->leg.nsec(); ++s) {
-            const int so = out->lay.out_of_in[s];
+        const ContractOut& out = outs[o];
+        for (int s = 0; s < out.leg.nsec(); ++s) {
+            const int so = out.lay.out_of_in[s];
             if (so < 0) continue;
             GJob j{};
-            j.C = gabs(out->d64->as<double>() + out->lay.off[s]);
-            j.M = out->leg.n[so];
-            j.N = out->leg.n[s];
+            j.C = shift(out.base, out.lay.off[s]);
+            j.M = out.leg.n[so];
+            j.N = out.leg.n[s];
             j.ldc = j.N;
             j.batch = 1;
-            j.p0 = (int)P.prods[2].size();
+            j.p0 = (int)P.prods[s0 + 2].size();
             auto it = groups.find({o, s});
             if (it != groups.end())
-                for (auto& p : it->second) P.prods[2].push_back(p);
-            j.p1 = (int)P.prods[2].size();
-            P.jobs[2].push_back(j);
+                for (auto& p : it->second) P.prods[s0 + 2].push_back(p);
+            j.p1 = (int)P.prods[s0 + 2].size();
+            P.jobs[s0 + 2].push_back(j);
         }
     }
-    split_long_reductions(P, 2);
+    if (split) split_long_reductions(P, s0 + 2);
+}
+
+Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
+                 const std::vector<OpP>& outs) {
+    Plan P;
+    P.dtype = QED_FP64;
+    std::vector<ContractOut> co;
+    for (const OpP& o : outs) co.push_back(ContractOut{o->leg, o->lay, gabs(o->d64->p)});
+    append_contract(P, n.legs, n.tab, gabs(n.ptr()), gabs(n.ptr()), which, terms, co, true);
     return P;
 }
 

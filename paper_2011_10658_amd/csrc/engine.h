@@ -64,6 +64,9 @@ void seg_ritz(double*, const double*, int64_t, const double*, int, const SegChun
 void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const double*, int,
                         double*, int64_t*, double*, hipStream_t);
 
+void launch_transpose_blocks(const double*, double*, const int64_t*, int, hipStream_t);
+void launch_scale_to_f64(const void*, int, double*, int64_t, double, hipStream_t);
+
 // ---- device memory ---------------------------------------------------
 struct Dev {
     int device = -1;
@@ -183,6 +186,22 @@ struct RTerm {
 Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
                  const std::vector<OpP>& outs);
 
+// Output of a two-tensor contraction: an operator layout on one leg and
+// the location of its blocks (compute dtype of the plan).
+struct ContractOut {
+    Leg leg;
+    OpLayout lay;
+    GRef base;
+};
+// Append out[t.out] += coef * sum over the two legs other than `which` of
+// partner (x) (in x_f1 a x_f2 b), both canonical tensors with the given
+// legs and table (renormalisation when partner = in = a node isometry;
+// operator gradients when partner = ybar and in = x).  Uses three new
+// stages (two mode stages, one contraction stage, optionally split-K).
+void append_contract(Plan& P, const Leg legs[3], const BlockTable& tab, GRef in_base,
+                     GRef partner_base, int which, const std::vector<RTerm>& terms,
+                     const std::vector<ContractOut>& outs, bool split);
+
 // out_tensor = op applied on leg e of in_tensor (sector preserving op)
 Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out);
 
@@ -218,6 +237,23 @@ LanczosResult lanczos(Dev* dev, LanczosWS& ws, const std::function<void(const do
 // ---- node-level effective Hamiltonian (C ABI object) ------------------
 struct Ctx;
 
+// Adjoint of H_eff x (hand-written reverse mode):
+//   xbar       = sum_k c_k (A_k^T (x) B_k^T (x) C_k^T) ybar
+//   Abar_k     = c_k sum_{r,p} ybar (x) (x x_r B_k x_p C_k)      (and B, C alike)
+//   cbar_k     = <ybar, A_k (x) B_k (x) C_k x> = <G_k, A_k>_F with G_k the
+//                unscaled gradient of the first non-identity factor.
+// Intermediates are recomputed (nothing from the forward pass is kept).
+struct Adjoint {
+    bool built = false;
+    Plan xbar;                                  // matvec with transposed factors
+    Plan grads;                                 // two-tensor contractions
+    std::vector<std::vector<OpP>> opT;          // transposed factors
+    std::vector<std::array<int64_t, 3>> goff;   // per term and leg: offset in G, or -1
+    int64_t gsize = 0;
+    BufP G, G64, ybc;
+    Arena ws;
+};
+
 struct Heff {
     Ctx* ctx = nullptr;
     Leg legs[3];
@@ -227,7 +263,11 @@ struct Heff {
     Arena ws;
     BufP xc, yc;   // compute-type staging for reduced precision
     LanczosWS lws;
+    Adjoint adj;
     void matvec(const double* x, double* y);
+    void build_adjoint();
+    void adjoint(const double* x, const double* ybar, double* xbar, double* const* opbar,
+                 double* coefbar);
 };
 
 // ---- the TTN sweep engine ---------------------------------------------

@@ -775,3 +775,44 @@ void launch_site_expect(const double* rho, const int64_t* diag_pos, const signed
 }
 
 }  // namespace qed
+
+namespace qed {
+
+// ---------------------------------------------------------------------
+// adjoint helpers
+// ---------------------------------------------------------------------
+// dst block (cols x rows) = transpose of src block (rows x cols), one
+// workgroup per block; blk = {src_off, dst_off, rows, cols}
+__global__ void k_transpose_blocks(const double* __restrict__ src, double* __restrict__ dst,
+                                   const int64_t* __restrict__ blk) {
+    const int64_t so = blk[4 * blockIdx.x], d0 = blk[4 * blockIdx.x + 1];
+    const int rows = (int)blk[4 * blockIdx.x + 2], cols = (int)blk[4 * blockIdx.x + 3];
+    for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += blockDim.x) {
+        const int r = (int)(e / cols), c = (int)(e % cols);
+        dst[d0 + (int64_t)c * rows + r] = src[so + e];
+    }
+}
+
+void launch_transpose_blocks(const double* src, double* dst, const int64_t* blk, int nblk,
+                             hipStream_t s) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL(k_transpose_blocks, dim3(nblk), dim3(256), 0, s, src, dst, blk);
+}
+
+template <typename S>
+__global__ void k_scale_to_f64(const S* __restrict__ a, double* __restrict__ b, int64_t n, double f) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = f * (double)a[i];
+}
+
+void launch_scale_to_f64(const void* a, int a_is_f32, double* b, int64_t n, double f, hipStream_t s) {
+    if (n <= 0) return;
+    const int g = (int)std::min<int64_t>(2048, (n + 255) / 256);
+    if (a_is_f32)
+        hipLaunchKernelGGL(k_scale_to_f64<float>, dim3(g), dim3(256), 0, s, (const float*)a, b, n, f);
+    else
+        hipLaunchKernelGGL(k_scale_to_f64<double>, dim3(g), dim3(256), 0, s, (const double*)a, b, n, f);
+}
+
+}  // namespace qed

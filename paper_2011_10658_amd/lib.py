@@ -110,6 +110,7 @@ SIGNATURES = {
     "qed_heff_matvec": [_P, _P, _P],
     "qed_heff_lanczos": [_P, _P, _I, _DP, _DP],
     "qed_heff_flops": [_P, _DP, _DP],
+    "qed_heff_matvec_adjoint": [_P, _P, _P, _P, C.POINTER(_P), _DP],
 }
 
 
@@ -368,6 +369,18 @@ class Heff:
         f, b = C.c_double(), C.c_double()
         _check(self.ctx.lib.qed_heff_flops(self.h, C.byref(f), C.byref(b)))
         return f.value, b.value
+
+    def adjoint(self, x_ptr, ybar_ptr, xbar_ptr=0, opbar_ptrs=None, want_coefbar=False, K=None):
+        """Reverse mode of y = H_eff x.  opbar_ptrs: list of 3K device
+        pointers (0 = skip).  Returns coefbar (np array) or None."""
+        ob = None
+        if opbar_ptrs is not None:
+            ob = (C.c_void_p * len(opbar_ptrs))(*[p or None for p in opbar_ptrs])
+        cb = np.zeros(K) if want_coefbar else None
+        self.ctx._c(self.ctx.lib.qed_heff_matvec_adjoint(
+            self.h, C.c_void_p(x_ptr), C.c_void_p(ybar_ptr), C.c_void_p(xbar_ptr or None), ob,
+            cb.ctypes.data_as(_DP) if cb is not None else None))
+        return cb
 
 
 class HeffBatch:
