@@ -298,6 +298,65 @@ def batched_workload(lib, torch, steps, warmup, cpu_budget, no_cpu):
     }
 
 
+def finite_density(lib, torch, steps):
+    """4x4x4 open lattice, free-flux boundary (d = 267 at every site), total
+    charge Q = +8, m = t = 1, g^2 = 1 (g_e^2 = 1, g_m^2 = 8), chi = 256 with
+    internal charges up to |q| <= 8; the same seeded start and penalty
+    schedule on the FP64, FP32 and BF16 GEMM paths (FP64 Lanczos, QR and
+    energies on all three).  Reports per-sweep energies, times, and the
+    energy and site-density differences of the reduced-precision paths from
+    the FP64 path after the same sweeps."""
+    res = {}
+    for name, dt in (("f64", lib.FP64), ("f32", lib.FP32), ("bf16", lib.BF16)):
+        ctx = lib.Context(0)
+        g2e, g2m = lib.physical_line(1.0, 1.0)
+        ctx.set_lattice(4, 4, 4, lib.BC_OPEN_FREE_FLUX)
+        ctx.set_couplings(1.0, 1.0, g2e, g2m)
+        ctx.set_charge_sector(8)
+        ctx.set_bond_dim(256)
+        ctx.set_penalty(40.0, max(1, steps // 2), max(0, steps - steps // 2))
+        ctx.set_lanczos(16, 1, 1e-8)
+        ctx.set_precision(dt, 1)
+        ctx.build_hamiltonian()
+        ctx.init_state(SEED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = []
+        for s in range(steps):
+            reps += ctx.sweep(1, report=True)
+            log(f"  {name} sweep {s}: E={reps[-1]['energy']:.10f} {reps[-1]['seconds']:.1f} s "
+                f"Q={reps[-1]['Q']:.6f} dL={reps[-1]['deltaL']:.3e}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ob = ctx.observables()
+        res[name] = dict(energies=[r["energy"] for r in reps], seconds=[r["seconds"] for r in reps],
+                         wall=wall, occ=ob["occ"], Q=ob["Q"], rho=ob["rho"],
+                         flops=sum(r["flops"] for r in reps))
+        ctx.close()
+    out = {}
+    for name in ("f32", "bf16"):
+        r, b = res[name], res["f64"]
+        out[name] = dict(
+            sweep_s=r["seconds"], energies=r["energies"],
+            dE_rel=[abs(e - f) / abs(f) for e, f in zip(r["energies"], b["energies"])],
+            max_abs_docc=float(np.abs(r["occ"] - b["occ"]).max()), Q=r["Q"], rho=r["rho"],
+            speedup_vs_fp64=sum(b["seconds"]) / sum(r["seconds"]))
+    tf = res["bf16"]["flops"] / sum(res["bf16"]["seconds"]) / 1e12
+    return {
+        "metric": METRIC, "value": tf, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": 1e3 * sum(res["bf16"]["seconds"]) / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "TTN sweeps, 4x4x4 open-lattice compact QED, free-flux boundary "
+                               "(d=267), Q=+8, m=t=1, g^2=1, chi=256, BF16 vs FP32 vs FP64 GEMMs",
+                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient"},
+        "fp64_path": dict(sweep_s=res["f64"]["seconds"], energies=res["f64"]["energies"],
+                          Q=res["f64"]["Q"], rho=res["f64"]["rho"]),
+        "f32_path": out["f32"], "bf16_path": out["bf16"],
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,7 +364,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("sweep", "batched"), default="sweep")
+    ap.add_argument("--workload", choices=("sweep", "batched", "finite_density"), default="sweep")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -317,6 +376,10 @@ def main():
         sys.exit(1)
     from paper_2011_10658_amd import lib
 
+    if a.workload == "finite_density":
+        log("== finite-density workload")
+        print(json.dumps(finite_density(lib, torch, a.steps)), flush=True)
+        return
     if a.workload == "batched":
         log("== batched workload")
         print(json.dumps(batched_workload(lib, torch, a.steps, a.warmup, a.cpu_budget,
@@ -330,6 +393,9 @@ def main():
     r32 = run_path(lib, torch, lib.FP32, a.steps, a.warmup)
     log(f"  {r32['ms_per_step']:.1f} ms/sweep, {r32['tflops']:.3f} TFLOP/s, E={r32['energy']:.12f}")
     dE = abs(r32["energy"] - r64["energy"]) / abs(r64["energy"])
+    log("== BF16-MFMA path")
+    r16 = run_path(lib, torch, lib.BF16, a.steps, a.warmup)
+    log(f"  {r16['ms_per_step']:.1f} ms/sweep, {r16['tflops']:.3f} TFLOP/s, E={r16['energy']:.12f}")
 
     # leg sectors of bottom node 0 for the CPU sample
     ctx = lib.Context(-1)
@@ -381,6 +447,10 @@ def main():
         "speedup_vs_fp64": {"sweep": r64["ms_per_step"] / r32["ms_per_step"],
                             "to_converge": (r64["seconds_to_converge"] / r32["seconds_to_converge"])
                             if r64["seconds_to_converge"] and r32["seconds_to_converge"] else None},
+        "bf16_path": {"ms_per_step": r16["ms_per_step"], "tflops": r16["tflops"],
+                      "energy": r16["energy"], "gemm_tflops": r16["gemm_tflops"],
+                      "dE_rel_vs_fp64": abs(r16["energy"] - r64["energy"]) / abs(r64["energy"]),
+                      "speedup_vs_fp64": r64["ms_per_step"] / r16["ms_per_step"]},
         "deltaL": r32["deltaL"],
         "roofline": {
             "bound": "mfma",

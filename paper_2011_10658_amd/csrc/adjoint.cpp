@@ -35,7 +35,7 @@ void Heff::build_adjoint() {
     Dev* dev = &ctx->dev;
     Adjoint& J = adj;
     const int dtype = plan.dtype;
-    const int es = dtype == QED_FP64 ? 8 : 4;
+    const int es = dtype_size(dtype);
     // xbar: the same schedule with every factor transposed
     std::vector<HTerm> tt;
     J.opT.assign(terms.size(), {});
@@ -82,7 +82,7 @@ void Heff::build_adjoint() {
             append_contract(J.grads, legs, tab, GRef{nullptr, 0, TAG_X, 0}, GRef{nullptr, 0, TAG_Y, 0},
                             e, rt[e], outs[e], true);
     J.grads.upload(dev);
-    if (dtype != QED_FP64) J.ybc = std::make_shared<DBuf>(dev, tab.size() * sizeof(float));
+    if (dtype != QED_FP64) J.ybc = std::make_shared<DBuf>(dev, tab.size() * es);
     J.built = true;
 }
 
@@ -92,14 +92,14 @@ void Heff::adjoint(const double* x, const double* ybar, double* xbar, double* co
     if (!adj.built) build_adjoint();
     Adjoint& J = adj;
     const int dtype = plan.dtype;
-    const int es = dtype == QED_FP64 ? 8 : 4;
+    const int es = dtype_size(dtype);
     const int64_t n = tab.size();
     // operands in the compute dtype
     const void* xc_ = x;
     const void* yb_ = ybar;
     if (dtype != QED_FP64) {
-        launch_f64_to_f32(x, xc->as<float>(), n, dev->stream);
-        launch_f64_to_f32(ybar, J.ybc->as<float>(), n, dev->stream);
+        to_compute(dtype, x, xc->p, n, dev->stream);
+        to_compute(dtype, ybar, J.ybc->p, n, dev->stream);
         xc_ = xc->p;
         yb_ = J.ybc->p;
     }
@@ -109,7 +109,7 @@ void Heff::adjoint(const double* x, const double* ybar, double* xbar, double* co
             J.xbar.run(dev, w, (void*)ybar, xbar);
         } else {
             J.xbar.run(dev, w, J.ybc->p, yc->p);
-            launch_f32_to_f64(yc->as<float>(), xbar, n, dev->stream);
+            from_compute(dtype, yc->p, xbar, n, dev->stream);
         }
         ctx->mv_flops += J.xbar.flops;
         ctx->mv_count += 1;
@@ -123,7 +123,7 @@ void Heff::adjoint(const double* x, const double* ybar, double* xbar, double* co
     void* w = J.ws.get(dev, std::max<int64_t>(1, J.grads.ws_elems) * es);
     J.grads.run(dev, w, (void*)xc_, (void*)yb_);
     // unscaled gradients in FP64
-    launch_scale_to_f64(J.G->p, dtype != QED_FP64, J.G64->as<double>(), J.gsize, 1.0, dev->stream);
+    launch_scale_to_f64(J.G->p, dtype, J.G64->as<double>(), J.gsize, 1.0, dev->stream);
     DBuf part(dev, 512 * sizeof(double));
     DBuf cb(dev, std::max<size_t>(1, terms.size()) * sizeof(double));
     for (size_t k = 0; k < terms.size(); ++k) {
@@ -133,7 +133,7 @@ void Heff::adjoint(const double* x, const double* ybar, double* xbar, double* co
             if (J.goff[k][e] < 0) continue;
             if (first < 0) first = e;
             if (opbar && opbar[3 * k + e])
-                launch_scale_to_f64(J.G64->as<double>() + J.goff[k][e], 0, opbar[3 * k + e],
+                launch_scale_to_f64(J.G64->as<double>() + J.goff[k][e], QED_FP64, opbar[3 * k + e],
                                     terms[k].op[e]->lay.size, c, dev->stream);
         }
         if (!coefbar) continue;

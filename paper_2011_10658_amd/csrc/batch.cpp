@@ -166,9 +166,9 @@ void HeffBatch::matvec(const double* x, double* y, hipStream_t s) {
     if (plan.dtype == QED_FP64) {
         plan.run(dev, ws->p, (void*)x, (void*)y);
     } else {
-        launch_f64_to_f32(x, xc->as<float>(), off.back(), s);
+        to_compute(plan.dtype, x, xc->p, off.back(), s);
         plan.run(dev, ws->p, xc->p, yc->p);
-        launch_f32_to_f64(yc->as<float>(), y, off.back(), s);
+        from_compute(plan.dtype, yc->p, y, off.back(), s);
     }
     dev->stream = keep;
 }

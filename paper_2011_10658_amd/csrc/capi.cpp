@@ -223,8 +223,7 @@ int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol) {
 
 int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine) {
     return guard(ctx, [&] {
-        if (gemm_dtype == QED_BF16) fail(QED_ERR_UNSUPPORTED, "BF16 GEMMs are not available in this build");
-        if (gemm_dtype != QED_FP64 && gemm_dtype != QED_FP32)
+        if (gemm_dtype != QED_FP64 && gemm_dtype != QED_FP32 && gemm_dtype != QED_BF16)
             fail(QED_ERR_INVALID_ARG, "unknown GEMM dtype");
         C(ctx).prm.dtype = gemm_dtype;
         C(ctx).prm.refine = refine ? 1 : 0;
@@ -484,11 +483,11 @@ int qed_heff_create(qed_ctx* ctx, const int* ch_l, const int* n_l, int s_l, cons
         H.plan = plan_matvec(H.legs, H.tab, H.terms, dtype);
         H.plan.upload(dev);
         if (dtype != QED_FP64) {
-            H.xc = std::make_shared<DBuf>(dev, H.tab.size() * sizeof(float));
-            H.yc = std::make_shared<DBuf>(dev, H.tab.size() * sizeof(float));
+            H.xc = std::make_shared<DBuf>(dev, H.tab.size() * dtype_size(dtype));
+            H.yc = std::make_shared<DBuf>(dev, H.tab.size() * dtype_size(dtype));
         }
         if (C(ctx).tuner.on) {
-            const size_t es = dtype == QED_FP64 ? 8 : 4;
+            const size_t es = dtype_size(dtype);
             void* w = H.ws.get(dev, std::max<int64_t>(1, H.plan.ws_elems) * es);
             DBuf tx(dev, H.tab.size() * es), ty(dev, H.tab.size() * es);
             C(ctx).tuner.tune(dev, H.plan, w, tx.p, ty.p);
@@ -625,14 +624,14 @@ int qed_heff_batch_create(qed_ctx* ctx, int nnodes, const qed_heff_desc* nodes,
         }
         const int64_t N = B.off.back();
         B.plan.upload(dev);
-        B.ws = std::make_shared<DBuf>(dev, std::max<int64_t>(1, B.plan.ws_elems) * (dtype == QED_FP64 ? 8 : 4));
+        B.ws = std::make_shared<DBuf>(dev, std::max<int64_t>(1, B.plan.ws_elems) * dtype_size(dtype));
         if (dtype != QED_FP64) {
-            B.xc = std::make_shared<DBuf>(dev, N * sizeof(float));
-            B.yc = std::make_shared<DBuf>(dev, N * sizeof(float));
+            B.xc = std::make_shared<DBuf>(dev, N * dtype_size(dtype));
+            B.yc = std::make_shared<DBuf>(dev, N * dtype_size(dtype));
         }
         dev->check(hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking), "stream");
         if (C(ctx).tuner.on) {
-            DBuf tx(dev, N * (dtype == QED_FP64 ? 8 : 4)), ty(dev, N * (dtype == QED_FP64 ? 8 : 4));
+            DBuf tx(dev, N * dtype_size(dtype)), ty(dev, N * dtype_size(dtype));
             C(ctx).tuner.tune(dev, B.plan, B.ws->p, tx.p, ty.p);
         }
         dev->sync();

@@ -69,11 +69,24 @@ void Dev::download(void* dst, const void* src, size_t bytes) {
 
 const void* LegOpD::data(int dtype) {
     if (dtype == QED_FP64) return f64();
-    if (!d32 && lay.size) {
-        d32 = std::make_shared<DBuf>(dev, lay.size * sizeof(float));
-        launch_f64_to_f32(f64(), d32->as<float>(), lay.size, dev->stream);
+    BufP& d = dtype == QED_BF16 ? d16 : d32;
+    if (!d && lay.size) {
+        d = std::make_shared<DBuf>(dev, lay.size * dtype_size(dtype));
+        to_compute(dtype, f64(), d->p, lay.size, dev->stream);
     }
-    return d32 ? d32->p : nullptr;
+    return d ? d->p : nullptr;
+}
+
+void to_compute(int dtype, const double* a, void* b, int64_t n, hipStream_t s) {
+    if (dtype == QED_BF16) launch_f64_to_bf16(a, b, n, s);
+    else if (dtype == QED_FP32) launch_f64_to_f32(a, (float*)b, n, s);
+    else fail(QED_ERR_INVALID_ARG, "to_compute: FP64 needs no conversion");
+}
+
+void from_compute(int dtype, const void* a, double* b, int64_t n, hipStream_t s) {
+    if (dtype == QED_BF16) launch_bf16_to_f64(a, b, n, 1.0, s);
+    else if (dtype == QED_FP32) launch_f32_to_f64((const float*)a, b, n, s);
+    else fail(QED_ERR_INVALID_ARG, "from_compute: FP64 needs no conversion");
 }
 
 OpP make_op(Dev* dev, const Leg& leg, int delta, bool zero) {
@@ -106,7 +119,7 @@ struct BV {
 struct Builder {
     Plan& P;
     int esize;
-    explicit Builder(Plan& p) : P(p), esize(p.dtype == QED_FP64 ? 8 : 4) {}
+    explicit Builder(Plan& p) : P(p), esize(dtype_size(p.dtype)) {}
 
     GRef ws(int64_t n) {
         GRef r = gtag(TAG_WS, P.ws_elems);
@@ -268,12 +281,16 @@ void Plan::run_stage(Dev* dev, int s, void* ws, void* x, void* y) {
     b.b[TAG_X] = x;
     b.b[TAG_Y] = y;
     if (!ntiles[s]) return;
-    if (dtype == QED_FP64)
-        launch_brgemm<double>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(), ntiles[s],
-                              b, shape[s], dev->stream);
-    else
-        launch_brgemm<float>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(), ntiles[s],
-                             b, shape[s], dev->stream);
+    launch_stage(s, b, dev->stream);
+}
+
+void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
+    const GJob* J = dj[s]->as<GJob>();
+    const GProd* Pp = dp[s]->as<GProd>();
+    const GTile* T = dt[s]->as<GTile>();
+    if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], st);
+    else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
+    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], st);
 }
 
 void Prof::record_begin(hipStream_t s, hipEvent_t& a) {
@@ -317,12 +334,7 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
         const bool timed = prof && prof->on;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timed) prof->record_begin(dev->stream, e0);
-        if (dtype == QED_FP64)
-            launch_brgemm<double>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(),
-                                  ntiles[s], b, shape[s], dev->stream);
-        else
-            launch_brgemm<float>(dj[s]->as<GJob>(), dp[s]->as<GProd>(), dt[s]->as<GTile>(),
-                                 ntiles[s], b, shape[s], dev->stream);
+        launch_stage(s, b, dev->stream);
         if (timed) {
             prof->record_begin(dev->stream, e1);
             prof->ev.push_back({e0, e1});
@@ -566,7 +578,7 @@ GRef gshift(GRef r, int64_t elems, int esize) {
 void split_long_reductions(Plan& P, int s) {
     const int64_t KCHUNK = 1024;
     const int MIN_TILES = 16;
-    const int esize = P.dtype == QED_FP64 ? 8 : 4;
+    const int esize = dtype_size(P.dtype);
     if ((int)P.jobs.size() <= s) return;
     while ((int)P.jobs.size() <= s + 1) {
         P.jobs.emplace_back();
@@ -806,14 +818,14 @@ void Heff::matvec(const double* x, double* y) {
     plan.prof = &ctx->prof;
     ctx->mv_flops += plan.flops;
     ctx->mv_count += 1;
-    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * (plan.dtype == QED_FP64 ? 8 : 4));
+    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(plan.dtype));
     const int64_t n = tab.size();
     if (plan.dtype == QED_FP64) {
         plan.run(dev, w, (void*)x, (void*)y);
     } else {
-        launch_f64_to_f32(x, xc->as<float>(), n, dev->stream);
+        to_compute(plan.dtype, x, xc->p, n, dev->stream);
         plan.run(dev, w, xc->p, yc->p);
-        launch_f32_to_f64(yc->as<float>(), y, n, dev->stream);
+        from_compute(plan.dtype, yc->p, y, n, dev->stream);
     }
 }
 

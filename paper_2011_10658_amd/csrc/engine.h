@@ -64,6 +64,10 @@ void seg_ritz(double*, const double*, int64_t, const double*, int, const SegChun
 void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const double*, int,
                         double*, int64_t*, double*, hipStream_t);
 
+void launch_brgemm_bf16(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape,
+                        hipStream_t);
+void launch_f64_to_bf16(const double*, void*, int64_t, hipStream_t);
+void launch_bf16_to_f64(const void*, double*, int64_t, double, hipStream_t);
 void launch_transpose_blocks(const double*, double*, const int64_t*, int, hipStream_t);
 void launch_scale_to_f64(const void*, int, double*, int64_t, double, hipStream_t);
 
@@ -114,7 +118,7 @@ struct Arena {
 struct LegOpD {
     Leg leg;
     OpLayout lay;
-    BufP d64, d32;
+    BufP d64, d32, d16;   // FP64 master copy; lazy FP32 and BF16 copies
     Dev* dev = nullptr;
     const double* f64() const { return d64 ? d64->as<double>() : nullptr; }
     const void* data(int dtype);
@@ -122,6 +126,13 @@ struct LegOpD {
 using OpP = std::shared_ptr<LegOpD>;
 
 OpP make_op(Dev* dev, const Leg& leg, int delta, bool zero = true);
+
+// Element size of a GEMM operand type and conversions between FP64
+// vectors and the operand type (FP32: round to nearest; BF16: FP32 first,
+// then round to nearest even).
+inline int dtype_size(int dtype) { return dtype == QED_FP64 ? 8 : dtype == QED_BF16 ? 2 : 4; }
+void to_compute(int dtype, const double* a, void* b, int64_t n, hipStream_t s);
+void from_compute(int dtype, const void* a, double* b, int64_t n, hipStream_t s);
 
 // Node tensor (canonical block layout, FP64).
 struct TensorD {
@@ -146,7 +157,7 @@ struct Prof {
 
 // ---- contraction plans -----------------------------------------------
 struct Plan {
-    int dtype = QED_FP64;   // QED_FP64 or QED_FP32 (GEMM arithmetic)
+    int dtype = QED_FP64;   // QED_FP64, QED_FP32 or QED_BF16 (GEMM operand type)
     std::vector<double> stage_flops;
     Prof* prof = nullptr;   // set for H_eff applications when profiling
     std::vector<std::vector<GJob>> jobs;
@@ -161,6 +172,7 @@ struct Plan {
     void upload(Dev* dev);
     void run(Dev* dev, void* ws, void* x, void* y);
     void run_stage(Dev* dev, int s, void* ws, void* x, void* y);
+    void launch_stage(size_t s, const Bases& b, hipStream_t st) const;
     void set_shape(Dev* dev, int s, int sh);   // re-tile one stage
 };
 

@@ -19,6 +19,10 @@
 namespace qed {
 
 constexpr double LZ_TOL_FLOOR_FP32 = 2e-6;
+// BF16 operands carry 8 significant bits (unit roundoff u = 2^-9): a
+// matvec is accurate to a few u relative, and Krylov residuals stall near
+// that level; the floor is 2u
+constexpr double LZ_TOL_FLOOR_BF16 = 3.9e-3;
 
 namespace {
 
@@ -401,30 +405,31 @@ double Engine::update(int n, double nu) {
             if (touch[e]) h.op[e] = E[e]->open.at(i);
         ht.push_back(h);
     }
-    const int dtype = P.dtype == QED_BF16 ? QED_FP32 : P.dtype;
+    const int dtype = P.dtype;
     Plan plan = plan_matvec(T.legs, T.tab, ht, dtype);
     plan.upload(dev);
     plan.prof = &ctx->prof;
     const int64_t n_el = T.tab.size();
     BufP xc, yc;
     if (dtype != QED_FP64) {
-        xc = std::make_shared<DBuf>(dev, n_el * sizeof(float));
-        yc = std::make_shared<DBuf>(dev, n_el * sizeof(float));
+        xc = std::make_shared<DBuf>(dev, n_el * dtype_size(dtype));
+        yc = std::make_shared<DBuf>(dev, n_el * dtype_size(dtype));
     }
-    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * (dtype == QED_FP64 ? 8 : 4));
+    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(dtype));
     auto apply = [&](const double* v, double* y) {
         if (dtype == QED_FP64) {
             plan.run(dev, w, (void*)v, (void*)y);
         } else {
-            launch_f64_to_f32(v, xc->as<float>(), n_el, dev->stream);
+            to_compute(dtype, v, xc->p, n_el, dev->stream);
             plan.run(dev, w, xc->p, yc->p);
-            launch_f32_to_f64(yc->as<float>(), y, n_el, dev->stream);
+            from_compute(dtype, yc->p, y, n_el, dev->stream);
         }
     };
     // an FP32 Krylov recurrence cannot resolve residuals below ~eps32 |H|:
     // restarts past that point only repeat work (the FP64 Rayleigh quotient
     // below fixes the energy)
-    const double tol = dtype == QED_FP64 ? P.lz_tol : std::max(P.lz_tol, LZ_TOL_FLOOR_FP32);
+    const double tol = dtype == QED_FP64 ? P.lz_tol
+                       : std::max(P.lz_tol, dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32);
     LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol);
     matvecs += R.matvecs;
     flops += R.matvecs * plan.flops;
@@ -464,9 +469,23 @@ void Engine::sweep(int s_index, qed_sweep_report* rep) {
     const double fl0 = flops;
     dev->sync();
     auto t0 = std::chrono::steady_clock::now();
+    const bool trace = std::getenv("QEDTTN_TRACE") != nullptr;
     for (int n = 0; n < (int)tree.nodes.size(); ++n) {
+        auto a = std::chrono::steady_clock::now();
         move_to(n);
+        if (trace) {
+            dev->sync();
+            auto b = std::chrono::steady_clock::now();
+            std::fprintf(stderr, "[qedttn] move to node %d: %.3f s\n", n,
+                         std::chrono::duration<double>(b - a).count());
+            a = b;
+        }
         update(n, nu);
+        if (trace) {
+            dev->sync();
+            std::fprintf(stderr, "[qedttn] update node %d: %.3f s\n", n,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count());
+        }
     }
     dev->sync();
     auto t1 = std::chrono::steady_clock::now();

@@ -13,6 +13,7 @@
 //  * k_householder_qr: per-sector Householder QR, one workgroup per
 //    sector matrix, wave-parallel over columns, diag(R) >= 0.
 #include "kernels.h"
+#include "qedttn.h"
 
 namespace qed {
 
@@ -781,6 +782,8 @@ namespace qed {
 // ---------------------------------------------------------------------
 // adjoint helpers
 // ---------------------------------------------------------------------
+void launch_bf16_to_f64(const void* a, double* b, int64_t n, double f, hipStream_t s);
+
 // dst block (cols x rows) = transpose of src block (rows x cols), one
 // workgroup per block; blk = {src_off, dst_off, rows, cols}
 __global__ void k_transpose_blocks(const double* __restrict__ src, double* __restrict__ dst,
@@ -806,10 +809,14 @@ __global__ void k_scale_to_f64(const S* __restrict__ a, double* __restrict__ b, 
         b[i] = f * (double)a[i];
 }
 
-void launch_scale_to_f64(const void* a, int a_is_f32, double* b, int64_t n, double f, hipStream_t s) {
+void launch_scale_to_f64(const void* a, int dtype, double* b, int64_t n, double f, hipStream_t s) {
     if (n <= 0) return;
+    if (dtype == QED_BF16) {
+        launch_bf16_to_f64(a, b, n, f, s);
+        return;
+    }
     const int g = (int)std::min<int64_t>(2048, (n + 255) / 256);
-    if (a_is_f32)
+    if (dtype == QED_FP32)
         hipLaunchKernelGGL(k_scale_to_f64<float>, dim3(g), dim3(256), 0, s, (const float*)a, b, n, f);
     else
         hipLaunchKernelGGL(k_scale_to_f64<double>, dim3(g), dim3(256), 0, s, (const double*)a, b, n, f);

@@ -16,7 +16,11 @@
 //             corners; -(g_m^2/2)(box + box^dag)
 //   onsite    m (-1)^x phi + (g_e^2/2) sum (1 - k_{+mu})^2 over the
 //             site's +mu links (+ dangling half-links under free flux)
-//   penalty   nu (1 - sum_a P^a_{x,+mu} P^{2-a}_{x+mu,-mu}) per link.
+//   penalty   nu (1 - sum_a P^a_{x,+mu} P^{2-a}_{x+mu,-mu}) per link, built
+//             as nu sum_a P^a_{x,+mu} (1 - P^{2-a}_{x+mu,-mu}) (equal, since
+//             sum_a P^a = 1): three nonnegative terms that vanish on links
+//             obeying the rishon constraint, and no constant part, so no
+//             large cancellation is left to the reduced-precision GEMMs.
 #include "model.h"
 
 #include <algorithm>
@@ -144,6 +148,12 @@ struct SiteBuilder {
             if (st.rows[s][1 + j] == a) o.m[(size_t)s * d() + s] = 1.0;
         return add(o);
     }
+    int notproj(int j, int a) {   // 1 - P^a on half-link j
+        SiteOp o = zero(0);
+        for (int s = 0; s < d(); ++s)
+            if (st.rows[s][1 + j] != a) o.m[(size_t)s * d() + s] = 1.0;
+        return add(o);
+    }
 };
 
 }  // namespace
@@ -160,7 +170,7 @@ void Model::build() {
     // per-site operator ids
     std::vector<std::array<int, 6>> Mid(L.N), Mdid(L.N);
     std::vector<std::array<std::array<int, 6>, 6>> Cid(L.N);
-    std::vector<std::array<std::array<int, 3>, 6>> Pid(L.N);
+    std::vector<std::array<std::array<int, 3>, 6>> Pid(L.N), Nid(L.N);
     std::vector<int> Hid(L.N);
     std::vector<SiteBuilder> builders;
     builders.reserve(L.N);
@@ -186,12 +196,15 @@ void Model::build() {
         Hid[s] = b.add(h);
         for (int j = 0; j < 6; ++j) {
             Mid[s][j] = Mdid[s][j] = -1;
-            for (int a = 0; a < 3; ++a) Pid[s][j][a] = -1;
+            for (int a = 0; a < 3; ++a) Pid[s][j][a] = Nid[s][j][a] = -1;
             for (int i = 0; i < 6; ++i) Cid[s][i][j] = -1;
             if (!present[j]) continue;
             Mid[s][j] = b.M(j);
             Mdid[s][j] = b.transpose(Mid[s][j], +1);
-            for (int a = 0; a < 3; ++a) Pid[s][j][a] = b.proj(j, a);
+            for (int a = 0; a < 3; ++a) {
+                if (j >= 3) Pid[s][j][a] = b.proj(j, a);
+                else Nid[s][j][a] = b.notproj(j, a);
+            }
         }
     }
     auto Cop = [&](int s, int i, int j) {
@@ -239,13 +252,12 @@ void Model::build() {
                 terms.push_back(Term{0.5 * g2m, CLS_PHYS, f});
                 terms.push_back(Term{0.5 * g2m, CLS_PHYS, fd});
             }
-    // penalty: 1 - sum_a P^a(x,+mu) P^{2-a}(y,-mu)
+    // penalty: sum_a P^a(x,+mu) (1 - P^{2-a}(y,-mu)) = 1 - sum_a P^a P^{2-a}
     for (int x = 0; x < L.N; ++x)
         for (int mu = 0; mu < 3; ++mu) {
             int y = L.neighbour(x, 3 + mu);
             if (y < 0) continue;
-            offset[CLS_PEN] += 1.0;
-            for (int a = 0; a < 3; ++a) two(-1.0, CLS_PEN, x, Pid[x][3 + mu][a], y, Pid[y][mu][2 - a]);
+            for (int a = 0; a < 3; ++a) two(1.0, CLS_PEN, x, Pid[x][3 + mu][a], y, Nid[y][mu][2 - a]);
         }
 }
 

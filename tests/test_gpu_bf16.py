@@ -1,0 +1,198 @@
+"""GPU parity of the BF16-operand path (MFMA 16x16x32 bf16, FP32
+accumulation; FP64 Lanczos, QR and energies).
+
+BF16 keeps 8 significant bits (unit roundoff u = 2^-9).  The inputs are
+first rounded to BF16 values (a change of input, done here in the test),
+so the conversions on the device are exact and the only differences from
+the FP64 oracle are the roundings of the stored intermediates and outputs
+and of coefficient-scaled operands: at most 4 per term.  Every output
+element is therefore within 4u (first order, plus 10% slack) of the
+oracle, relative to the same contraction taken over absolute values."""
+
+import numpy as np
+import pytest
+
+from oracle import blocks as oblocks
+from oracle import heff as oheff
+from paper_2011_10658_amd import lib, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U = 2.0 ** -9
+GAMMA = 4.4 * U
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def bf16_round(a):
+    """Nearest BF16 value (ties to even) of each float64 entry, through
+    binary32 as the device conversion does."""
+    f = np.asarray(a, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16 << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def flat_op(blk, leg):
+    parts = [blk[q].reshape(-1) for q, _ in leg if q in blk]
+    return np.concatenate(parts) if parts else np.zeros(0)
+
+
+LEG42 = [(-2, 5), (-1, 9), (0, 14), (1, 9), (2, 5)]
+SHIFTS = [(1, 0, 1), (0, 0, 0), (None, -1, -1), (0, None, None), (-1, 1, None),
+          (None, None, None), (0, None, 0), (2, -1, 1)]
+
+
+def rounded_case(seed, leg, shifts, coefs):
+    sizes = dict(leg)
+    terms, dterms, absterms = [], [], []
+    stream = 0
+    for sh, c in zip(shifts, coefs):
+        ops, dense, dabs = [], [], []
+        for d in sh:
+            if d is None:
+                ops.append(None)
+                dense.append(None)
+                dabs.append(None)
+                continue
+            blk = {}
+            for q, n in leg:
+                if q + d in sizes:
+                    g = synth.normal(seed, 1000 + stream, sizes[q + d] * n).reshape(sizes[q + d], n)
+                    blk[q] = bf16_round(g)
+                    stream += 1
+            ops.append(blk)
+            D = oblocks.op_to_dense(blk, leg, d)
+            dense.append(D)
+            dabs.append(np.abs(D))
+        terms.append((c, ops, tuple(0 if d is None else d for d in sh)))
+        dterms.append((c, *dense))
+        absterms.append((abs(c), *dabs))
+    legs = (leg, leg, leg)
+    size = oblocks.block_table(*legs)[1][-1]
+    x = bf16_round(synth.normal(seed, 1, size))
+    yb = bf16_round(synth.normal(seed, 2, size))
+    return legs, terms, dterms, absterms, x, yb
+
+
+def make_heff(ctx, legs, terms):
+    keep, spec = [], []
+    for c, ops, sh in terms:
+        ptrs = []
+        for e, o in enumerate(ops):
+            if o is None:
+                ptrs.append(0)
+                continue
+            t = dev(flat_op(o, legs[e]))
+            keep.append(t)
+            ptrs.append(t.data_ptr())
+        spec.append((c, tuple(ptrs), sh))
+    return ctx.heff(*legs, spec), keep
+
+
+CASES = [
+    ("c1", synth.C1_LEG, [(0, 0, 0)] * 8, [1.0] * 8),
+    ("shifted", LEG42, SHIFTS, [1.0, -0.5, 0.75, 2.0, 1.0, 0.3, -1.25, 1.0]),
+    ("c4", synth.C4_LEG, [(0, 0, 0)] * 6, [0.5, 0.5, 1.0, 1.0, 1.0, 1.0]),
+]
+
+
+@pytest.mark.parametrize("name,leg,shifts,coefs", CASES, ids=[c[0] for c in CASES])
+def test_bf16_matvec_within_rounding_bound(ctx, name, leg, shifts, coefs):
+    ctx.set_precision(lib.BF16)
+    legs, terms, dterms, absterms, x, _ = rounded_case(11, leg, shifts, coefs)
+    h, keep = make_heff(ctx, legs, terms)
+    xd = dev(x)
+    yd = torch.full_like(xd, np.nan)
+    h.matvec(xd.data_ptr(), yd.data_ptr())
+    y = yd.cpu().numpy()
+    h.close()
+    ctx.set_precision(lib.FP64)
+    yo = oheff.apply_flat(x, legs, dterms)
+    bound = oheff.apply_flat(np.abs(x), legs, absterms)
+    err = np.abs(y - yo)
+    assert np.all(err <= GAMMA * bound + 1e-30), (name, float((err / np.maximum(bound, 1e-300)).max() / U))
+    # and the typical error is at the rounding level, not at the bound
+    assert np.linalg.norm(y - yo) <= 2 * U * np.linalg.norm(bound)
+
+
+def test_bf16_adjoint_within_rounding_bound(ctx):
+    ctx.set_precision(lib.BF16)
+    legs, terms, dterms, absterms, x, yb = rounded_case(12, LEG42, SHIFTS,
+                                                        [1.0, -0.5, 0.75, 2.0, 1.0, 0.3, -1.25, 1.0])
+    h, keep = make_heff(ctx, legs, terms)
+    xd, ybd = dev(x), dev(yb)
+    xbar = torch.full_like(xd, np.nan)
+    opbar = []
+    for c, ops, sh in terms:
+        for e, o in enumerate(ops):
+            n = 0 if o is None else flat_op(o, legs[e]).size
+            opbar.append(torch.full((max(n, 1),), np.nan, dtype=torch.float64, device="cuda"))
+    cbar = h.adjoint(xd.data_ptr(), ybd.data_ptr(), xbar.data_ptr(), [g.data_ptr() for g in opbar],
+                     True, len(terms))
+    h.close()
+    ctx.set_precision(lib.FP64)
+    td = lambda v: oblocks.to_dense(v, *legs)
+    xb_o, g_o, c_o = oheff.adjoint_dense(td(x), td(yb), dterms)
+    xb_a, g_a, c_a = oheff.adjoint_dense(td(np.abs(x)), td(np.abs(yb)), absterms)
+    xb_o, xb_a = oblocks.from_dense(xb_o, *legs), oblocks.from_dense(xb_a, *legs)
+    assert np.all(np.abs(xbar.cpu().numpy() - xb_o) <= GAMMA * xb_a + 1e-30)
+    for k, (c, ops, sh) in enumerate(terms):
+        for e in range(3):
+            if ops[e] is None:
+                continue
+            ref = flat_op(oblocks.op_from_dense(g_o[k][e], legs[e], sh[e]), legs[e])
+            bnd = flat_op(oblocks.op_from_dense(g_a[k][e], legs[e], sh[e]), legs[e])
+            got = opbar[3 * k + e].cpu().numpy()[:ref.size]
+            assert np.all(np.abs(got - ref) <= GAMMA * bnd + 1e-30), (k, e)
+    # cbar = <G, A> with G rounded once more: 5 roundings
+    assert np.all(np.abs(cbar - c_o) <= (GAMMA + 1.1 * U) * c_a + 1e-30)
+
+
+CPL_T, CPL_M, CPL_G2E, CPL_G2M = 1.0, 0.7, 1.3, 0.9
+
+
+def test_bf16_sweeps_track_fp64(ctx):
+    """2x2x2 zero flux, chi 16: BF16-operand sweeps (FP64 Lanczos, QR and
+    Rayleigh quotient) from the converged FP64 state stay close to the FP64
+    energy; the deviation is reported through the assertion message."""
+    def setup(dtype):
+        ctx.set_lattice(2, 2, 2, lib.BC_OPEN_ZERO_FLUX)
+        ctx.set_couplings(CPL_T, CPL_M, CPL_G2E, CPL_G2M)
+        ctx.set_charge_sector(0)
+        ctx.set_bond_dim(16)
+        ctx.set_penalty(10.0, 0, 0)
+        ctx.set_lanczos(24, 6, 1e-12)
+        ctx.set_precision(dtype)
+        ctx.build_hamiltonian()
+
+    setup(lib.FP64)
+    ctx.init_state(7)
+    reps = ctx.sweep(16)
+    e64 = reps[-1]["energy"]
+    nn, _ = ctx.tree()
+    state = [ctx.get_node(n) for n in range(nn)]
+    setup(lib.BF16)
+    for n in range(nn):
+        ctx.set_node(n, state[n])
+    out = ctx.sweep(3)
+    for r in out:
+        # the energy is the FP64 Rayleigh quotient of a BF16 Ritz vector:
+        # not below the converged FP64 energy, and above it by less than one
+        # operand rounding of the Hamiltonian (4u |E|; about 1e-3 relative is
+        # typical at this chi)
+        assert r["energy"] >= e64 - 1e-8 * abs(e64)
+        assert r["energy"] - e64 <= 4 * U * abs(e64), (r["energy"], e64)
+    ctx.set_precision(lib.FP64)
