@@ -43,7 +43,7 @@ void launch_ritz(double*, const double*, int64_t, const double*, int64_t, const 
 void launch_normalise_sign(double*, int64_t, const double*, double*, int64_t*, double*,
                            hipStream_t);
 void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_t);
-void launch_qr(const QRMat*, int, int, double*, double*, double*, hipStream_t);
+void launch_qr(const QRMat*, int, double*, double*, double*, hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
 

@@ -170,12 +170,11 @@ OpP Engine::qr_toward(int n, int which) {
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 0, dev->stream);
     // sectors with few rows: one batched launch; tall sectors: TSQR each
     std::vector<QRMat> small;
-    int64_t small_cols = 0;
     for (int s = 0; s < ns; ++s) {
         const int n_s = L.n[s];
-        if (rows[s] <= std::max<int64_t>(4096, 16 * (int64_t)n_s)) {
+        if (n_s > QR_COLS) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 256 columns");
+        if (rows[s] <= QR_ROWS) {
             small.push_back(QRMat{mat[s], R->lay.off[s], rows[s], n_s, 1, (int)rows[s], n_s});
-            small_cols = std::max<int64_t>(small_cols, n_s);
         } else {
             tsqr(dev, packed.as<double>() + mat[s], rows[s], n_s, (double*)R->d64->p + R->lay.off[s],
                  n_s, 1);
@@ -185,8 +184,8 @@ OpP Engine::qr_toward(int n, int which) {
         DBuf dqm(dev, small.size() * sizeof(QRMat));
         dev->upload(dqm.p, small.data(), small.size() * sizeof(QRMat));
         DBuf qbuf(dev, tot * sizeof(double));
-        launch_qr(dqm.as<QRMat>(), (int)small.size(), (int)small_cols, packed.as<double>(),
-                  qbuf.as<double>(), (double*)R->d64->p, dev->stream);
+        launch_qr(dqm.as<QRMat>(), (int)small.size(), packed.as<double>(), qbuf.as<double>(),
+                  (double*)R->d64->p, dev->stream);
     }
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 1, dev->stream);
     dev->check(hipGetLastError(), "qr launch");

@@ -10,8 +10,8 @@
 //    shuffle reductions in a fixed order (deterministic), fused updates.
 //  * k_tridiag_lowest: lowest eigenpair of the Lanczos tridiagonal
 //    (Sturm bisection + inverse iteration with partial pivoting).
-//  * k_householder_qr: per-sector Householder QR, one workgroup per
-//    sector matrix, wave-parallel over columns, diag(R) >= 0.
+//  * k_householder_qr: per-sector blocked Householder QR (compact WY
+//    panels in LDS), one workgroup per sector matrix, diag(R) >= 0.
 #include "kernels.h"
 #include "qedttn.h"
 
@@ -652,60 +652,212 @@ void launch_pack(const PackBlk* blks, int nblk, int64_t maxsize, double* tensor,
 }
 
 // Householder QR of one column-major rows x cols matrix (leading dimension
-// ld) per workgroup, rows >= cols.  On exit the matrix holds the explicit Q
-// with orthonormal columns and R is written through (rout, rrs, rcs); signs
-// are fixed so that diag(R) >= 0.  `qbuf` is scratch with the same layout
-// as the input.  Zero columns (rank deficiency) get tau = 0 and R_jj = 0,
-// and Q still has orthonormal columns.
+// ld) per workgroup, cols <= rows <= QR_ROWS, cols <= QR_COLS.  On exit the
+// matrix holds the explicit Q with orthonormal columns and R is written
+// through (rout, rrs, rcs); signs are fixed so that diag(R) >= 0.  `qbuf` is
+// scratch with the same layout as the input.  Zero columns (rank
+// deficiency) get tau = 0 and R_jj = 0, and Q still has orthonormal columns.
+//
+// Blocked (compact WY) form: panels of QB columns are staged in LDS and
+// factored there; the panel's reflectors H_1..H_w are combined into
+// I - V T V^T (T upper triangular, from the Gram matrix of V and the tau),
+// and the trailing columns get (I - V T^T V^T) in one pass each, a wave per
+// pair of columns held in registers.  Q is accumulated backwards by panels
+// with the same one-pass update.  Each trailing column is thus read and
+// written once per panel instead of once per reflector.
+constexpr int QB = 8;
+constexpr int QR_RPL = QR_ROWS / 64;   // rows per lane in the column passes
+constexpr int QB_PAIRS = QB * (QB - 1) / 2;
+
+__device__ __forceinline__ double wave_bcast_sum(double v) { return __shfl(wave_sum(v), 0, 64); }
+
+// y <- y - V S y for the QB-column panel V in LDS (rows r >= k of column k;
+// r relative to the panel's first row), S = T^T (trans = 1) or T, on the
+// columns c0 and c0 + 1 (if present) of the column-major matrix X.
+template <bool TRANS>
+__device__ __forceinline__ void apply_panel(double* X, int64_t ld, int row0, int mr, int c0, bool two,
+                                            const double* Vp, const double* T, int lane) {
+    double a0[QR_RPL], a1[QR_RPL];
+    double* x0 = X + (int64_t)c0 * ld + row0;
+    double* x1 = x0 + ld;
+#pragma unroll
+    for (int t = 0; t < QR_RPL; ++t) {
+        const int r = lane + 64 * t;
+        a0[t] = r < mr ? x0[r] : 0.0;
+        a1[t] = (two && r < mr) ? x1[r] : 0.0;
+    }
+    double w0[QB], w1[QB];
+#pragma unroll
+    for (int k = 0; k < QB; ++k) w0[k] = w1[k] = 0.0;
+#pragma unroll
+    for (int t = 0; t < QR_RPL; ++t) {
+        const int r = lane + 64 * t;
+        if (r < mr) {
+#pragma unroll
+            for (int k = 0; k < QB; ++k) {
+                const double v = r >= k ? Vp[r * QB + k] : 0.0;
+                w0[k] += v * a0[t];
+                w1[k] += v * a1[t];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < QB; ++k) {
+        w0[k] = wave_bcast_sum(w0[k]);
+        w1[k] = wave_bcast_sum(w1[k]);
+    }
+    double s0[QB], s1[QB];
+#pragma unroll
+    for (int k = 0; k < QB; ++k) {
+        s0[k] = s1[k] = 0.0;
+#pragma unroll
+        for (int a = 0; a < QB; ++a) {
+            const double tk = TRANS ? T[a * QB + k] : T[k * QB + a];
+            s0[k] += tk * w0[a];
+            s1[k] += tk * w1[a];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < QR_RPL; ++t) {
+        const int r = lane + 64 * t;
+        if (r < mr) {
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < QB; ++k) {
+                const double v = r >= k ? Vp[r * QB + k] : 0.0;
+                d0 += v * s0[k];
+                d1 += v * s1[k];
+            }
+            x0[r] = a0[t] - d0;
+            if (two) x1[r] = a1[t] - d1;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict__ mats,
                                                         double* __restrict__ packed,
                                                         double* __restrict__ qbuf,
                                                         double* __restrict__ rbuf) {
-    extern __shared__ double lds[];
+    __shared__ double Vp[QR_ROWS * QB];                    // panel, row-major
+    __shared__ double Ts[(QR_COLS / QB) * QB * QB];        // T of every panel
+    __shared__ double tau[QR_COLS], diag[QR_COLS];
+    __shared__ double red[4][QB_PAIRS > QB ? QB_PAIRS : QB];
     const QRMat Mt = mats[blockIdx.x];
     const int m = Mt.rows, n = Mt.cols;
     const int64_t ld = Mt.ld;
     double* A = packed + Mt.mat;
     double* Qm = qbuf + Mt.mat;
     double* R = rbuf + Mt.rout;
-    double* tau = lds;          // n
-    double* diag = lds + n;     // n  (R_jj)
-    double* red = lds + 2 * n;  // 4
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = j + tid; i < m; i += 256) s += A[(int64_t)j * ld + i] * A[(int64_t)j * ld + i];
-        s = wave_sum(s);
-        if (lane == 0) red[wave] = s;
+    const int npan = (n + QB - 1) / QB;
+    for (int p = 0; p < npan; ++p) {
+        const int j0 = p * QB, w = min(QB, n - j0), mr = m - j0;
+        for (int e = tid; e < mr * QB; e += 256) {
+            const int k = e / mr, r = e % mr;
+            Vp[r * QB + k] = k < w ? A[(int64_t)(j0 + k) * ld + j0 + r] : 0.0;
+        }
         __syncthreads();
+        // unblocked factorisation of the panel
+        for (int i = 0; i < w; ++i) {
+            double s = 0.0;
+            for (int r = i + tid; r < mr; r += 256) s += Vp[r * QB + i] * Vp[r * QB + i];
+            s = wave_sum(s);
+            if (lane == 0) red[wave][0] = s;
+            __syncthreads();
+            if (tid == 0) {
+                const double norm2 = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+                const double x0 = Vp[i * QB + i];
+                const double nrm = sqrt(norm2);
+                if (nrm == 0.0) {
+                    tau[j0 + i] = 0.0;
+                    diag[j0 + i] = 0.0;
+                } else {
+                    const double al = x0 >= 0.0 ? -nrm : nrm;
+                    const double v0 = x0 - al;
+                    const double vtv = v0 * v0 + (norm2 - x0 * x0);
+                    tau[j0 + i] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+                    diag[j0 + i] = al;
+                    Vp[i * QB + i] = v0;
+                }
+            }
+            __syncthreads();
+            const double ti = tau[j0 + i];
+            if (ti != 0.0 && i + 1 < w) {
+                double d[QB];
+#pragma unroll
+                for (int k = 0; k < QB; ++k) d[k] = 0.0;
+                for (int r = i + tid; r < mr; r += 256) {
+                    const double v = Vp[r * QB + i];
+#pragma unroll
+                    for (int k = 0; k < QB; ++k)
+                        if (k > i) d[k] += v * Vp[r * QB + k];
+                }
+#pragma unroll
+                for (int k = 0; k < QB; ++k) {
+                    if (k <= i) continue;
+                    const double t = wave_sum(d[k]);
+                    if (lane == 0) red[wave][k] = t;
+                }
+                __syncthreads();
+                double f[QB];
+#pragma unroll
+                for (int k = 0; k < QB; ++k)
+                    f[k] = k > i ? ti * (((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]) : 0.0;
+                for (int r = i + tid; r < mr; r += 256) {
+                    const double v = Vp[r * QB + i];
+#pragma unroll
+                    for (int k = 0; k < QB; ++k)
+                        if (k > i) Vp[r * QB + k] -= f[k] * v;
+                }
+                __syncthreads();
+            }
+        }
+        // the panel back to the matrix: v below the diagonal, v0 on it,
+        // the panel's part of R above it
+        for (int e = tid; e < mr * w; e += 256) {
+            const int k = e / mr, r = e % mr;
+            A[(int64_t)(j0 + k) * ld + j0 + r] = Vp[r * QB + k];
+        }
+        // compact WY factor T from the Gram matrix of the panel's V
+        double g[QB_PAIRS];
+#pragma unroll
+        for (int q = 0; q < QB_PAIRS; ++q) g[q] = 0.0;
+        for (int r = tid; r < mr; r += 256) {
+            int q = 0;
+#pragma unroll
+            for (int b = 1; b < QB; ++b)
+#pragma unroll
+                for (int a = 0; a < b; ++a, ++q)
+                    if (r >= b) g[q] += Vp[r * QB + a] * Vp[r * QB + b];
+        }
+#pragma unroll
+        for (int q = 0; q < QB_PAIRS; ++q) {
+            const double t = wave_sum(g[q]);
+            if (lane == 0) red[wave][q] = t;
+        }
+        __syncthreads();
+        double* T = Ts + p * QB * QB;
         if (tid == 0) {
-            const double norm2 = ((red[0] + red[1]) + red[2]) + red[3];
-            const double x0 = A[(int64_t)j * ld + j];
-            const double nrm = sqrt(norm2);
-            if (nrm == 0.0) {
-                tau[j] = 0.0;
-                diag[j] = 0.0;
-            } else {
-                const double al = x0 >= 0.0 ? -nrm : nrm;
-                const double v0 = x0 - al;
-                const double vtv = v0 * v0 + (norm2 - x0 * x0);
-                tau[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
-                diag[j] = al;
-                A[(int64_t)j * ld + j] = v0;
+            for (int e = 0; e < QB * QB; ++e) T[e] = 0.0;
+            for (int i = 0; i < w; ++i) {
+                const double ti = tau[j0 + i];
+                T[i * QB + i] = ti;
+                double z[QB];
+                for (int a = 0; a < i; ++a) {
+                    const int q = i * (i - 1) / 2 + a;   // pair (a, b = i)
+                    z[a] = -ti * (((red[0][q] + red[1][q]) + red[2][q]) + red[3][q]);
+                }
+                for (int a = 0; a < i; ++a) {
+                    double s = 0.0;
+                    for (int b = a; b < i; ++b) s += T[a * QB + b] * z[b];
+                    T[a * QB + i] = s;
+                }
             }
         }
         __syncthreads();
-        const double tj = tau[j];
-        if (tj != 0.0) {
-            for (int k = j + 1 + wave; k < n; k += 4) {
-                double d = 0.0;
-                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * ld + i] * A[(int64_t)k * ld + i];
-                d = wave_sum(d);
-                d = __shfl(d, 0, 64);
-                const double f = tj * d;
-                for (int i = j + lane; i < m; i += 64) A[(int64_t)k * ld + i] -= f * A[(int64_t)j * ld + i];
-            }
-        }
+        // trailing columns: A <- (I - V T^T V^T) A
+        for (int c0 = j0 + w + 2 * wave; c0 < n; c0 += 8)
+            apply_panel<true>(A, ld, j0, mr, c0, c0 + 1 < n, Vp, T, lane);
         __syncthreads();
     }
     for (int e = tid; e < n * n; e += 256) {
@@ -717,18 +869,16 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
         Qm[(int64_t)c * ld + r] = r == c ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int j = n - 1; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj != 0.0) {
-            for (int k = j + wave; k < n; k += 4) {
-                double d = 0.0;
-                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * ld + i] * Qm[(int64_t)k * ld + i];
-                d = wave_sum(d);
-                d = __shfl(d, 0, 64);
-                const double f = tj * d;
-                for (int i = j + lane; i < m; i += 64) Qm[(int64_t)k * ld + i] -= f * A[(int64_t)j * ld + i];
-            }
+    // Q = H_1 ... H_n [I; 0], panels applied last to first: Q <- (I - V T V^T) Q
+    for (int p = npan - 1; p >= 0; --p) {
+        const int j0 = p * QB, w = min(QB, n - j0), mr = m - j0;
+        for (int e = tid; e < mr * QB; e += 256) {
+            const int k = e / mr, r = e % mr;
+            Vp[r * QB + k] = (k < w && r >= k) ? A[(int64_t)(j0 + k) * ld + j0 + r] : 0.0;
         }
+        __syncthreads();
+        for (int c0 = j0 + 2 * wave; c0 < n; c0 += 8)
+            apply_panel<false>(Qm, ld, j0, mr, c0, c0 + 1 < n, Vp, Ts + p * QB * QB, lane);
         __syncthreads();
     }
     for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
@@ -742,11 +892,10 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
     }
 }
 
-void launch_qr(const QRMat* mats, int nmats, int maxcols, double* packed, double* qbuf,
-               double* rbuf, hipStream_t s) {
+void launch_qr(const QRMat* mats, int nmats, double* packed, double* qbuf, double* rbuf,
+               hipStream_t s) {
     if (nmats <= 0) return;
-    size_t lds = (size_t)(2 * maxcols + 4) * sizeof(double);
-    hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), lds, s, mats, packed, qbuf, rbuf);
+    hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), 0, s, mats, packed, qbuf, rbuf);
 }
 
 // ---------------------------------------------------------------------

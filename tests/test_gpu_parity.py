@@ -306,3 +306,39 @@ def test_lanczos_large_vector_deterministic(ctx):
     th, u, _, _, _ = olanczos.lanczos_cycle(lambda v: oheff.apply_flat(v, legs, dterms), x0, 6)
     assert abs(outs[0][0] - th) <= 1e-11 * abs(th)
     assert np.abs(outs[0][1] - u).max() < 1e-9
+
+
+def test_isometries_after_free_flux_sweep(ctx):
+    """After a sweep the centre sits at the root and every other node is an
+    isometry from its two children to its parent leg: per parent sector the
+    stacked blocks have orthonormal columns (Methods, tree isometries).  The
+    bottom nodes (legs 267 x 267 x 64) have 10^4 - 10^5 rows per sector and
+    take the chunked (TSQR) path of the QR."""
+    g2e, g2m = lib.physical_line(1.0, 1.0)
+    ctx.set_lattice(2, 2, 2, lib.BC_OPEN_FREE_FLUX)
+    ctx.set_couplings(1.0, 1.0, g2e, g2m)
+    ctx.set_charge_sector(0)
+    ctx.set_bond_dim(64)
+    ctx.set_penalty(10.0, 0, 0)
+    ctx.set_lanczos(8, 1, 0.0)
+    ctx.set_precision(lib.FP64)
+    ctx.build_hamiltonian()
+    ctx.init_state(5)
+    ctx.sweep(1)
+    nn, _ = ctx.tree()
+    worst, tall = 0.0, 0
+    for n in range(nn - 1):          # the root is the last node
+        l, r, p = [ctx.leg_sectors(e) for e in ctx.node_links(n)]
+        triples, offs = oblocks.block_table(l, r, p)
+        x = ctx.get_node(n)
+        gram = {ip: np.zeros((p[ip][1], p[ip][1])) for ip in range(len(p))}
+        rows = {ip: 0 for ip in range(len(p))}
+        for b, (il, ir, ip) in enumerate(triples):
+            B = x[offs[b]:offs[b + 1]].reshape(l[il][1] * r[ir][1], p[ip][1])
+            gram[ip] += B.T @ B
+            rows[ip] += B.shape[0]
+        for ip, G in gram.items():
+            worst = max(worst, np.abs(G - np.eye(G.shape[0])).max())
+            tall += rows[ip] > 2048
+    assert tall > 0
+    assert worst < 1e-12, worst
