@@ -185,6 +185,27 @@ int qed_node_size(qed_ctx* ctx, int node, int64_t* n_entries);
  * highest layer); rep (optional, n entries) receives one record each. */
 int qed_sweep(qed_ctx* ctx, int n, qed_sweep_report* rep);
 
+/* Checkpoint / resume of the variational state (the paper's runs take
+ * weeks, Methods, so a state must survive a restart).  The file holds, in
+ * native byte order: magic "QEDTTNS", format version 1, lattice extents,
+ * boundary, total charge, bond dimension, couplings, the sweep index (it
+ * sets the penalty schedule), whether the isometry centre sits at the
+ * root, the last energy, every link's (charge, size) sectors, every node's
+ * FP64 blocks in canonical order, and an FNV-1a 64-bit checksum of all
+ * preceding bytes.  Save writes `path`.tmp and renames it over `path`.
+ * Load needs a context built (qed_build_hamiltonian) for the same lattice,
+ * boundary, charge and bond dimension (couplings may differ: a warm start);
+ * a state saved with the centre at the root resumes with the same
+ * arithmetic as an uninterrupted run.  QED_ERR_IO for unreadable,
+ * truncated or corrupt files (checked before anything changes),
+ * QED_ERR_INVALID_ARG for a file of another problem. */
+int qed_save_state(qed_ctx* ctx, const char* path);
+int qed_load_state(qed_ctx* ctx, const char* path);
+
+/* Failure injection for tests: overwrite the first entry of a node tensor
+ * with a quiet NaN.  The next sweep reports QED_ERR_NONFINITE. */
+int qed_debug_poison(qed_ctx* ctx, int node);
+
 int qed_get_energy(qed_ctx* ctx, double* E);
 
 /* Local observables of the current state (isometry centre moved to the

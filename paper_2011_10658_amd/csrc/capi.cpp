@@ -2,8 +2,11 @@
 // include/qedttn.h).  Every entry point turns internal errors into status
 // codes and a context-owned message.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
+#include <string>
 
 #include "engine.h"
 
@@ -66,6 +69,55 @@ Leg make_leg(const int* ch, const int* n, int s) {
 }
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// ---- checkpoint / resume -------------------------------------------------
+namespace {
+
+constexpr char CKPT_MAGIC[8] = {'Q', 'E', 'D', 'T', 'T', 'N', 'S', '\0'};
+constexpr uint32_t CKPT_VERSION = 1;
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    }
+};
+
+struct Writer {
+    std::FILE* f;
+    Fnv sum;
+    void put(const void* p, size_t n) {
+        if (std::fwrite(p, 1, n, f) != n) fail(QED_ERR_IO, "checkpoint write failed");
+        sum.add(p, n);
+    }
+    template <typename T> void val(T v) { put(&v, sizeof(T)); }
+};
+
+struct Reader {
+    std::FILE* f;
+    Fnv sum;
+    int64_t left = 0;   // bytes not read yet
+    void get(void* p, size_t n) {
+        if ((int64_t)n > left || std::fread(p, 1, n, f) != n) fail(QED_ERR_IO, "checkpoint truncated");
+        left -= (int64_t)n;
+        sum.add(p, n);
+    }
+    template <typename T> T val() {
+        T v;
+        get(&v, sizeof(T));
+        return v;
+    }
+};
+
+struct FileCloser {
+    std::FILE* f;
+    ~FileCloser() {
+        if (f) std::fclose(f);
+    }
+};
 
 }  // namespace
 
@@ -336,6 +388,141 @@ int qed_get_node(qed_ctx* ctx, int node, double* host, int64_t n) {
         TensorD& T = e.nodes[node];
         if (n != T.tab.size()) fail(QED_ERR_INVALID_ARG, "wrong number of entries");
         C(ctx).dev.download(host, T.d->p, n * sizeof(double));
+        return QED_OK;
+    });
+}
+
+
+int qed_save_state(qed_ctx* ctx, const char* path) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        if (!path || !*path) fail(QED_ERR_INVALID_ARG, "empty path");
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state to save");
+        const Params& P = C(ctx).prm;
+        const std::string tmp = std::string(path) + ".tmp";
+        {
+            FileCloser fc{std::fopen(tmp.c_str(), "wb")};
+            if (!fc.f) fail(QED_ERR_IO, "cannot open checkpoint file for writing");
+            Writer w{fc.f, {}};
+            w.put(CKPT_MAGIC, sizeof(CKPT_MAGIC));
+            w.val<uint32_t>(CKPT_VERSION);
+            for (int v : {P.Lx, P.Ly, P.Lz, P.bc, P.Q, P.chi}) w.val<int32_t>(v);
+            for (double v : {P.t, P.m, P.g2e, P.g2m}) w.val<double>(v);
+            w.val<int32_t>(e.sweeps_done);
+            w.val<int32_t>(e.centre == e.tree.root ? 1 : 0);
+            w.val<int32_t>(e.have_energy ? 1 : 0);
+            w.val<double>(e.energy);
+            w.val<int32_t>((int)e.legs.size());
+            for (const Leg& L : e.legs) {
+                w.val<int32_t>(L.nsec());
+                for (int s = 0; s < L.nsec(); ++s) {
+                    w.val<int32_t>(L.q[s]);
+                    w.val<int32_t>(L.n[s]);
+                }
+            }
+            w.val<int32_t>((int)e.nodes.size());
+            std::vector<double> h;
+            for (const TensorD& T : e.nodes) {
+                h.resize(T.tab.size());
+                C(ctx).dev.download(h.data(), T.ptr(), h.size() * sizeof(double));
+                w.val<int64_t>((int64_t)h.size());
+                w.put(h.data(), h.size() * sizeof(double));
+            }
+            const uint64_t s = w.sum.h;
+            if (std::fwrite(&s, 1, sizeof(s), fc.f) != sizeof(s)) fail(QED_ERR_IO, "checkpoint write failed");
+            if (std::fflush(fc.f) != 0) fail(QED_ERR_IO, "checkpoint flush failed");
+        }
+        if (std::rename(tmp.c_str(), path) != 0) fail(QED_ERR_IO, "cannot move the checkpoint into place");
+        return QED_OK;
+    });
+}
+
+int qed_load_state(qed_ctx* ctx, const char* path) {
+    return guard(ctx, [&] {
+        if (!path || !*path) fail(QED_ERR_INVALID_ARG, "empty path");
+        FileCloser fc{std::fopen(path, "rb")};
+        if (!fc.f) fail(QED_ERR_IO, "cannot open checkpoint file");
+        Reader r{fc.f, {}, 0};
+        if (std::fseek(fc.f, 0, SEEK_END) != 0) fail(QED_ERR_IO, "cannot size the checkpoint file");
+        r.left = (int64_t)std::ftell(fc.f);
+        if (r.left < 0 || std::fseek(fc.f, 0, SEEK_SET) != 0) fail(QED_ERR_IO, "cannot size the checkpoint file");
+        char magic[8];
+        r.get(magic, sizeof(magic));
+        if (std::memcmp(magic, CKPT_MAGIC, sizeof(magic)) != 0) fail(QED_ERR_IO, "not a checkpoint file");
+        if (r.val<uint32_t>() != CKPT_VERSION) fail(QED_ERR_IO, "unsupported checkpoint version");
+        int32_t hdr[6];
+        for (int& v : hdr) v = r.val<int32_t>();
+        double cpl[4];
+        for (double& v : cpl) v = r.val<double>();
+        const int32_t sweeps = r.val<int32_t>();
+        const int32_t iso = r.val<int32_t>();
+        const int32_t have_e = r.val<int32_t>();
+        const double energy = r.val<double>();
+        const int32_t nlegs = r.val<int32_t>();
+        if (nlegs < 1 || nlegs > (1 << 20)) fail(QED_ERR_IO, "corrupt checkpoint (legs)");
+        std::vector<Leg> legs(nlegs);
+        for (Leg& L : legs) {
+            const int32_t ns = r.val<int32_t>();
+            if (ns < 1 || ns > 4096) fail(QED_ERR_IO, "corrupt checkpoint (sectors)");
+            for (int s = 0; s < ns; ++s) {
+                L.q.push_back(r.val<int32_t>());
+                L.n.push_back(r.val<int32_t>());
+            }
+        }
+        const int32_t nn = r.val<int32_t>();
+        if (nn < 1 || nn > (1 << 20)) fail(QED_ERR_IO, "corrupt checkpoint (nodes)");
+        std::vector<std::vector<double>> data(nn);
+        for (auto& d : data) {
+            const int64_t sz = r.val<int64_t>();
+            if (sz < 0 || sz > r.left / (int64_t)sizeof(double)) fail(QED_ERR_IO, "corrupt checkpoint (node size)");
+            d.resize(sz);
+            r.get(d.data(), sz * sizeof(double));
+        }
+        uint64_t stored = 0;
+        const uint64_t computed = r.sum.h;
+        if (std::fread(&stored, 1, sizeof(stored), fc.f) != sizeof(stored) || stored != computed)
+            fail(QED_ERR_IO, "checkpoint checksum mismatch");
+        // the file is whole; now it has to fit the configured problem
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        const Params& P = C(ctx).prm;
+        const int cur[6] = {P.Lx, P.Ly, P.Lz, P.bc, P.Q, P.chi};
+        for (int i = 0; i < 6; ++i)
+            if (hdr[i] != cur[i])
+                fail(QED_ERR_INVALID_ARG, "checkpoint is for another lattice, boundary, charge or bond dimension");
+        if (nlegs != (int)e.legs.size() || nn != (int)e.tree.nodes.size())
+            fail(QED_ERR_INVALID_ARG, "checkpoint tree does not match");
+        for (int i = 0; i < nlegs; ++i)
+            if (legs[i].q != e.legs[i].q || legs[i].n != e.legs[i].n)
+                fail(QED_ERR_INVALID_ARG, "checkpoint leg sectors do not match");
+        if (e.nodes.empty()) e.init_nodes(0);
+        for (int i = 0; i < nn; ++i) {
+            if ((int64_t)data[i].size() != e.nodes[i].tab.size())
+                fail(QED_ERR_INVALID_ARG, "checkpoint node size does not match");
+            C(ctx).dev.upload(e.nodes[i].ptr(), data[i].data(), data[i].size() * sizeof(double));
+        }
+        e.invalidate();
+        e.isometric = iso != 0;
+        e.sweeps_done = sweeps;
+        e.have_energy = have_e != 0;
+        e.energy = energy;
+        return QED_OK;
+    });
+}
+
+int qed_debug_poison(qed_ctx* ctx, int node) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state");
+        if (node < 0 || node >= (int)e.nodes.size()) fail(QED_ERR_INVALID_ARG, "bad node");
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        C(ctx).dev.upload(e.nodes[node].ptr(), &nan, sizeof(double));
+        e.invalidate();
         return QED_OK;
     });
 }

@@ -313,6 +313,7 @@ struct Engine {
     std::vector<std::vector<int>> tsites;    // per term: its sites
     int centre = -1;
     int sweeps_done = 0;
+    bool isometric = false;   // every non-root node is an isometry toward the root
     double energy = 0.0;
     bool have_energy = false;
     Arena ws;
@@ -323,7 +324,10 @@ struct Engine {
     void build(Ctx* c);
     void init_nodes(uint64_t seed);
     bool ready() const { return !nodes.empty(); }
-    void invalidate() { centre = -1; }
+    void invalidate() {
+        centre = -1;
+        isometric = false;
+    }
     void prepare();
     void sweep(int s, qed_sweep_report* rep);
     void observables(std::vector<double>& site7);

@@ -362,14 +362,19 @@ void Engine::prepare() {
         e.valid = true;
         up[s] = e;
     }
-    // isometrise bottom-up; the centre ends at the root
+    // isometrise bottom-up; the centre ends at the root (a state restored
+    // from a checkpoint taken with the centre at the root is isometric
+    // already: only its environments are rebuilt)
     for (int n = 0; n < (int)tree.nodes.size(); ++n) {
         if (n == tree.root) continue;
         const auto& nd = tree.nodes[n];
-        OpP R = qr_toward(n, 2);
-        absorb(tree.parent_node[nd.p], tree.parent_side[nd.p], R);
+        if (!isometric) {
+            OpP R = qr_toward(n, 2);
+            absorb(tree.parent_node[nd.p], tree.parent_side[nd.p], R);
+        }
         build_env(n, 2, up[nd.p]);
     }
+    isometric = false;
     EnvD top;
     for (int cls = 0; cls < 2; ++cls) top.H[cls] = make_op(dev, legs[tree.top], 0, true);
     top.valid = true;

@@ -91,6 +91,9 @@ SIGNATURES = {
     "qed_get_node": [_P, _I, _DP, C.c_int64],
     "qed_node_size": [_P, _I, _LP],
     "qed_sweep": [_P, _I, C.POINTER(SweepReport)],
+    "qed_save_state": [_P, C.c_char_p],
+    "qed_load_state": [_P, C.c_char_p],
+    "qed_debug_poison": [_P, _I],
     "qed_get_energy": [_P, _DP],
     "qed_get_observables": [_P, _DP, _DP, _DP, _DP, _DP],
     "qed_heff_batch_create": [_P, _I, C.POINTER(HeffDesc), C.POINTER(_P)],
@@ -282,6 +285,15 @@ class Context:
         reps = (SweepReport * max(1, n))()
         self._c(self.lib.qed_sweep(self.h, n, reps))
         return [reps[i].as_dict() for i in range(n)]
+
+    def save_state(self, path):
+        self._c(self.lib.qed_save_state(self.h, os.fsencode(path)))
+
+    def load_state(self, path):
+        self._c(self.lib.qed_load_state(self.h, os.fsencode(path)))
+
+    def debug_poison(self, node):
+        self._c(self.lib.qed_debug_poison(self.h, node))
 
     def energy(self):
         e = C.c_double()

@@ -121,3 +121,78 @@ def test_error_paths():
     assert lib.physical_line(1.0) == (1.0, 8.0)
     with pytest.raises(lib.QedError):
         lib.physical_line(0.0)
+
+
+# -- checkpoint files ---------------------------------------------------------
+def _fnv(data):
+    h = 1469598103934665603
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _checkpoint_bytes(ctx, L, bc, Q, chi, cpl, nodes_fill=0.25):
+    """A well-formed state file for the context's tree, written from the
+    documented layout (independent of the library's writer)."""
+    import struct
+    nn, _ = ctx.tree()
+    links = []
+    e = 0
+    while True:
+        try:
+            links.append(ctx.leg_sectors(e))
+        except lib.QedError:
+            break
+        e += 1
+    body = b"QEDTTNS\x00" + struct.pack("<I", 1)
+    body += struct.pack("<6i", *L, bc, Q, chi) + struct.pack("<4d", *cpl)
+    body += struct.pack("<iiid", 3, 1, 1, -1.5)
+    body += struct.pack("<i", len(links))
+    for leg in links:
+        body += struct.pack("<i", len(leg))
+        for q, n in leg:
+            body += struct.pack("<ii", q, n)
+    body += struct.pack("<i", nn)
+    for n in range(nn):
+        l, r, p = [links[k] for k in ctx.node_links(n)]
+        size = int(oblocks.block_table(l, r, p)[1][-1])
+        body += struct.pack("<q", size) + np.full(size, nodes_fill).tobytes()
+    return body + struct.pack("<Q", _fnv(body))
+
+
+def test_checkpoint_file_checks(tmp_path):
+    ctx = lib.Context(-1)
+    with pytest.raises(lib.QedError) as e:
+        ctx.load_state(str(tmp_path / "missing.ckpt"))
+    assert e.value.code == -8
+    junk = tmp_path / "junk.ckpt"
+    junk.write_bytes(b"not a checkpoint at all")
+    with pytest.raises(lib.QedError) as e:
+        ctx.load_state(str(junk))
+    assert e.value.code == -8
+    ctx.set_lattice(2, 2, 1, lib.BC_OPEN_ZERO_FLUX)
+    ctx.set_couplings(1.0, 1.0, 1.0, 8.0)
+    ctx.set_bond_dim(8)
+    ctx.build_hamiltonian()
+    good = _checkpoint_bytes(ctx, (2, 2, 1), lib.BC_OPEN_ZERO_FLUX, 0, 8, (1.0, 1.0, 1.0, 8.0))
+    f = tmp_path / "state.ckpt"
+    f.write_bytes(good)
+    # a whole file passes every format check and stops only at the device
+    with pytest.raises(lib.QedError) as e:
+        ctx.load_state(str(f))
+    assert e.value.code == -2 and "host-only" in str(e.value)
+    # any flipped byte, or a cut, is caught by the checksum or the reader
+    for pos in (20, len(good) // 2, len(good) - 3):
+        bad = bytearray(good)
+        bad[pos] ^= 0x10
+        f.write_bytes(bytes(bad))
+        with pytest.raises(lib.QedError) as e:
+            ctx.load_state(str(f))
+        assert e.value.code == -8, pos
+    f.write_bytes(good[:-100])
+    with pytest.raises(lib.QedError) as e:
+        ctx.load_state(str(f))
+    assert e.value.code == -8
+    with pytest.raises(lib.QedError) as e:
+        ctx.save_state(str(tmp_path / "x.ckpt"))
+    assert e.value.code == -2
