@@ -48,23 +48,29 @@ __device__ __forceinline__ T* resolve(const GRef& r, const Bases& bs) {
 // grouped batch-reduce GEMM
 // ---------------------------------------------------------------------
 // Workgroup tile (16 WM BM) x (16 WN BN) on 4 waves in a WM x WN grid;
-// every wave owns BM x BN MFMA 16x16 blocks.  K advances in chunks of KC
-// staged k-major in LDS (As[k][m], Bs[k][n]: the MFMA operand reads of a
-// wave hit 16 consecutive words); the next chunk is fetched into
-// registers while the current one is multiplied.
-constexpr int KC = 16;
+// every wave owns BM x BN MFMA 16x16 blocks.  K advances in chunks of
+// KC = 16 staged k-major in LDS (As[k][m], Bs[k][n]:
+// the MFMA operand reads of a wave hit 16 consecutive words).  The LDS
+// stage is double-buffered: chunk c + 1 is fetched into registers while
+// chunk c is multiplied, then stored into the other buffer, so a chunk
+// costs one barrier.  Each thread's element offsets are computed once per
+// product; a chunk only adds its k offset.
+template <typename T> struct GemmK;
+template <> struct GemmK<float> { static constexpr int KC = 16; };
+template <> struct GemmK<double> { static constexpr int KC = 16; };
 
 template <typename T, int WM, int WN, int BM, int BN>
 __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
                                                 const GProd* __restrict__ prods,
                                                 const GTile* __restrict__ tiles, Bases bases) {
     typedef typename Mfma<T>::v4 v4;
+    constexpr int KC = GemmK<T>::KC;
     constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
     constexpr int PAD = 4;
     constexpr int AE = TM * KC / 256;   // A elements per thread per chunk
     constexpr int BE = TN * KC / 256;
-    __shared__ T As[KC][TM + PAD];
-    __shared__ T Bs[KC][TN + PAD];
+    __shared__ T As[2][KC][TM + PAD];
+    __shared__ T Bs[2][KC][TN + PAD];
     const GTile tl = tiles[blockIdx.x];
     const GJob J = jobs[tl.job];
     const int tid = threadIdx.x;
@@ -81,7 +87,13 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
 #pragma unroll
         for (int j = 0; j < BN; ++j) acc[i][j] = v4{0, 0, 0, 0};
     T ra[AE], rb[BE];
-    int bcol[BE];       // column offsets of this thread's B elements (tB = 0)
+    // every tile extent divides 256, so element e of a thread sits at a
+    // fixed stride from its element 0: one base offset per operand
+    constexpr int ASA = 256 / KC, ASB = 256 / TM;    // A rows (A^T k) per e
+    constexpr int BSB = 256 / KC, BSN = 256 / TN;    // B^T rows (B k) per e
+    const int t_kc = tid % KC, t_kq = tid / KC;
+    const int t_tm = tid % TM, t_tq = tid / TM;
+    const int t_tn = tid % TN, t_nq = tid / TN;
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
         const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
@@ -104,79 +116,75 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
         }
         const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
         const int nchunk = (P.K + KC - 1) / KC;
-        if (!P.tB) {
-#pragma unroll
-            for (int e = 0; e < BE; ++e) {
-                const int n = (tid + e * 256) % TN;
-                const int gn = n0 + n;
-                bcol[e] = P.nsb ? (int)((gn / P.nsb) * P.nob + gn % P.nsb) : gn;
-            }
+        // element e of this thread: A row am0 + e amE, A column (k) ak0 + e akE
+        // within the chunk (and likewise for B), one branch-free form for
+        // both storage orders
+        const int am0 = P.tA ? t_tm : t_kq, amE = P.tA ? 0 : ASA;
+        const int ak0 = P.tA ? t_tq : t_kc, akE = P.tA ? ASB : 0;
+        const int64_t akm = P.tA ? (int64_t)P.lda : 1;
+        const int64_t aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
+        const int64_t abase = P.tA ? (int64_t)ak0 * P.lda + m0 + am0 : (int64_t)(m0 + am0) * P.lda + ak0;
+        const int bn0 = P.tB ? t_kq : t_tn, bnE = P.tB ? BSB : 0;
+        const int bk0 = P.tB ? t_kc : t_nq, bkE = P.tB ? 0 : BSN;
+        const int64_t bkm = P.tB ? 1 : (int64_t)P.ldb;
+        const int64_t bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
+        int64_t bbase;
+        if (P.tB) {
+            bbase = (int64_t)(n0 + bn0) * P.ldb + bk0;
+        } else {
+            const int gn = n0 + bn0;
+            const int64_t col = P.nsb ? (int64_t)(gn / P.nsb) * P.nob + gn % P.nsb : gn;
+            bbase = (int64_t)bk0 * P.ldb + col;
         }
         for (int r = 0; r < P.nred; ++r) {
-            const T* A = Ab + (int64_t)r * P.rsA;
-            const T* B = Bb + (int64_t)r * P.rsB;
-            auto fetch = [&](int k0) {
+            const T* A = Ab + (int64_t)r * P.rsA + abase;
+            const T* B = Bb + (int64_t)r * P.rsB + bbase;
+            auto fetch = [&](int c) {
+                const int k0 = c * KC;
+                const T* pa = A + k0 * akm;
+                const T* pb = B + k0 * bkm;
 #pragma unroll
                 for (int e = 0; e < AE; ++e) {
-                    const int idx = tid + e * 256;
-                    int m, k;
-                    if (P.tA) { m = idx % TM; k = idx / TM; }
-                    else { k = idx % KC; m = idx / KC; }
-                    const int gm = m0 + m, gk = k0 + k;
                     T v = (T)0;
-                    if (gm < J.M && gk < P.K)
-                        v = P.tA ? A[(int64_t)gk * P.lda + gm] : A[(int64_t)gm * P.lda + gk];
+                    if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
                     ra[e] = v * alpha;
                 }
 #pragma unroll
                 for (int e = 0; e < BE; ++e) {
-                    const int idx = tid + e * 256;
-                    int k, n;
-                    if (P.tB) { k = idx % KC; n = idx / KC; }
-                    else { n = idx % TN; k = idx / TN; }
-                    const int gn = n0 + n, gk = k0 + k;
                     T v = (T)0;
-                    if (gn < J.N && gk < P.K)
-                        v = P.tB ? B[(int64_t)gn * P.ldb + gk] : B[(int64_t)gk * P.ldb + bcol[e]];
+                    if (n0 + bn0 + e * bnE < J.N && k0 + bk0 + e * bkE < P.K) v = pb[e * bes];
                     rb[e] = v;
                 }
             };
-            auto stash = [&]() {
+            auto stash = [&](int buf) {
 #pragma unroll
-                for (int e = 0; e < AE; ++e) {
-                    const int idx = tid + e * 256;
-                    int m, k;
-                    if (P.tA) { m = idx % TM; k = idx / TM; }
-                    else { k = idx % KC; m = idx / KC; }
-                    As[k][m] = ra[e];
-                }
+                for (int e = 0; e < AE; ++e) As[buf][ak0 + e * akE][am0 + e * amE] = ra[e];
 #pragma unroll
-                for (int e = 0; e < BE; ++e) {
-                    const int idx = tid + e * 256;
-                    int k, n;
-                    if (P.tB) { k = idx % KC; n = idx / KC; }
-                    else { n = idx % TN; k = idx / TN; }
-                    Bs[k][n] = rb[e];
-                }
+                for (int e = 0; e < BE; ++e) Bs[buf][bk0 + e * bkE][bn0 + e * bnE] = rb[e];
             };
+            // the previous product's last chunk may still be read from
+            // buffer 0 by other waves
+            __syncthreads();
             fetch(0);
+            stash(0);
+            __syncthreads();
             for (int c = 0; c < nchunk; ++c) {
-                __syncthreads();
-                stash();
-                __syncthreads();
-                if (c + 1 < nchunk) fetch((c + 1) * KC);
+                const int cur = c & 1;
+                if (c + 1 < nchunk) fetch(c + 1);
 #pragma unroll
                 for (int kk = 0; kk < KC; kk += 4) {
                     T a[BM], bb[BN];
 #pragma unroll
-                    for (int i = 0; i < BM; ++i) a[i] = As[kk + lk][wm0 + i * 16 + lr];
+                    for (int i = 0; i < BM; ++i) a[i] = As[cur][kk + lk][wm0 + i * 16 + lr];
 #pragma unroll
-                    for (int j = 0; j < BN; ++j) bb[j] = Bs[kk + lk][wn0 + j * 16 + lr];
+                    for (int j = 0; j < BN; ++j) bb[j] = Bs[cur][kk + lk][wn0 + j * 16 + lr];
 #pragma unroll
                     for (int i = 0; i < BM; ++i)
 #pragma unroll
                         for (int j = 0; j < BN; ++j) acc[i][j] = Mfma<T>::step(a[i], bb[j], acc[i][j]);
                 }
+                if (c + 1 < nchunk) stash(cur ^ 1);
+                __syncthreads();
             }
         }
     }
