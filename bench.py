@@ -388,6 +388,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--workload", choices=("sweep", "batched", "finite_density"), default="sweep")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one elementwise pass of known size (256 MiB read, 256 MiB "
+                         "written) to calibrate hardware byte counters")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -399,6 +402,12 @@ def main():
         sys.exit(1)
     from paper_2011_10658_amd import lib
 
+    if a.copy_probe:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = x * 2.0
+        torch.cuda.synchronize()
+        log(f"== copy probe: {x.numel() * 4 >> 20} MiB read, {y.numel() * 4 >> 20} MiB written")
+        del x, y
     if a.workload == "finite_density":
         log("== finite-density workload")
         print(json.dumps(finite_density(lib, torch, a.steps)), flush=True)

@@ -211,16 +211,33 @@ int64_t key3(int a, int b, int c) { return ((int64_t)a * 4096 + b) * 4096 + c; }
 
 }  // namespace
 
+// Tile order of a launch.  The tiles of one output column panel (same job,
+// batch entry and column tile; all row tiles) read the same B panel, so
+// they are kept on one XCD: workgroup i runs on XCD i mod 8, and each
+// XCD's tile list takes whole panels, least-loaded XCD first.  Slot
+// 8 k + x holds the k-th tile of XCD x; XCDs with fewer tiles are padded
+// with empty tiles (job -1), which return at once.
+constexpr int NXCD = 8;
+
 static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, int sh) {
     const int TM = gemm_tm(sh), TN = gemm_tn(sh);
-    std::vector<GTile> tiles;
+    std::vector<std::vector<GTile>> per(NXCD);
     for (size_t j = 0; j < jobs.size(); ++j) {
         const GJob& J = jobs[j];
         const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
         for (int b = 0; b < J.batch; ++b)
-            for (int a = 0; a < tm; ++a)
-                for (int c = 0; c < tn; ++c) tiles.push_back(GTile{(int)j, b, a, c});
+            for (int c = 0; c < tn; ++c) {
+                int x = 0;
+                for (int y = 1; y < NXCD; ++y)
+                    if (per[y].size() < per[x].size()) x = y;
+                for (int a = 0; a < tm; ++a) per[x].push_back(GTile{(int)j, b, a, c});
+            }
     }
+    size_t slots = 0;
+    for (const auto& v : per) slots = std::max(slots, v.size());
+    std::vector<GTile> tiles(slots * NXCD, GTile{-1, 0, 0, 0});
+    for (int x = 0; x < NXCD; ++x)
+        for (size_t k = 0; k < per[x].size(); ++k) tiles[k * NXCD + x] = per[x][k];
     return tiles;
 }
 

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(256) void k_brgemm_bf16(const GJob* __restrict__ jo
     __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];
     const GTile tl = tiles[blockIdx.x];
+    if (tl.job < 0) return;   // padding of the XCD-ordered tile list
     const GJob J = jobs[tl.job];
     const int tid = threadIdx.x;
     const int lane = tid & 63;

@@ -46,7 +46,7 @@ struct GJob {
 
 // Work item of one workgroup: tile (tm, tn) of batch item b of job j.
 struct GTile {
-    int job, b, tm, tn;
+    int job, b, tm, tn;   // job < 0: an empty slot (the workgroup returns)
 };
 
 // Workgroup tile shapes of the block GEMM (rows x cols of the output).

@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
     __shared__ T As[2][KC][TM + PAD];
     __shared__ T Bs[2][KC][TN + PAD];
     const GTile tl = tiles[blockIdx.x];
+    if (tl.job < 0) return;   // padding of the XCD-ordered tile list
     const GJob J = jobs[tl.job];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
