@@ -36,7 +36,9 @@ __device__ __forceinline__ P* at(const GRef& r, const Bases& bs) {
 // K advances in chunks of KB = 32, one MFMA depth.  LDS holds the chunk
 // row-major with k contiguous (As[m][k], Bs[n][k]) so that every lane reads
 // its 8 consecutive k of one row as a single 16-byte access; rows are
-// padded by 8 elements to spread the rows over the banks.
+// padded by 8 elements to spread the rows over the banks.  The stage is
+// double-buffered (one barrier per chunk) and every thread's elements sit
+// at fixed strides from its first one (all tile extents divide 256).
 constexpr int KB = 32;
 constexpr int KP = KB + 8;
 
@@ -47,8 +49,8 @@ __global__ __launch_bounds__(256) void k_brgemm_bf16(const GJob* __restrict__ jo
     constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
     constexpr int AE = TM * KB / 256;
     constexpr int BE = TN * KB / 256;
-    __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TM][KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN][KP];
     const GTile tl = tiles[blockIdx.x];
     if (tl.job < 0) return;   // padding of the XCD-ordered tile list
     const GJob J = jobs[tl.job];
@@ -66,7 +68,11 @@ __global__ __launch_bounds__(256) void k_brgemm_bf16(const GJob* __restrict__ jo
 #pragma unroll
         for (int j = 0; j < BN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     uint16_t ra[AE], rb[BE];
-    int bcol[BE];
+    constexpr int ASA = 256 / KB, ASB = 256 / TM;
+    constexpr int BSB = 256 / KB, BSN = 256 / TN;
+    const int t_kc = tid % KB, t_kq = tid / KB;
+    const int t_tm = tid % TM, t_tq = tid / TM;
+    const int t_tn = tid % TN, t_nq = tid / TN;
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
         const uint16_t* Bb = at<const uint16_t>(P.B, bases) + (int64_t)tl.b * P.bsB;
@@ -90,78 +96,70 @@ __global__ __launch_bounds__(256) void k_brgemm_bf16(const GJob* __restrict__ jo
         const uint16_t* Ab = at<const uint16_t>(P.A, bases) + (int64_t)tl.b * P.bsA;
         const bool scale = alpha != 1.0f;
         const int nchunk = (P.K + KB - 1) / KB;
-        if (!P.tB) {
-#pragma unroll
-            for (int e = 0; e < BE; ++e) {
-                const int gn = n0 + (tid + e * 256) % TN;
-                bcol[e] = P.nsb ? (int)((gn / P.nsb) * P.nob + gn % P.nsb) : gn;
-            }
+        const int am0 = P.tA ? t_tm : t_kq, amE = P.tA ? 0 : ASA;
+        const int ak0 = P.tA ? t_tq : t_kc, akE = P.tA ? ASB : 0;
+        const int64_t akm = P.tA ? (int64_t)P.lda : 1;
+        const int64_t aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
+        const int64_t abase = P.tA ? (int64_t)ak0 * P.lda + m0 + am0 : (int64_t)(m0 + am0) * P.lda + ak0;
+        const int bn0 = P.tB ? t_kq : t_tn, bnE = P.tB ? BSB : 0;
+        const int bk0 = P.tB ? t_kc : t_nq, bkE = P.tB ? 0 : BSN;
+        const int64_t bkm = P.tB ? 1 : (int64_t)P.ldb;
+        const int64_t bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
+        int64_t bbase;
+        if (P.tB) {
+            bbase = (int64_t)(n0 + bn0) * P.ldb + bk0;
+        } else {
+            const int gn = n0 + bn0;
+            const int64_t col = P.nsb ? (int64_t)(gn / P.nsb) * P.nob + gn % P.nsb : gn;
+            bbase = (int64_t)bk0 * P.ldb + col;
         }
         for (int r = 0; r < P.nred; ++r) {
-            const uint16_t* A = Ab + (int64_t)r * P.rsA;
-            const uint16_t* B = Bb + (int64_t)r * P.rsB;
-            auto fetch = [&](int k0) {
+            const uint16_t* A = Ab + (int64_t)r * P.rsA + abase;
+            const uint16_t* B = Bb + (int64_t)r * P.rsB + bbase;
+            auto fetch = [&](int c) {
+                const int k0 = c * KB;
+                const uint16_t* pa = A + k0 * akm;
+                const uint16_t* pb = B + k0 * bkm;
 #pragma unroll
                 for (int e = 0; e < AE; ++e) {
-                    const int idx = tid + e * 256;
-                    int m, k;
-                    if (P.tA) { m = idx % TM; k = idx / TM; }
-                    else { k = idx % KB; m = idx / KB; }
-                    const int gm = m0 + m, gk = k0 + k;
                     uint16_t v = 0;
-                    if (gm < J.M && gk < P.K)
-                        v = P.tA ? A[(int64_t)gk * P.lda + gm] : A[(int64_t)gm * P.lda + gk];
+                    if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
                     ra[e] = scale ? f2bf(alpha * bf2f(v)) : v;
                 }
 #pragma unroll
                 for (int e = 0; e < BE; ++e) {
-                    const int idx = tid + e * 256;
-                    int k, n;
-                    if (P.tB) { k = idx % KB; n = idx / KB; }
-                    else { n = idx % TN; k = idx / TN; }
-                    const int gn = n0 + n, gk = k0 + k;
                     uint16_t v = 0;
-                    if (gn < J.N && gk < P.K)
-                        v = P.tB ? B[(int64_t)gn * P.ldb + gk] : B[(int64_t)gk * P.ldb + bcol[e]];
+                    if (n0 + bn0 + e * bnE < J.N && k0 + bk0 + e * bkE < P.K) v = pb[e * bes];
                     rb[e] = v;
                 }
             };
-            auto stash = [&]() {
+            auto stash = [&](int buf) {
 #pragma unroll
-                for (int e = 0; e < AE; ++e) {
-                    const int idx = tid + e * 256;
-                    int m, k;
-                    if (P.tA) { m = idx % TM; k = idx / TM; }
-                    else { k = idx % KB; m = idx / KB; }
-                    As[m][k] = ra[e];
-                }
+                for (int e = 0; e < AE; ++e) As[buf][am0 + e * amE][ak0 + e * akE] = ra[e];
 #pragma unroll
-                for (int e = 0; e < BE; ++e) {
-                    const int idx = tid + e * 256;
-                    int k, n;
-                    if (P.tB) { k = idx % KB; n = idx / KB; }
-                    else { n = idx % TN; k = idx / TN; }
-                    Bs[n][k] = rb[e];
-                }
+                for (int e = 0; e < BE; ++e) Bs[buf][bn0 + e * bnE][bk0 + e * bkE] = rb[e];
             };
+            __syncthreads();
             fetch(0);
+            stash(0);
+            __syncthreads();
             for (int c = 0; c < nchunk; ++c) {
-                __syncthreads();
-                stash();
-                __syncthreads();
-                if (c + 1 < nchunk) fetch((c + 1) * KB);
+                const int cur = c & 1;
+                if (c + 1 < nchunk) fetch(c + 1);
                 bf16x8 a[BM], b[BN];
 #pragma unroll
                 for (int i = 0; i < BM; ++i)
-                    a[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)&As[wm0 + i * 16 + lr][8 * lk]);
+                    a[i] = __builtin_bit_cast(bf16x8, *(const u16x8*)&As[cur][wm0 + i * 16 + lr][8 * lk]);
 #pragma unroll
                 for (int j = 0; j < BN; ++j)
-                    b[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)&Bs[wn0 + j * 16 + lr][8 * lk]);
+                    b[j] = __builtin_bit_cast(bf16x8, *(const u16x8*)&Bs[cur][wn0 + j * 16 + lr][8 * lk]);
 #pragma unroll
                 for (int i = 0; i < BM; ++i)
 #pragma unroll
                     for (int j = 0; j < BN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                if (c + 1 < nchunk) stash(cur ^ 1);
+                __syncthreads();
             }
         }
     }
