@@ -380,6 +380,102 @@ def finite_density(lib, torch, steps):
     }
 
 
+def adjoint_workload(lib, torch, steps, warmup, cpu_budget, no_cpu):
+    """Differentiation: one node with legs chi = 128 (charges -4..4, sizes
+    4,8,16,23,26,23,16,8,4), 24 terms of symmetric sector-preserving factors
+    (terms 0-7 carry g^2/2 at g^2 = 1), seed 4.  A step is the forward
+    H_eff application plus the full adjoint (node cotangent, every factor's
+    gradient, every coefficient's), FP32 GEMMs; the FP64 path beside it."""
+    from oracle import blocks as ob
+    from paper_2011_10658_amd import synth
+
+    leg = synth.C4_LEG
+    K = 24
+    terms = synth.single_node_terms(4, K, leg)
+    ops = [torch.from_numpy(np.concatenate([o[q].reshape(-1) for q, _ in leg])).cuda()
+           for _, *fs in terms for o in fs]
+    coefs = [0.5] * 8 + [1.0] * (K - 8)
+    spec = [(coefs[k], tuple(ops[3 * k + e].data_ptr() for e in range(3)), (0, 0, 0)) for k in range(K)]
+    res = {}
+    for name, dt in (("f64", lib.FP64), ("f32", lib.FP32)):
+        ctx = lib.Context(0)
+        ctx.set_precision(dt)
+        h = ctx.heff(leg, leg, leg, spec)
+        x = torch.from_numpy(synth.normal(4, 1, h.size)).cuda()
+        ybar = torch.from_numpy(synth.normal(4, 2, h.size)).cuda()
+        y, xbar = torch.empty_like(x), torch.empty_like(x)
+        opbar = [torch.empty_like(o) for o in ops]
+        ptrs = [g.data_ptr() for g in opbar]
+
+        def step():
+            h.matvec(x.data_ptr(), y.data_ptr())
+            return h.adjoint(x.data_ptr(), ybar.data_ptr(), xbar.data_ptr(), ptrs, True, K)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        # forward alone
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h.matvec(x.data_ptr(), y.data_ptr())
+        torch.cuda.synchronize()
+        fwd = (time.perf_counter() - t0) / steps
+        f_fwd, _ = h.flops()
+        f_xb, f_gr = h.adjoint_flops()
+        res[name] = dict(ms=1e3 * wall, fwd_ms=1e3 * fwd, adj_ms=1e3 * (wall - fwd),
+                         flops_fwd=f_fwd, flops_adj=f_xb + f_gr,
+                         tflops=(f_fwd + f_xb + f_gr) / wall / 1e12,
+                         adj_tflops=(f_xb + f_gr) / (wall - fwd) / 1e12 if wall > fwd else None,
+                         size=h.size)
+        log(f"  {name}: forward {res[name]['fwd_ms']:.3f} ms, forward+adjoint {res[name]['ms']:.3f} ms, "
+            f"{res[name]['tflops']:.2f} TFLOP/s (adjoint {f_xb + f_gr:.3e} flops, "
+            f"{(f_xb + f_gr) / f_fwd:.2f}x forward)")
+        h.close()
+        ctx.close()
+    cpu = None
+    if not no_cpu:
+        from oracle import heff as oh
+        d = [(coefs[k], *(ob.op_to_dense(o, leg, 0) for o in t[1:])) for k, t in enumerate(terms)]
+        xs = synth.normal(4, 1, res["f32"]["size"])
+        yb = synth.normal(4, 2, res["f32"]["size"])
+        xd, ybd = ob.to_dense(xs, leg, leg, leg), ob.to_dense(yb, leg, leg, leg)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oh.apply_dense(xd, d[:1])
+            oh.adjoint_dense(xd, ybd, d[:1])
+            n += 1
+            if time.perf_counter() - t0 >= min(cpu_budget, 30.0) or n >= 20:
+                break
+        el = time.perf_counter() - t0
+        per_term = (res["f32"]["flops_fwd"] + res["f32"]["flops_adj"]) / K
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count()
+        cpu = dict(value=per_term * n / el / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
+                   sample=f"{n} oracle forward + reverse-mode applications of one of the 24 terms "
+                          f"(dense NumPy float64 definition), {el:.1f} s; flops counted per term as "
+                          f"the library counts them")
+    r = res["f32"]
+    return {
+        "metric": METRIC, "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "H_eff forward + hand-written adjoint, one node, legs chi=128 "
+                               "(charges -4..4), 24 terms, seed 4", "entries": r["size"]},
+        "forward_ms": r["fwd_ms"], "adjoint_ms": r["adj_ms"], "adjoint_tflops": r["adj_tflops"],
+        "adjoint_over_forward_flops": r["flops_adj"] / r["flops_fwd"],
+        "fp64_path": res["f64"],
+        "roofline": None, "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,7 +483,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("sweep", "batched", "finite_density"), default="sweep")
+    ap.add_argument("--workload", choices=("sweep", "batched", "finite_density", "adjoint"),
+                    default="sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one elementwise pass of known size (256 MiB read, 256 MiB "
                          "written) to calibrate hardware byte counters")
@@ -408,6 +505,11 @@ def main():
         torch.cuda.synchronize()
         log(f"== copy probe: {x.numel() * 4 >> 20} MiB read, {y.numel() * 4 >> 20} MiB written")
         del x, y
+    if a.workload == "adjoint":
+        log("== adjoint workload")
+        print(json.dumps(adjoint_workload(lib, torch, a.steps, a.warmup, a.cpu_budget,
+                                          a.no_cpu_baseline)), flush=True)
+        return
     if a.workload == "finite_density":
         log("== finite-density workload")
         print(json.dumps(finite_density(lib, torch, a.steps)), flush=True)

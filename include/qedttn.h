@@ -303,6 +303,12 @@ int qed_heff_flops(qed_heff* h, double* flops, double* bytes);
 int qed_heff_matvec_adjoint(qed_heff* h, const double* x, const double* ybar, double* xbar,
                             double* const* opbar, double* coefbar);
 
+/* Algorithmic flops of one adjoint call: the transposed-factor matvec for
+ * xbar, and the mode products plus two-tensor contractions for all factor
+ * gradients (the coefficient dot products are not counted).  Builds the
+ * adjoint schedule if no adjoint call has yet. */
+int qed_heff_adjoint_flops(qed_heff* h, double* xbar_flops, double* grad_flops);
+
 /* ---------------------------------------------------------------- */
 /* batched node updates                                              */
 /* ---------------------------------------------------------------- */

@@ -749,6 +749,16 @@ int qed_heff_flops(qed_heff* h, double* flops, double* bytes) {
     return QED_OK;
 }
 
+int qed_heff_adjoint_flops(qed_heff* h, double* xbar_flops, double* grad_flops) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    return guard(h->owner, [&] {
+        if (!h->h.adj.built) h->h.build_adjoint();
+        if (xbar_flops) *xbar_flops = h->h.adj.xbar.flops;
+        if (grad_flops) *grad_flops = h->h.adj.grads.flops;
+        return (int)QED_OK;
+    });
+}
+
 int qed_autotune(qed_ctx* ctx, const char* cache_path) {
     return guard(ctx, [&] {
         Tuner& t = C(ctx).tuner;

@@ -114,6 +114,7 @@ SIGNATURES = {
     "qed_heff_lanczos": [_P, _P, _I, _DP, _DP],
     "qed_heff_flops": [_P, _DP, _DP],
     "qed_heff_matvec_adjoint": [_P, _P, _P, _P, C.POINTER(_P), _DP],
+    "qed_heff_adjoint_flops": [_P, _DP, _DP],
 }
 
 
@@ -381,6 +382,11 @@ class Heff:
         f, b = C.c_double(), C.c_double()
         _check(self.ctx.lib.qed_heff_flops(self.h, C.byref(f), C.byref(b)))
         return f.value, b.value
+
+    def adjoint_flops(self):
+        a, b = C.c_double(), C.c_double()
+        self.ctx._c(self.ctx.lib.qed_heff_adjoint_flops(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def adjoint(self, x_ptr, ybar_ptr, xbar_ptr=0, opbar_ptrs=None, want_coefbar=False, K=None):
         """Reverse mode of y = H_eff x.  opbar_ptrs: list of 3K device

@@ -189,6 +189,11 @@ def test_c4_adjoint_sampled_against_oracle(ctx):
     opbar = [torch.full_like(ops[i], np.nan) if i // 3 in sample else None for i in range(3 * K4)]
     cbar = h.adjoint(xd.data_ptr(), ybd.data_ptr(), xbar.data_ptr(),
                      [0 if g is None else g.data_ptr() for g in opbar], True, K4)
+    # the transposed schedule of sector-preserving square factors costs what
+    # the forward one costs; every factor gradient adds work
+    f_fwd, _ = h.flops()
+    f_xb, f_gr = h.adjoint_flops()
+    assert f_xb == f_fwd and f_gr > f_fwd
     h.close()
     legs = (C4, C4, C4)
     dterms = [(coefs[k], *(oblocks.op_to_dense(o, C4, 0) for o in t[1:])) for k, t in enumerate(terms)]
