@@ -53,6 +53,7 @@ def make_ctx(lib, dtype):
     nu_max = 10.0 * max(1.0, 1.0, 0.5 * g2e, 0.5 * g2m)
     ctx.set_penalty(nu_max, 4, 4)
     ctx.set_lanczos(24, 4, 1e-10)
+    ctx.set_lanczos_schedule(1e-4, 0.1)    # tol_s = max(1e-10, 1e-4 10^-s)
     ctx.set_precision(dtype, 1)
     ctx.build_hamiltonian()
     ctx.init_state(SEED)
@@ -569,7 +570,8 @@ def main():
             "workload": "TTN sweep, 2x2x2 open-lattice compact QED, free-flux boundary "
                         "(d=267 per site), Q=0, m=t=1, g^2=1 (g_e^2=1, g_m^2=8), chi=64",
             "lattice": "2x2x2", "bond_dim": CHI, "charge": 0, "seed": SEED,
-            "lanczos": "24 steps x <=4 cycles, tol 1e-10 (FP32 floor 2e-6, BF16 floor 3.9e-3), "
+            "lanczos": "24 steps x <=4 cycles, tol max(1e-10, 1e-4 10^-s) in sweep s "
+                       "(FP32 floor 2e-6, BF16 floor 3.9e-3), "
                        "FP64 Rayleigh quotient per update",
             "timed": "sweeps resumed from the converged FP64 state (checkpoint after the "
                      "warm-up trajectory), after one untimed sweep",

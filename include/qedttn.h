@@ -143,6 +143,12 @@ int qed_set_bond_dim(qed_ctx* ctx, int chi);
  * is <= tol |theta| or `max_cycles` cycles ran (tol = 0: always all). */
 int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol);
 
+/* Eigensolver precision raised sweep by sweep (Methods: the Arnoldi
+ * precision is increased at every sweep): in sweep s the node updates use
+ * the tolerance max(tol, tol0 * factor^s), tol from qed_set_lanczos.
+ * tol0 = 0 (the default) switches the schedule off; 0 < factor < 1. */
+int qed_set_lanczos_schedule(qed_ctx* ctx, double tol0, double factor);
+
 /* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16).  refine != 0 adds one
  * FP64 Rayleigh quotient per node update on the reduced-precision paths
  * (the node energy then carries an error second order in the eigenvector

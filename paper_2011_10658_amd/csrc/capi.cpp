@@ -273,6 +273,17 @@ int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol) {
     });
 }
 
+int qed_set_lanczos_schedule(qed_ctx* ctx, double tol0, double factor) {
+    return guard(ctx, [&] {
+        if (!(tol0 >= 0.0) || !(factor > 0.0 && factor < 1.0))
+            fail(QED_ERR_INVALID_ARG, "Lanczos schedule: tol0 >= 0 and 0 < factor < 1");
+        Params& P = C(ctx).prm;
+        P.lz_tol0 = tol0;
+        P.lz_factor = factor;
+        return QED_OK;
+    });
+}
+
 int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine) {
     return guard(ctx, [&] {
         if (gemm_dtype != QED_FP64 && gemm_dtype != QED_FP32 && gemm_dtype != QED_BF16)

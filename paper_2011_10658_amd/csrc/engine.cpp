@@ -694,18 +694,23 @@ void split_long_reductions(Plan& P, int s) {
 
 void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs) {
     if (m < n) fail(QED_ERR_BAD_STATE, "QR of a wide matrix");
-    if (n > QR_COLS) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 256 columns");
-    if (m <= QR_ROWS) {
+    if (n > 8192) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 8192 columns");
+    // sectors up to QR_COLS wide take the blocked kernel (at most QR_ROWS
+    // rows per workgroup); wider ones the unblocked kernel
+    const bool blocked = n <= QR_COLS;
+    const int64_t direct_max = blocked ? QR_ROWS : std::max<int64_t>(4096, 16 * (int64_t)n);
+    if (m <= direct_max) {
         DBuf scratch(dev, (size_t)m * n * sizeof(double));
         QRMat q{0, 0, m, rrs, rcs, (int)m, n};
         DBuf dq(dev, sizeof(QRMat));
         dev->upload(dq.p, &q, sizeof(QRMat));
-        launch_qr(dq.as<QRMat>(), 1, M, scratch.as<double>(), R, dev->stream);
+        launch_qr(dq.as<QRMat>(), 1, m, n, M, scratch.as<double>(), R, dev->stream);
         dev->check(hipGetLastError(), "qr launch");
         return;
     }
-    // chunks of b rows (the last one takes the remainder, < 2b <= QR_ROWS)
-    const int64_t b = std::max<int64_t>(512, 4 * (int64_t)n);
+    // chunks of b rows (the last one takes the remainder, < 2b, which is at
+    // most QR_ROWS on the blocked path)
+    const int64_t b = blocked ? std::max<int64_t>(512, 4 * (int64_t)n) : std::max<int64_t>(2048, 4 * (int64_t)n);
     const int P = (int)(m / b);
     const int64_t ls = (int64_t)P * n;   // rows of the stacked R factors
     DBuf S(dev, (size_t)ls * n * sizeof(double));
@@ -718,7 +723,9 @@ void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t
     }
     DBuf dq(dev, qs.size() * sizeof(QRMat));
     dev->upload(dq.p, qs.data(), qs.size() * sizeof(QRMat));
-    launch_qr(dq.as<QRMat>(), P, M, T.as<double>(), S.as<double>(), dev->stream);
+    int64_t maxrows = 0;
+    for (const QRMat& q : qs) maxrows = std::max<int64_t>(maxrows, q.rows);
+    launch_qr(dq.as<QRMat>(), P, maxrows, n, M, T.as<double>(), S.as<double>(), dev->stream);
     dev->check(hipGetLastError(), "qr launch");
     tsqr(dev, S.as<double>(), ls, n, R, rrs, rcs);
     // Q = blockdiag(Q1_i) * Q2: chunk i of Q is Q1_i Q2[i n .. (i+1) n)

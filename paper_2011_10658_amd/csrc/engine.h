@@ -43,7 +43,10 @@ void launch_ritz(double*, const double*, int64_t, const double*, int64_t, const 
 void launch_normalise_sign(double*, int64_t, const double*, double*, int64_t*, double*,
                            hipStream_t);
 void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_t);
-void launch_qr(const QRMat*, int, double*, double*, double*, hipStream_t);
+// blocked kernel when every matrix has rows <= QR_ROWS and cols <= QR_COLS,
+// else the unblocked one
+void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, double*, double*, double*,
+               hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
 
@@ -297,6 +300,7 @@ struct Params {
     int Q = 0, chi = 16;
     int lz_steps = 30, lz_cycles = 1;
     double lz_tol = 0.0;
+    double lz_tol0 = 0.0, lz_factor = 0.1;   // per-sweep tolerance schedule (off: tol0 = 0)
     int dtype = QED_FP64, refine = 1;
     bool have_lattice = false, have_couplings = false;
 };

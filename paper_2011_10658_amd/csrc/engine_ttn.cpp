@@ -172,8 +172,7 @@ OpP Engine::qr_toward(int n, int which) {
     std::vector<QRMat> small;
     for (int s = 0; s < ns; ++s) {
         const int n_s = L.n[s];
-        if (n_s > QR_COLS) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 256 columns");
-        if (rows[s] <= QR_ROWS) {
+        if (rows[s] <= QR_ROWS && n_s <= QR_COLS) {
             small.push_back(QRMat{mat[s], R->lay.off[s], rows[s], n_s, 1, (int)rows[s], n_s});
         } else {
             tsqr(dev, packed.as<double>() + mat[s], rows[s], n_s, (double*)R->d64->p + R->lay.off[s],
@@ -184,8 +183,8 @@ OpP Engine::qr_toward(int n, int which) {
         DBuf dqm(dev, small.size() * sizeof(QRMat));
         dev->upload(dqm.p, small.data(), small.size() * sizeof(QRMat));
         DBuf qbuf(dev, tot * sizeof(double));
-        launch_qr(dqm.as<QRMat>(), (int)small.size(), packed.as<double>(), qbuf.as<double>(),
-                  (double*)R->d64->p, dev->stream);
+        launch_qr(dqm.as<QRMat>(), (int)small.size(), QR_ROWS, QR_COLS, packed.as<double>(),
+                  qbuf.as<double>(), (double*)R->d64->p, dev->stream);
     }
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 1, dev->stream);
     dev->check(hipGetLastError(), "qr launch");
@@ -432,8 +431,11 @@ double Engine::update(int n, double nu) {
     // an FP32 Krylov recurrence cannot resolve residuals below ~eps32 |H|:
     // restarts past that point only repeat work (the FP64 Rayleigh quotient
     // below fixes the energy)
-    const double tol = dtype == QED_FP64 ? P.lz_tol
-                       : std::max(P.lz_tol, dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32);
+    // the precision schedule of the sweeps (raised sweep by sweep)
+    double tol_s = P.lz_tol;
+    if (P.lz_tol0 > 0.0) tol_s = std::max(tol_s, P.lz_tol0 * std::pow(P.lz_factor, (double)sweeps_done));
+    const double tol = dtype == QED_FP64 ? tol_s
+                       : std::max(tol_s, dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32);
     LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol);
     matvecs += R.matvecs;
     flops += R.matvecs * plan.flops;

@@ -901,10 +901,111 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
     }
 }
 
-void launch_qr(const QRMat* mats, int nmats, double* packed, double* qbuf, double* rbuf,
-               hipStream_t s) {
+// Unblocked Householder QR for sectors wider than QR_COLS (no size limit
+// beyond LDS for 2 cols + 4 doubles): one column-major rows x cols matrix
+// (leading dimension ld) per workgroup, rows >= cols, reflectors applied
+// to the trailing columns one at a time, waves over columns.  On exit the matrix holds the explicit Q
+// with orthonormal columns and R is written through (rout, rrs, rcs); signs
+// are fixed so that diag(R) >= 0.  `qbuf` is scratch with the same layout
+// as the input.  Zero columns (rank deficiency) get tau = 0 and R_jj = 0,
+// and Q still has orthonormal columns.
+__global__ __launch_bounds__(256) void k_householder_qr_wide(const QRMat* __restrict__ mats,
+                                                        double* __restrict__ packed,
+                                                        double* __restrict__ qbuf,
+                                                        double* __restrict__ rbuf) {
+    extern __shared__ double lds[];
+    const QRMat Mt = mats[blockIdx.x];
+    const int m = Mt.rows, n = Mt.cols;
+    const int64_t ld = Mt.ld;
+    double* A = packed + Mt.mat;
+    double* Qm = qbuf + Mt.mat;
+    double* R = rbuf + Mt.rout;
+    double* tau = lds;          // n
+    double* diag = lds + n;     // n  (R_jj)
+    double* red = lds + 2 * n;  // 4
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = j + tid; i < m; i += 256) s += A[(int64_t)j * ld + i] * A[(int64_t)j * ld + i];
+        s = wave_sum(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        if (tid == 0) {
+            const double norm2 = ((red[0] + red[1]) + red[2]) + red[3];
+            const double x0 = A[(int64_t)j * ld + j];
+            const double nrm = sqrt(norm2);
+            if (nrm == 0.0) {
+                tau[j] = 0.0;
+                diag[j] = 0.0;
+            } else {
+                const double al = x0 >= 0.0 ? -nrm : nrm;
+                const double v0 = x0 - al;
+                const double vtv = v0 * v0 + (norm2 - x0 * x0);
+                tau[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+                diag[j] = al;
+                A[(int64_t)j * ld + j] = v0;
+            }
+        }
+        __syncthreads();
+        const double tj = tau[j];
+        if (tj != 0.0) {
+            for (int k = j + 1 + wave; k < n; k += 4) {
+                double d = 0.0;
+                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * ld + i] * A[(int64_t)k * ld + i];
+                d = wave_sum(d);
+                d = __shfl(d, 0, 64);
+                const double f = tj * d;
+                for (int i = j + lane; i < m; i += 64) A[(int64_t)k * ld + i] -= f * A[(int64_t)j * ld + i];
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += 256) {
+        const int r = e / n, c = e % n;
+        R[r * Mt.rrs + c * Mt.rcs] = c > r ? A[(int64_t)c * ld + r] : (c == r ? diag[r] : 0.0);
+    }
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
+        const int c = (int)(e / m), r = (int)(e % m);
+        Qm[(int64_t)c * ld + r] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj != 0.0) {
+            for (int k = j + wave; k < n; k += 4) {
+                double d = 0.0;
+                for (int i = j + lane; i < m; i += 64) d += A[(int64_t)j * ld + i] * Qm[(int64_t)k * ld + i];
+                d = wave_sum(d);
+                d = __shfl(d, 0, 64);
+                const double f = tj * d;
+                for (int i = j + lane; i < m; i += 64) Qm[(int64_t)k * ld + i] -= f * A[(int64_t)j * ld + i];
+            }
+        }
+        __syncthreads();
+    }
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
+        const int c = (int)(e / m), r = (int)(e % m);
+        const double q = Qm[(int64_t)c * ld + r];
+        A[(int64_t)c * ld + r] = diag[c] < 0.0 ? -q : q;
+    }
+    for (int e = tid; e < n * n; e += 256) {
+        const int r = e / n, c = e % n;
+        if (diag[r] < 0.0) R[r * Mt.rrs + c * Mt.rcs] = -R[r * Mt.rrs + c * Mt.rcs];
+    }
+}
+
+void launch_qr(const QRMat* mats, int nmats, int64_t maxrows, int maxcols, double* packed,
+               double* qbuf, double* rbuf, hipStream_t s) {
     if (nmats <= 0) return;
-    hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), 0, s, mats, packed, qbuf, rbuf);
+    if (maxrows <= QR_ROWS && maxcols <= QR_COLS) {
+        hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), 0, s, mats, packed, qbuf, rbuf);
+        return;
+    }
+    const size_t lds = (size_t)(2 * maxcols + 4) * sizeof(double);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_householder_qr_wide,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_householder_qr_wide, dim3(nmats), dim3(256), lds, s, mats, packed, qbuf, rbuf);
 }
 
 // ---------------------------------------------------------------------

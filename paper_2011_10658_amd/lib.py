@@ -80,6 +80,7 @@ SIGNATURES = {
     "qed_set_charge_sector": [_P, _I],
     "qed_set_bond_dim": [_P, _I],
     "qed_set_lanczos": [_P, _I, _I, _D],
+    "qed_set_lanczos_schedule": [_P, C.c_double, C.c_double],
     "qed_set_precision": [_P, _I, _I],
     "qed_build_hamiltonian": [_P],
     "qed_get_local_dims": [_P, _IP],
@@ -229,6 +230,9 @@ class Context:
 
     def set_lanczos(self, steps, cycles=1, tol=0.0):
         self._c(self.lib.qed_set_lanczos(self.h, steps, cycles, tol))
+
+    def set_lanczos_schedule(self, tol0, factor=0.1):
+        self._c(self.lib.qed_set_lanczos_schedule(self.h, tol0, factor))
 
     def set_precision(self, dtype, refine=1):
         self._c(self.lib.qed_set_precision(self.h, dtype, refine))

@@ -116,6 +116,10 @@ def test_error_paths():
     assert e.value.code == -2
     with pytest.raises(lib.QedError):
         ctx.set_lanczos(0)
+    with pytest.raises(lib.QedError):
+        ctx.set_lanczos_schedule(1e-4, 1.5)
+    ctx.set_lanczos_schedule(1e-4, 0.1)
+    ctx.set_lanczos_schedule(0.0)
     with pytest.raises(lib.QedError) as e:
         lib.node_blocks([(0, 1), (0, 2)], [(0, 1)], [(0, 1)])
     assert lib.physical_line(1.0) == (1.0, 8.0)

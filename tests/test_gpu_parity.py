@@ -342,3 +342,38 @@ def test_isometries_after_free_flux_sweep(ctx):
             tall += rows[ip] > 2048
     assert tall > 0
     assert worst < 1e-12, worst
+
+
+@pytest.mark.parametrize("g2", [0.5, 1.0, 4.0])
+def test_config2_zero_flux_against_ed(ctx, g2):
+    """2x2x2 open lattice with zero-flux boundary (13 states per corner site,
+    3197 gauge-invariant states), m = t = 1, g^2 on the physical line,
+    driven penalty, chi = 64 and 128: each converged TTN energy respects the
+    variational bound of the exact ground energy, the energy does not rise
+    with chi, and the charge and rishon constraints hold.  (The gap to the
+    exact energy is a truncation of the ansatz: about 1% at chi = 64, 0.1%
+    at chi = 128, 2e-4 at chi = 256 for g^2 = 1.)"""
+    g2e, g2m = lib.physical_line(g2, 1.0)
+    cpl = Couplings(t=1.0, m=1.0, g2e=g2e, g2m=g2m)
+    e0 = OriginalED(Lattice(2, 2, 2), cpl).spectrum()[0]
+    nu_max = 10.0 * max(1.0, 1.0, 0.5 * g2e, 0.5 * g2m)
+    energies = []
+    for chi in (64, 128):
+        ctx.set_lattice(2, 2, 2, lib.BC_OPEN_ZERO_FLUX)
+        ctx.set_couplings(1.0, 1.0, g2e, g2m)
+        ctx.set_charge_sector(0)
+        ctx.set_bond_dim(chi)
+        ctx.set_penalty(nu_max, 4, 4)
+        ctx.set_lanczos(24, 4, 1e-11)
+        ctx.set_precision(lib.FP64)
+        ctx.build_hamiltonian()
+        ctx.init_state(2011)
+        reps = ctx.sweep(14)
+        e = reps[-1]["energy"]
+        assert abs(e - reps[-2]["energy"]) <= 1e-7 * abs(e)
+        assert e >= e0 - 1e-9 * abs(e0), (chi, e, e0)
+        ob = ctx.observables()
+        assert abs(ob["Q"]) < 1e-10 and ob["deltaL"] < 1e-6
+        energies.append(e)
+    assert energies[1] <= energies[0] + 1e-9 * abs(e0), energies
+    assert energies[1] - e0 <= 1e-2 * abs(e0), (energies, e0)
