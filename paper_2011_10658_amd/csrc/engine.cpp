@@ -15,6 +15,8 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -320,15 +322,32 @@ void Prof::harvest() {
         float t = 0.0f;
         if (hipEventElapsedTime(&t, ev[i].first, ev[i].second) == hipSuccess) ms += t;
         flops += ev_flops[i];
+        auto& k = by_key[i < ev_key.size() ? ev_key[i] : -1];
+        k[0] += 1.0;
+        k[1] += t;
+        k[2] += ev_flops[i];
         (void)hipEventDestroy(ev[i].first);
         (void)hipEventDestroy(ev[i].second);
     }
     ev.clear();
     ev_flops.clear();
+    ev_key.clear();
+}
+
+void Prof::report() const {
+    static const char* shapes[] = {"64x64", "128x32", "32x128"};
+    for (const auto& kv : by_key) {
+        const int st = kv.first / 16, sh = kv.first % 16;
+        const auto& v = kv.second;
+        std::fprintf(stderr, "[qedttn] gemm stage %d tile %s: %.0f launches, %.3f ms, %.3e flops, %.2f TFLOP/s\n",
+                     st, sh < 3 ? shapes[sh] : "?", v[0], v[1], v[2], v[1] > 0 ? v[2] / v[1] / 1e9 : 0.0);
+    }
 }
 
 void Prof::reset() {
     harvest();
+    if (std::getenv("QEDTTN_TRACE") && !by_key.empty()) report();
+    by_key.clear();
     launches = 0;
     ms = flops = 0.0;
 }
@@ -356,6 +375,7 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
             prof->record_begin(dev->stream, e1);
             prof->ev.push_back({e0, e1});
             prof->ev_flops.push_back(s < stage_flops.size() ? stage_flops[s] : 0.0);
+            prof->ev_key.push_back((int)s * 16 + shape[s]);
             prof->launches += 1;
         }
     }
@@ -369,6 +389,10 @@ void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
     std::map<int64_t, int> bidx;
     for (int b = 0; b < tab.nblk(); ++b) bidx[key3(tab.s[0][b], tab.s[1][b], tab.s[2][b])] = b;
     std::vector<std::vector<GProd>> groups(tab.nblk());
+    // terms without a factor on l end in stage 0 (factor on p only) or in
+    // stage 1 (last factor on r): they are summed there, per output block,
+    // into one partial that stage 2 adds once
+    std::vector<std::vector<GProd>> acc0(tab.nblk()), acc1(tab.nblk());
     for (const HTerm& t : terms) {
         if (t.coef == 0.0) continue;
         for (int b = 0; b < tab.nblk(); ++b) {
@@ -389,10 +413,26 @@ void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
             auto it = bidx.find(key3(os[0], os[1], os[2]));
             if (it == bidx.end()) continue;
             const int ob = it->second;
+            int M, N, ldc, batch;
+            int64_t bsC;
+            if (t.op[2] && !t.op[1] && !t.op[0]) {
+                GRef opblk = gabs((const char*)t.op[2]->data(P.dtype) + t.op[2]->lay.off[cur.s[2]] * B.esize);
+                const int nout = legs[2].n[os[2]];
+                acc0[ob].push_back(Builder::mode_prod(cur, 2, opblk, nout, t.coef, M, N, ldc, batch, bsC));
+                B.add_flops(0, 2.0 * cur.n[0] * cur.n[1] * cur.n[2] * nout);
+                continue;
+            }
             if (t.op[2]) {
                 BV nxt;
                 B.mode(0, cur, 2, *t.op[2], legs[2], nxt);
                 cur = nxt;
+            }
+            if (t.op[1] && !t.op[0]) {
+                GRef opblk = gabs((const char*)t.op[1]->data(P.dtype) + t.op[1]->lay.off[cur.s[1]] * B.esize);
+                const int nout = legs[1].n[os[1]];
+                acc1[ob].push_back(Builder::mode_prod(cur, 1, opblk, nout, t.coef, M, N, ldc, batch, bsC));
+                B.add_flops(1, 2.0 * cur.n[0] * cur.n[1] * cur.n[2] * nout);
+                continue;
             }
             if (t.op[1]) {
                 BV nxt;
@@ -404,8 +444,6 @@ void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
                 const int nout = legs[0].n[os[0]];
                 GRef opblk = gabs((const char*)t.op[0]->data(P.dtype) +
                                   t.op[0]->lay.off[cur.s[0]] * B.esize);
-                int M, N, ldc, batch;
-                int64_t bsC;
                 p = Builder::mode_prod(cur, 0, opblk, nout, t.coef, M, N, ldc, batch, bsC);
                 B.add_flops(2, 2.0 * cur.n[0] * cur.n[1] * cur.n[2] * nout);
             } else {
@@ -418,6 +456,46 @@ void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
             groups[ob].push_back(p);
         }
     }
+    // the partial-sum jobs go first in their stages (their tiles run longest)
+    std::vector<GJob> first0, first1;
+    for (int b = 0; b < tab.nblk(); ++b) {
+        const int n0 = legs[0].n[tab.s[0][b]], n1 = legs[1].n[tab.s[1][b]],
+                  n2 = legs[2].n[tab.s[2][b]];
+        const int64_t sz = (int64_t)n0 * n1 * n2;
+        for (int st = 0; st < 2; ++st) {
+            auto& list = st == 0 ? acc0[b] : acc1[b];
+            if (list.empty()) continue;
+            B.stage(st);
+            GRef part = B.ws(sz);
+            GJob j{};
+            j.C = part;
+            j.batch = 1;
+            if (st == 0) {   // rows (i0, i1), columns i2
+                j.M = n0 * n1;
+                j.N = n2;
+                j.ldc = n2;
+            } else {         // rows i1, columns (i0, i2) split like the input
+                j.M = n1;
+                j.N = n0 * n2;
+                j.ldc = n2;
+                j.nsc = n2;
+                j.noc = (int64_t)n1 * n2;
+            }
+            j.p0 = (int)P.prods[st].size();
+            for (auto& p : list) P.prods[st].push_back(p);
+            j.p1 = (int)P.prods[st].size();
+            (st == 0 ? first0 : first1).push_back(j);
+            GProd add{};
+            add.ident = 1;
+            add.B = part;
+            add.ldb = n1 * n2;
+            add.alpha = 1.0;
+            add.nred = 1;
+            groups[b].push_back(add);
+        }
+    }
+    if (!first0.empty()) P.jobs[0].insert(P.jobs[0].begin(), first0.begin(), first0.end());
+    if (!first1.empty()) P.jobs[1].insert(P.jobs[1].begin(), first1.begin(), first1.end());
     for (int b = 0; b < tab.nblk(); ++b) {
         GJob j{};
         j.C = gtag(TAG_Y, xoff + tab.off[b]);
@@ -446,6 +524,10 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
     Plan P;
     P.dtype = dtype;
     append_matvec(P, legs, tab, terms, 0);
+    // a single node's last stage has one job per output block, each summing
+    // every term: too few tiles to fill the chip, so the term sums are split
+    // into partial jobs and added in a final stage
+    split_for_occupancy(P, (int)P.jobs.size() - 1, 2048);
     return P;
 }
 
@@ -687,6 +769,88 @@ void split_long_reductions(Plan& P, int s) {
             P.prods[s + 1].push_back(add);
         }
         for (auto& q : direct) P.prods[s + 1].push_back(q);
+        sum.p1 = (int)P.prods[s + 1].size();
+        P.jobs[s + 1].push_back(sum);
+    }
+}
+
+void split_for_occupancy(Plan& P, int s, int64_t target_tiles) {
+    if ((int)P.jobs.size() != s + 1) return;   // only the last stage of a plan
+    auto tiles_of = [](const GJob& J) {
+        return (int64_t)((J.M + 63) / 64) * ((J.N + 63) / 64) * J.batch;
+    };
+    int64_t T = 0;
+    for (const GJob& J : P.jobs[s]) T += tiles_of(J);
+    if (T == 0 || T >= target_tiles) return;
+    const int S = (int)std::min<int64_t>(8, (target_tiles + T - 1) / T);
+    if (S < 2) return;
+    P.jobs.emplace_back();
+    P.prods.emplace_back();
+    P.stage_flops.push_back(0.0);
+    std::vector<GJob> old = P.jobs[s];
+    std::vector<GProd> oldp = P.prods[s];
+    P.jobs[s].clear();
+    P.prods[s].clear();
+    for (const GJob& J : old) {
+        std::vector<GProd> work, direct;
+        int64_t W = 0;
+        for (int p = J.p0; p < J.p1; ++p) {
+            if (oldp[p].ident) {
+                direct.push_back(oldp[p]);
+            } else {
+                work.push_back(oldp[p]);
+                W += (int64_t)oldp[p].K * oldp[p].nred;
+            }
+        }
+        const int parts = (int)std::min<size_t>((size_t)S, work.size());
+        if (J.batch != 1 || parts < 2) {
+            GJob j = J;
+            j.p0 = (int)P.prods[s].size();
+            for (int p = J.p0; p < J.p1; ++p) P.prods[s].push_back(oldp[p]);
+            j.p1 = (int)P.prods[s].size();
+            P.jobs[s].push_back(j);
+            continue;
+        }
+        // contiguous groups of products with about W / parts work each
+        GJob sum{};
+        sum.C = J.C;
+        sum.M = J.M;
+        sum.N = J.N;
+        sum.ldc = J.ldc;
+        sum.batch = 1;
+        sum.acc = J.acc;
+        sum.nsc = J.nsc;
+        sum.noc = J.noc;
+        sum.p0 = (int)P.prods[s + 1].size();
+        size_t q = 0;
+        int64_t done = 0;
+        for (int g = 0; g < parts && q < work.size(); ++g) {
+            const int64_t goal = W * (g + 1) / parts;
+            GRef part = GRef{nullptr, P.ws_elems, TAG_WS, 0};
+            P.ws_elems += ((int64_t)J.M * J.N + 63) & ~(int64_t)63;
+            GJob pj{};
+            pj.C = part;
+            pj.M = J.M;
+            pj.N = J.N;
+            pj.ldc = J.N;
+            pj.batch = 1;
+            pj.p0 = (int)P.prods[s].size();
+            do {
+                P.prods[s].push_back(work[q]);
+                done += (int64_t)work[q].K * work[q].nred;
+                ++q;
+            } while (q < work.size() && (done < goal || g == parts - 1));
+            pj.p1 = (int)P.prods[s].size();
+            P.jobs[s].push_back(pj);
+            GProd add{};
+            add.ident = 1;
+            add.B = part;
+            add.ldb = J.N;
+            add.alpha = 1.0;
+            add.nred = 1;
+            P.prods[s + 1].push_back(add);
+        }
+        for (auto& d : direct) P.prods[s + 1].push_back(d);
         sum.p1 = (int)P.prods[s + 1].size();
         P.jobs[s + 1].push_back(sum);
     }

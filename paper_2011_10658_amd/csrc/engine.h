@@ -150,11 +150,14 @@ struct Prof {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<double> ev_flops;
+    std::vector<int> ev_key;             // stage index * 16 + tile shape
     long long launches = 0;
     double ms = 0.0, flops = 0.0;
+    std::map<int, std::array<double, 3>> by_key;   // launches, ms, flops per stage and shape
     void record_begin(hipStream_t s, hipEvent_t& a);
     void harvest();     // fold finished event pairs into ms (stream synced)
     void reset();
+    void report() const;   // per stage and shape, to stderr
     ~Prof();
 };
 
@@ -223,6 +226,12 @@ Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out);
 // Split the jobs of stage s that have few output tiles and a long
 // reduction into K-chunk partial products (stage s) summed in stage s+1.
 void split_long_reductions(Plan& P, int s);
+
+// When the last stage s of a plan has fewer than target_tiles 64x64 output
+// tiles, split every job's product list into up to 8 contiguous groups of
+// about equal work (partial jobs into workspace, stage s) and sum the
+// partials in a new stage s+1, in a fixed order.
+void split_for_occupancy(Plan& P, int s, int64_t target_tiles);
 
 // In-place QR of the contiguous column-major m x n matrix M (m >= n):
 // M := Q (orthonormal columns), R(r, c) written at R[r*rrs + c*rcs],
