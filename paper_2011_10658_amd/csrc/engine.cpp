@@ -856,74 +856,119 @@ void split_for_occupancy(Plan& P, int s, int64_t target_tiles) {
     }
 }
 
-void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs) {
-    if (m < n) fail(QED_ERR_BAD_STATE, "QR of a wide matrix");
-    if (n > 8192) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 8192 columns");
-    // sectors up to QR_COLS wide take the blocked kernel (at most QR_ROWS
-    // rows per workgroup); wider ones the unblocked kernel
-    const bool blocked = n <= QR_COLS;
-    const int64_t direct_max = blocked ? QR_ROWS : std::max<int64_t>(4096, 16 * (int64_t)n);
-    if (m <= direct_max) {
-        DBuf scratch(dev, (size_t)m * n * sizeof(double));
-        QRMat q{0, 0, m, rrs, rcs, (int)m, n};
-        DBuf dq(dev, sizeof(QRMat));
-        dev->upload(dq.p, &q, sizeof(QRMat));
-        launch_qr(dq.as<QRMat>(), 1, m, n, M, scratch.as<double>(), R, dev->stream);
+void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
+    if (tasks.empty()) return;
+    // level 1: every direct matrix and every row chunk of every tall one
+    std::vector<QRMat> blocked, wide;
+    int64_t rows_b = 0, rows_w = 0;
+    int cols_b = 0, cols_w = 0;
+    std::vector<BufP> keep;
+    struct Tall {
+        QRTask t;
+        int64_t b;
+        int P;
+        BufP S, T;
+    };
+    std::vector<Tall> tall;
+    auto add = [&](const QRMat& q) {
+        const bool bl = q.rows <= QR_ROWS && q.cols <= QR_COLS;
+        (bl ? blocked : wide).push_back(q);
+        if (bl) {
+            rows_b = std::max<int64_t>(rows_b, q.rows);
+            cols_b = std::max(cols_b, q.cols);
+        } else {
+            rows_w = std::max<int64_t>(rows_w, q.rows);
+            cols_w = std::max(cols_w, q.cols);
+        }
+    };
+    for (const QRTask& t : tasks) {
+        if (t.m < t.n) fail(QED_ERR_BAD_STATE, "QR of a wide matrix");
+        if (t.n > 8192) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 8192 columns");
+        if (t.n == 0) continue;
+        // sectors up to QR_COLS wide take the blocked kernel (at most QR_ROWS
+        // rows per workgroup); wider ones the unblocked kernel
+        const bool bl = t.n <= QR_COLS;
+        const int64_t direct_max = bl ? QR_ROWS : std::max<int64_t>(4096, 16 * (int64_t)t.n);
+        if (t.m <= direct_max) {
+            auto q = std::make_shared<DBuf>(dev, (size_t)t.m * t.n * sizeof(double));
+            keep.push_back(q);
+            add(QRMat{t.M, q->as<double>(), t.R, t.m, t.rrs, t.rcs, (int)t.m, t.n});
+            continue;
+        }
+        // chunks of b rows (the last one takes the remainder, < 2b, which is
+        // at most QR_ROWS on the blocked path)
+        Tall T;
+        T.t = t;
+        T.b = bl ? std::max<int64_t>(512, 4 * (int64_t)t.n) : std::max<int64_t>(2048, 4 * (int64_t)t.n);
+        T.P = (int)(t.m / T.b);
+        const int64_t ls = (int64_t)T.P * t.n;   // rows of the stacked R factors
+        T.S = std::make_shared<DBuf>(dev, (size_t)ls * t.n * sizeof(double));
+        T.T = std::make_shared<DBuf>(dev, (size_t)t.m * t.n * sizeof(double));
+        for (int i = 0; i < T.P; ++i) {
+            const int64_t r0 = (int64_t)i * T.b;
+            const int64_t rows = i == T.P - 1 ? t.m - r0 : T.b;
+            add(QRMat{t.M + r0, T.T->as<double>() + r0, T.S->as<double>() + (int64_t)i * t.n, t.m, 1, ls,
+                      (int)rows, t.n});
+        }
+        tall.push_back(T);
+    }
+    for (int kind = 0; kind < 2; ++kind) {
+        const auto& list = kind == 0 ? blocked : wide;
+        if (list.empty()) continue;
+        DBuf dq(dev, list.size() * sizeof(QRMat));
+        dev->upload(dq.p, list.data(), list.size() * sizeof(QRMat));
+        launch_qr(dq.as<QRMat>(), (int)list.size(), kind == 0 ? rows_b : rows_w,
+                  kind == 0 ? cols_b : cols_w, dev->stream);
         dev->check(hipGetLastError(), "qr launch");
-        return;
     }
-    // chunks of b rows (the last one takes the remainder, < 2b, which is at
-    // most QR_ROWS on the blocked path)
-    const int64_t b = blocked ? std::max<int64_t>(512, 4 * (int64_t)n) : std::max<int64_t>(2048, 4 * (int64_t)n);
-    const int P = (int)(m / b);
-    const int64_t ls = (int64_t)P * n;   // rows of the stacked R factors
-    DBuf S(dev, (size_t)ls * n * sizeof(double));
-    DBuf T(dev, (size_t)m * n * sizeof(double));
-    std::vector<QRMat> qs;
-    for (int i = 0; i < P; ++i) {
-        const int64_t r0 = (int64_t)i * b;
-        const int64_t rows = i == P - 1 ? m - r0 : b;
-        qs.push_back(QRMat{r0, (int64_t)i * n, m, 1, ls, (int)rows, n});
-    }
-    DBuf dq(dev, qs.size() * sizeof(QRMat));
-    dev->upload(dq.p, qs.data(), qs.size() * sizeof(QRMat));
-    int64_t maxrows = 0;
-    for (const QRMat& q : qs) maxrows = std::max<int64_t>(maxrows, q.rows);
-    launch_qr(dq.as<QRMat>(), P, maxrows, n, M, T.as<double>(), S.as<double>(), dev->stream);
-    dev->check(hipGetLastError(), "qr launch");
-    tsqr(dev, S.as<double>(), ls, n, R, rrs, rcs);
-    // Q = blockdiag(Q1_i) * Q2: chunk i of Q is Q1_i Q2[i n .. (i+1) n)
+    if (tall.empty()) return;
+    // the stacked R factors of every tall matrix, one level further up
+    std::vector<QRTask> up;
+    for (const Tall& T : tall)
+        up.push_back(QRTask{T.S->as<double>(), (int64_t)T.P * T.t.n, T.t.n, T.t.R, T.t.rrs, T.t.rcs});
+    tsqr_multi(dev, up);
+    // Q = blockdiag(Q1_i) * Q2: chunk i of Q is Q1_i Q2[i n .. (i+1) n), all
+    // matrices in one GEMM launch
     Plan pl;
     pl.dtype = QED_FP64;
     pl.jobs.emplace_back();
     pl.prods.emplace_back();
     pl.stage_flops.push_back(0.0);
-    for (int i = 0; i < P; ++i) {
-        const int64_t r0 = (int64_t)i * b;
-        const int rows = qs[i].rows;
-        GProd pr{};
-        pr.A = GRef{S.as<double>() + (int64_t)i * n, 0, TAG_ABS, 0};
-        pr.lda = (int)ls;
-        pr.B = GRef{M + r0, 0, TAG_ABS, 0};
-        pr.ldb = (int)m;
-        pr.K = n;
-        pr.alpha = 1.0;
-        pr.nred = 1;
-        GJob j{};
-        j.C = GRef{T.as<double>() + r0, 0, TAG_ABS, 0};
-        j.M = n;
-        j.N = rows;
-        j.ldc = (int)m;
-        j.batch = 1;
-        j.p0 = (int)pl.prods[0].size();
-        pl.prods[0].push_back(pr);
-        j.p1 = j.p0 + 1;
-        pl.jobs[0].push_back(j);
+    for (const Tall& T : tall) {
+        const int n = T.t.n;
+        const int64_t m = T.t.m, ls = (int64_t)T.P * n;
+        for (int i = 0; i < T.P; ++i) {
+            const int64_t r0 = (int64_t)i * T.b;
+            const int rows = (int)(i == T.P - 1 ? m - r0 : T.b);
+            GProd pr{};
+            pr.A = GRef{T.S->as<double>() + (int64_t)i * n, 0, TAG_ABS, 0};
+            pr.lda = (int)ls;
+            pr.B = GRef{T.t.M + r0, 0, TAG_ABS, 0};
+            pr.ldb = (int)m;
+            pr.K = n;
+            pr.alpha = 1.0;
+            pr.nred = 1;
+            GJob j{};
+            j.C = GRef{T.T->as<double>() + r0, 0, TAG_ABS, 0};
+            j.M = n;
+            j.N = rows;
+            j.ldc = (int)m;
+            j.batch = 1;
+            j.p0 = (int)pl.prods[0].size();
+            pl.prods[0].push_back(pr);
+            j.p1 = j.p0 + 1;
+            pl.jobs[0].push_back(j);
+        }
     }
     pl.upload(dev);
     pl.run(dev, nullptr, nullptr, nullptr);
-    dev->check(hipMemcpyAsync(M, T.p, (size_t)m * n * sizeof(double), hipMemcpyDeviceToDevice,
-                              dev->stream), "tsqr copy");
+    for (const Tall& T : tall)
+        dev->check(hipMemcpyAsync(T.t.M, T.T->p, (size_t)T.t.m * T.t.n * sizeof(double),
+                                  hipMemcpyDeviceToDevice, dev->stream), "tsqr copy");
+}
+
+void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs) {
+    tsqr_multi(dev, {QRTask{M, m, n, R, rrs, rcs}});
 }
 
 // ---------------------------------------------------------------------
@@ -938,7 +983,7 @@ void LanczosWS::ensure(Dev* dev, int mm, int64_t nn) {
     w = std::make_shared<DBuf>(dev, n * sizeof(double));
     alpha = std::make_shared<DBuf>(dev, 72 * sizeof(double));
     beta = std::make_shared<DBuf>(dev, 72 * sizeof(double));
-    coef = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+    coef = std::make_shared<DBuf>(dev, 144 * sizeof(double));   // two passes of coefficients
     partial = std::make_shared<DBuf>(dev, (size_t)72 * G * sizeof(double));
     sv = std::make_shared<DBuf>(dev, 72 * sizeof(double));
     work = std::make_shared<DBuf>(dev, 256 * sizeof(double));
@@ -959,6 +1004,7 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const dou
     double* al = W.alpha->as<double>();
     double* be = W.beta->as<double>();
     double* co = W.coef->as<double>();
+    double* co2 = co + 72;
     double* part = W.partial->as<double>();
     double* sc = W.scal->as<double>();
     LState* st = W.st->as<LState>();
@@ -972,12 +1018,20 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const dou
             apply(vj, w);
             ++R.matvecs;
             launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
-            launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
-            for (int pass = 0; pass < 2; ++pass) {
-                launch_dots(V, ld, j + 1, w, n, part, co, 0, st, 1, s);
-                launch_lz_subtract(w, V, ld, j + 1, co, n, st, s);
+            // three-term recurrence, two passes of classical Gram-Schmidt
+            // against V, norm: fused so that each pass reads the basis once
+            // (same arithmetic as the separate kernels)
+            if (launch_lz_fused(0, w, V, ld, 0, j, al, be, nullptr, n, part, co, st, s)) {
+                launch_lz_fused(1, w, V, ld, j + 1, j, al, be, co, n, part, co2, st, s);
+                launch_lz_fused(2, w, V, ld, j + 1, j, al, be, co2, n, part, sc + 1, st, s);
+            } else {
+                launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
+                for (int pass = 0; pass < 2; ++pass) {
+                    launch_dots(V, ld, j + 1, w, n, part, co, 0, st, 1, s);
+                    launch_lz_subtract(w, V, ld, j + 1, co, n, st, s);
+                }
+                launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
             }
-            launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
             launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
             launch_lz_next(V, ld, j, w, be, n, st, s);
         }

@@ -29,6 +29,9 @@ int dot_grid(int64_t n);
 void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64_t n,
                  double* partial, double* out, int mode, const LState* st, int skip,
                  hipStream_t stream);
+bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
+                     const double* alpha, const double* beta, const double* c, int64_t n,
+                     double* partial, double* out, const LState* st, hipStream_t s);
 void launch_lz_three_term(double*, const double*, int64_t, int, const double*, const double*,
                           int64_t, const LState*, hipStream_t);
 void launch_lz_subtract(double*, const double*, int64_t, int, const double*, int64_t,
@@ -45,8 +48,7 @@ void launch_normalise_sign(double*, int64_t, const double*, double*, int64_t*, d
 void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_t);
 // blocked kernel when every matrix has rows <= QR_ROWS and cols <= QR_COLS,
 // else the unblocked one
-void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, double*, double*, double*,
-               hipStream_t);
+void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
 
@@ -233,10 +235,20 @@ void split_long_reductions(Plan& P, int s);
 // partials in a new stage s+1, in a fixed order.
 void split_for_occupancy(Plan& P, int s, int64_t target_tiles);
 
-// In-place QR of the contiguous column-major m x n matrix M (m >= n):
+// In-place QR of contiguous column-major m x n matrices M (m >= n):
 // M := Q (orthonormal columns), R(r, c) written at R[r*rrs + c*rcs],
 // diag(R) >= 0.  Tall matrices use a tree of Householder QRs over row
-// chunks (TSQR) with a block GEMM assembling Q.
+// chunks (TSQR) with a block GEMM assembling Q.  All matrices of one call
+// advance level by level together: one QR launch per tree level (per
+// kernel kind), one GEMM launch assembling every Q.
+struct QRTask {
+    double* M;
+    int64_t m;
+    int n;
+    double* R;
+    int64_t rrs, rcs;
+};
+void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks);
 void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs);
 
 // ---- Lanczos -----------------------------------------------------------

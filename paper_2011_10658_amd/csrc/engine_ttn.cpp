@@ -168,24 +168,12 @@ OpP Engine::qr_toward(int n, int which) {
     dev->upload(dpb.p, pb.data(), pb.size() * sizeof(PackBlk));
     DBuf packed(dev, tot * sizeof(double));
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 0, dev->stream);
-    // sectors with few rows: one batched launch; tall sectors: TSQR each
-    std::vector<QRMat> small;
-    for (int s = 0; s < ns; ++s) {
-        const int n_s = L.n[s];
-        if (rows[s] <= QR_ROWS && n_s <= QR_COLS) {
-            small.push_back(QRMat{mat[s], R->lay.off[s], rows[s], n_s, 1, (int)rows[s], n_s});
-        } else {
-            tsqr(dev, packed.as<double>() + mat[s], rows[s], n_s, (double*)R->d64->p + R->lay.off[s],
-                 n_s, 1);
-        }
-    }
-    if (!small.empty()) {
-        DBuf dqm(dev, small.size() * sizeof(QRMat));
-        dev->upload(dqm.p, small.data(), small.size() * sizeof(QRMat));
-        DBuf qbuf(dev, tot * sizeof(double));
-        launch_qr(dqm.as<QRMat>(), (int)small.size(), QR_ROWS, QR_COLS, packed.as<double>(),
-                  qbuf.as<double>(), (double*)R->d64->p, dev->stream);
-    }
+    // every sector of the leg in one batched (level-synchronous) QR
+    std::vector<QRTask> tasks;
+    for (int s = 0; s < ns; ++s)
+        tasks.push_back(QRTask{packed.as<double>() + mat[s], rows[s], L.n[s],
+                               (double*)R->d64->p + R->lay.off[s], L.n[s], 1});
+    tsqr_multi(dev, tasks);
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 1, dev->stream);
     dev->check(hipGetLastError(), "qr launch");
     return R;

@@ -85,8 +85,9 @@ constexpr int QR_ROWS = 2048;
 constexpr int QR_COLS = 256;
 
 struct QRMat {
-    int64_t mat;
-    int64_t rout;
+    double* a;          // the matrix (column-major, leading dimension ld); Q on exit
+    double* q;          // scratch with the same layout
+    double* r;          // R written at r[i * rrs + j * rcs]
     int64_t ld;
     int64_t rrs, rcs;
     int rows, cols;

@@ -589,6 +589,99 @@ __global__ void k_scale_by(double* __restrict__ u, int64_t n, const double* fac)
         u[i] *= f;
 }
 
+// Fused Lanczos vector update + dot products, one pass over the basis:
+//   mode 0: w -= alpha_j v_j + beta_{j-1} v_{j-1}, then partials of V[r].w, r <= j
+//   mode 1: w -= sum_{r < nrows} c[r] V[r],       then partials of V[r].w, r < nrows
+//   mode 2: w -= sum_{r < nrows} c[r] V[r],       then the partial of w.w
+// The element partition (contiguous slice per workgroup, stride 256 inside),
+// the per-row accumulation order and the wave/block reduction are those of
+// k_dot_partial, and the update expressions those of k_lz_three_term and
+// k_lz_subtract, so the results equal the unfused kernels' bit for bit; each
+// basis element is loaded once for both the update and the dots.
+template <int MAXR>
+__global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const double* __restrict__ V,
+                                                  int64_t ldv, int mode, int nrows, int j,
+                                                  const double* __restrict__ alpha,
+                                                  const double* __restrict__ beta,
+                                                  const double* __restrict__ c, int64_t n,
+                                                  double* __restrict__ partial, const LState* st) {
+    if (st->broken) return;
+    __shared__ double sh[MAXR][4];
+    const int G = gridDim.x;
+    const int64_t chunk = (n + G - 1) / G;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    const int nr = mode == 0 ? j + 1 : nrows;          // rows in the update / dots
+    const int nd = mode == 2 ? 1 : nr;                  // dot rows
+    const double a = mode == 0 ? alpha[j] : 0.0;
+    const double b = (mode == 0 && j > 0) ? beta[j - 1] : 0.0;
+    double s[MAXR];
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) s[q] = 0.0;
+    // up to 16 rows the element's basis entries stay in registers between
+    // the update and the dots; beyond, the second read hits the cache
+    constexpr bool CACHE = MAXR <= 16;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        constexpr int NV = CACHE ? MAXR : 1;
+        double v[NV];
+        if constexpr (CACHE) {
+#pragma unroll
+            for (int r = 0; r < NV; ++r) v[r] = r < nr ? V[(int64_t)r * ldv + i] : 0.0;
+        }
+#define QED_ROW(r) (CACHE ? v[(r) < NV ? (r) : 0] : V[(int64_t)(r) * ldv + i])
+        double wi = w[i];
+        if (mode == 0) {
+            // rows j and j-1 are cached from the loads above
+            double t = a * V[(int64_t)j * ldv + i];
+            if (j > 0) t += b * V[(int64_t)(j - 1) * ldv + i];
+            wi -= t;
+        } else {
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r < nr) t += c[r] * QED_ROW(r);
+            wi -= t;
+        }
+        w[i] = wi;
+        if (mode == 2) {
+            s[0] += wi * wi;
+        } else {
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r < nd) s[r] += QED_ROW(r) * wi;
+        }
+    }
+#undef QED_ROW
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) {
+        if (q < nd) {
+            double t = wave_sum(s[q]);
+            if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = t;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nd)
+        partial[(int64_t)threadIdx.x * G + blockIdx.x] =
+            ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
+}
+
+bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
+                     const double* alpha, const double* beta, const double* c, int64_t n,
+                     double* partial, double* out, const LState* st, hipStream_t s) {
+    const int nr = mode == 0 ? j + 1 : nrows;
+    if (nr > 32) return false;
+    const int G = dot_grid(n);
+    if (nr <= 16)
+        hipLaunchKernelGGL(k_lz_fused<16>, dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
+                           beta, c, n, partial, st);
+    else
+        hipLaunchKernelGGL(k_lz_fused<32>, dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
+                           beta, c, n, partial, st);
+    const int nd = mode == 2 ? 1 : nr;
+    hipLaunchKernelGGL(k_dot_final, dim3(nd), dim3(256), 0, s, partial, G, nd, out, 0, st, 1);
+    return true;
+}
+
 void launch_lz_three_term(double* w, const double* V, int64_t ldv, int j, const double* alpha,
                           const double* beta, int64_t n, const LState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_lz_three_term, dim3(grid_for(n)), dim3(256), 0, s, w, V, ldv, j, alpha,
@@ -743,10 +836,7 @@ __device__ __forceinline__ void apply_panel(double* X, int64_t ld, int row0, int
     }
 }
 
-__global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict__ mats,
-                                                        double* __restrict__ packed,
-                                                        double* __restrict__ qbuf,
-                                                        double* __restrict__ rbuf) {
+__global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict__ mats) {
     __shared__ double Vp[QR_ROWS * QB];                    // panel, row-major
     __shared__ double Ts[(QR_COLS / QB) * QB * QB];        // T of every panel
     __shared__ double tau[QR_COLS], diag[QR_COLS];
@@ -754,9 +844,9 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
     const QRMat Mt = mats[blockIdx.x];
     const int m = Mt.rows, n = Mt.cols;
     const int64_t ld = Mt.ld;
-    double* A = packed + Mt.mat;
-    double* Qm = qbuf + Mt.mat;
-    double* R = rbuf + Mt.rout;
+    double* A = Mt.a;
+    double* Qm = Mt.q;
+    double* R = Mt.r;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int npan = (n + QB - 1) / QB;
     for (int p = 0; p < npan; ++p) {
@@ -909,17 +999,14 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
 // are fixed so that diag(R) >= 0.  `qbuf` is scratch with the same layout
 // as the input.  Zero columns (rank deficiency) get tau = 0 and R_jj = 0,
 // and Q still has orthonormal columns.
-__global__ __launch_bounds__(256) void k_householder_qr_wide(const QRMat* __restrict__ mats,
-                                                        double* __restrict__ packed,
-                                                        double* __restrict__ qbuf,
-                                                        double* __restrict__ rbuf) {
+__global__ __launch_bounds__(256) void k_householder_qr_wide(const QRMat* __restrict__ mats) {
     extern __shared__ double lds[];
     const QRMat Mt = mats[blockIdx.x];
     const int m = Mt.rows, n = Mt.cols;
     const int64_t ld = Mt.ld;
-    double* A = packed + Mt.mat;
-    double* Qm = qbuf + Mt.mat;
-    double* R = rbuf + Mt.rout;
+    double* A = Mt.a;
+    double* Qm = Mt.q;
+    double* R = Mt.r;
     double* tau = lds;          // n
     double* diag = lds + n;     // n  (R_jj)
     double* red = lds + 2 * n;  // 4
@@ -994,18 +1081,17 @@ __global__ __launch_bounds__(256) void k_householder_qr_wide(const QRMat* __rest
     }
 }
 
-void launch_qr(const QRMat* mats, int nmats, int64_t maxrows, int maxcols, double* packed,
-               double* qbuf, double* rbuf, hipStream_t s) {
+void launch_qr(const QRMat* mats, int nmats, int64_t maxrows, int maxcols, hipStream_t s) {
     if (nmats <= 0) return;
     if (maxrows <= QR_ROWS && maxcols <= QR_COLS) {
-        hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), 0, s, mats, packed, qbuf, rbuf);
+        hipLaunchKernelGGL(k_householder_qr, dim3(nmats), dim3(256), 0, s, mats);
         return;
     }
     const size_t lds = (size_t)(2 * maxcols + 4) * sizeof(double);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_householder_qr_wide,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_householder_qr_wide, dim3(nmats), dim3(256), lds, s, mats, packed, qbuf, rbuf);
+    hipLaunchKernelGGL(k_householder_qr_wide, dim3(nmats), dim3(256), lds, s, mats);
 }
 
 // ---------------------------------------------------------------------
