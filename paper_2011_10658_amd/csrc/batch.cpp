@@ -121,7 +121,7 @@ void Tuner::tune(Dev* dev, Plan& P, void* ws, void* x, void* y) {
     if (!on) return;
     bool changed = false;
     for (size_t s = 0; s < P.jobs.size(); ++s) {
-        if (!P.ntiles[s]) continue;
+        if (!P.ntiles[s] || P.sumk[s]) continue;
         const std::string key = stage_key(P, s);
         auto it = cache.find(key);
         if (it != cache.end()) {

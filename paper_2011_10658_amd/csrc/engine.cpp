@@ -243,13 +243,28 @@ static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, int sh) {
     return tiles;
 }
 
+static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
+    std::vector<GTile> tiles;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const int64_t n = (int64_t)jobs[j].M * jobs[j].N;
+        for (int b = 0; b < jobs[j].batch; ++b)
+            for (int64_t c = 0; c * SUM_TILE < n; ++c) tiles.push_back(GTile{(int)j, b, (int)c, 0});
+    }
+    return tiles;
+}
+
 void Plan::upload(Dev* dev) {
     dj.clear();
     dp.clear();
     dt.clear();
     ntiles.clear();
     shape.clear();
+    sumk.clear();
     for (size_t s = 0; s < jobs.size(); ++s) {
+        bool only_ident = !jobs[s].empty();
+        for (const GProd& p : prods[s])
+            if (!p.ident) only_ident = false;
+        sumk.push_back(only_ident ? 1 : 0);
         // the tile shape that pads the stage's jobs least
         int best = GEMM_SHAPE_SQUARE;
         double best_area = -1.0;
@@ -263,7 +278,7 @@ void Plan::upload(Dev* dev) {
                 best = sh;
             }
         }
-        std::vector<GTile> tiles = make_tiles(jobs[s], best);
+        std::vector<GTile> tiles = only_ident ? make_sum_tiles(jobs[s]) : make_tiles(jobs[s], best);
         auto bj = std::make_shared<DBuf>(dev, jobs[s].size() * sizeof(GJob));
         auto bp = std::make_shared<DBuf>(dev, std::max<size_t>(1, prods[s].size()) * sizeof(GProd));
         auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
@@ -284,7 +299,7 @@ void Plan::upload(Dev* dev) {
 }
 
 void Plan::set_shape(Dev* dev, int s, int sh) {
-    if (shape[s] == sh) return;
+    if (shape[s] == sh || sumk[s]) return;
     std::vector<GTile> tiles = make_tiles(jobs[s], sh);
     auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
     dev->upload(bt->p, tiles.data(), tiles.size() * sizeof(GTile));
@@ -307,6 +322,10 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
     const GJob* J = dj[s]->as<GJob>();
     const GProd* Pp = dp[s]->as<GProd>();
     const GTile* T = dt[s]->as<GTile>();
+    if (sumk[s]) {
+        launch_sum_stage(dtype, J, Pp, T, ntiles[s], b, st);
+        return;
+    }
     if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], st);
     else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
     else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], st);

@@ -29,6 +29,9 @@ int dot_grid(int64_t n);
 void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64_t n,
                  double* partial, double* out, int mode, const LState* st, int skip,
                  hipStream_t stream);
+// stages whose products are all identity products (sums of blocks): one
+// workgroup per SUM_TILE consecutive output elements of a job
+void launch_sum_stage(int dtype, const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
 bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
                      const double* alpha, const double* beta, const double* c, int64_t n,
                      double* partial, double* out, const LState* st, hipStream_t s);
@@ -177,6 +180,7 @@ struct Plan {
     std::vector<BufP> dj, dp, dt;
     std::vector<int> ntiles;
     std::vector<int> shape;   // workgroup tile shape per stage
+    std::vector<char> sumk;   // stage of identity products only: elementwise sum kernel
     void upload(Dev* dev);
     void run(Dev* dev, void* ws, void* x, void* y);
     void run_stage(Dev* dev, int s, void* ws, void* x, void* y);

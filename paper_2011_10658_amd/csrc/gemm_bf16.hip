@@ -181,6 +181,32 @@ __global__ __launch_bounds__(256) void k_brgemm_bf16(const GJob* __restrict__ jo
         }
 }
 
+// identity-only stage (see k_sum_stage): BF16 storage, FP32 sums
+__global__ __launch_bounds__(256) void k_sum_stage_bf16(const GJob* __restrict__ jobs,
+                                                        const GProd* __restrict__ prods,
+                                                        const GTile* __restrict__ tiles, Bases bases) {
+    const GTile tl = tiles[blockIdx.x];
+    if (tl.job < 0) return;
+    const GJob J = jobs[tl.job];
+    const int64_t total = (int64_t)J.M * J.N;
+    const int64_t e0 = (int64_t)tl.tm * SUM_TILE;
+    const int64_t e1 = e0 + SUM_TILE < total ? e0 + SUM_TILE : total;
+    uint16_t* C = at<uint16_t>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const int row = (int)(e / J.N), col = (int)(e % J.N);
+        float acc = 0.0f;
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd P = prods[p];
+            const uint16_t* Bb = at<const uint16_t>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
+            acc += (float)P.alpha * bf2f(Bb[(int64_t)row * P.ldb + co]);
+        }
+        const int64_t cc = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
+        uint16_t* c = C + (int64_t)row * J.ldc + cc;
+        *c = f2bf(J.acc ? bf2f(*c) + acc : acc);
+    }
+}
+
 __global__ void k_f64_to_bf16(const double* __restrict__ a, uint16_t* __restrict__ b, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -216,6 +242,12 @@ void launch_brgemm_bf16(const GJob* jobs, const GProd* prods, const GTile* tiles
         default:
             hipLaunchKernelGGL((k_brgemm_bf16<2, 2, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
     }
+}
+
+void launch_sum_stage_bf16(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
+                           const Bases& bases, hipStream_t st) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_sum_stage_bf16, dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
 }
 
 void launch_f64_to_bf16(const double* a, void* b, int64_t n, hipStream_t st) {

@@ -80,6 +80,9 @@ struct PackBlk {
 // One matrix for the QR kernel: column-major rows x cols with leading
 // dimension ld at `mat` (in the packed buffer and, for the scratch copy of
 // Q, in the scratch buffer); R(r, c) is written at rout + r*rrs + c*rcs.
+// Output elements per workgroup of an identity-only (summation) stage.
+constexpr int SUM_TILE = 1024;
+
 // Sizes one QR workgroup handles (the panel and the T factors live in LDS).
 constexpr int QR_ROWS = 2048;
 constexpr int QR_COLS = 256;

@@ -207,6 +207,49 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
         }
 }
 
+// A stage whose products are all identity products: C (+)= sum_p alpha_p
+// B_p elementwise, with the same column splits and the same order of
+// additions as the GEMM kernel's identity path (so the same results), but
+// coalesced: one workgroup per SUM_TILE consecutive elements of a job.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_stage(const GJob* __restrict__ jobs,
+                                                   const GProd* __restrict__ prods,
+                                                   const GTile* __restrict__ tiles, Bases bases) {
+    const GTile tl = tiles[blockIdx.x];
+    if (tl.job < 0) return;
+    const GJob J = jobs[tl.job];
+    const int64_t total = (int64_t)J.M * J.N;
+    const int64_t e0 = (int64_t)tl.tm * SUM_TILE;
+    const int64_t e1 = e0 + SUM_TILE < total ? e0 + SUM_TILE : total;
+    T* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const int row = (int)(e / J.N), col = (int)(e % J.N);
+        T acc = (T)0;
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd P = prods[p];
+            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
+            acc += (T)P.alpha * Bb[(int64_t)row * P.ldb + co];
+        }
+        const int64_t cc = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
+        T* c = C + (int64_t)row * J.ldc + cc;
+        *c = J.acc ? *c + acc : acc;
+    }
+}
+
+void launch_sum_stage_bf16(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
+
+void launch_sum_stage(int dtype, const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
+                      const Bases& bases, hipStream_t st) {
+    if (ntiles <= 0) return;
+    if (dtype == QED_FP64)
+        hipLaunchKernelGGL(k_sum_stage<double>, dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+    else if (dtype == QED_FP32)
+        hipLaunchKernelGGL(k_sum_stage<float>, dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+    else
+        launch_sum_stage_bf16(jobs, prods, tiles, ntiles, bases, st);
+}
+
 template <typename T>
 void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
                    const Bases& bases, int shape, hipStream_t st) {
@@ -620,7 +663,7 @@ __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const 
     for (int q = 0; q < MAXR; ++q) s[q] = 0.0;
     // up to 16 rows the element's basis entries stay in registers between
     // the update and the dots; beyond, the second read hits the cache
-    constexpr bool CACHE = MAXR <= 16;
+    constexpr bool CACHE = MAXR <= 32;
     for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
         constexpr int NV = CACHE ? MAXR : 1;
         double v[NV];
