@@ -3,15 +3,19 @@
 //  * k_brgemm: grouped batch-reduce GEMM.  Every contraction of the hot
 //    path (H_eff mode products, the term-summed output accumulation, the
 //    environment renormalisation) is a list of jobs, each a sum of
-//    products of dense symmetry blocks; one workgroup owns one 32 x 32
-//    output tile, stages A/B through LDS and runs 16x16x4 MFMA on four
-//    waves.  FP64 and FP32 instances; FP32 accumulates in FP32.
+//    products of dense symmetry blocks; one workgroup owns one output tile
+//    (64x64, 128x32 or 32x128), stages A/B through double-buffered LDS and
+//    runs 16x16x4 MFMA on four waves.  FP64 and FP32 instances; FP32
+//    accumulates in FP32.  k_sum_stage runs stages of identity products.
 //  * FP64 Lanczos vector kernels: multi-row dot products with wave64
-//    shuffle reductions in a fixed order (deterministic), fused updates.
+//    shuffle reductions in a fixed order (deterministic); the recurrence,
+//    both Gram-Schmidt passes and the norm fused with their dot products.
 //  * k_tridiag_lowest: lowest eigenpair of the Lanczos tridiagonal
-//    (Sturm bisection + inverse iteration with partial pivoting).
+//    (Sturm-count multisection on one wave + inverse iteration with
+//    partial pivoting).
 //  * k_householder_qr: per-sector blocked Householder QR (compact WY
-//    panels in LDS), one workgroup per sector matrix, diag(R) >= 0.
+//    panels in LDS), one workgroup per sector matrix, diag(R) >= 0;
+//    k_householder_qr_wide for sectors wider than 256 columns.
 #include "kernels.h"
 #include "qedttn.h"
 
@@ -472,11 +476,13 @@ __global__ void k_lz_start(double* __restrict__ dst, const double* __restrict__ 
 }
 
 // lowest eigenpair of the k x k tridiagonal (alpha, beta): Sturm-count
-// bisection to full precision, then inverse iteration with a pivoted
-// tridiagonal LU.  Writes s[0..k), st->theta and st->resid.
+// multisection on one wave (64 shifts per round, the interval shrinks 65x),
+// to full precision, then inverse iteration with a pivoted tridiagonal LU
+// by lane 0.  Writes s[0..k), st->theta and st->resid.
 __global__ void k_tridiag_lowest(const double* alpha, const double* beta, double* s, LState* st,
                                  double* work) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0 || threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
     const int k = st->k;
     double lo = 0.0, hi = 0.0, tnorm = 0.0;
     for (int i = 0; i < k; ++i) {
@@ -487,21 +493,29 @@ __global__ void k_tridiag_lowest(const double* alpha, const double* beta, double
         tnorm = fmax(tnorm, fabs(alpha[i]) + r);
     }
     const double tiny = 1e-300;
-    for (int it = 0; it < 2000; ++it) {
-        double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        // number of eigenvalues < mid
+    // invariant: no eigenvalue below lo, at least one below hi
+    for (int it = 0; it < 64; ++it) {
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
         int cnt = 0;
-        double d = alpha[0] - mid;
+        double d = alpha[0] - x;
         if (d == 0.0) d = -tiny;
         if (d < 0) ++cnt;
         for (int i = 1; i < k; ++i) {
-            d = alpha[i] - mid - beta[i - 1] * beta[i - 1] / d;
+            d = alpha[i] - x - beta[i - 1] * beta[i - 1] / d;
             if (d == 0.0) d = -tiny;
             if (d < 0) ++cnt;
         }
-        if (cnt >= 1) hi = mid; else lo = mid;
+        // the first shift with an eigenvalue below it bounds the lowest one
+        const unsigned long long m = __ballot(cnt >= 1 && x > lo && x <= hi);
+        const int f = m ? __ffsll((long long)m) - 1 : 64;
+        const double nhi = f < 64 ? __shfl(x, f, 64) : hi;
+        const double nlo = f > 0 ? __shfl(x, f - 1 < 64 ? f - 1 : 63, 64) : lo;
+        const double lo2 = (f > 0 && f <= 64 && nlo > lo && nlo < nhi) ? nlo : lo;
+        if (nhi >= hi && lo2 <= lo) break;   // no representable progress
+        lo = lo2;
+        hi = nhi;
     }
+    if (lane != 0) return;
     const double theta = 0.5 * (lo + hi);
     // inverse iteration on (T - theta I)
     double* dl = work;
