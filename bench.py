@@ -43,6 +43,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# sources whose change invalidates recorded hardware byte counts of the GEMM
+# (the kernel, its tile order and the plans it runs)
+TRAFFIC_SOURCES = ("paper_2011_10658_amd/csrc/kernels.hip", "paper_2011_10658_amd/csrc/kernels.h",
+                   "paper_2011_10658_amd/csrc/engine.cpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_brgemm_f32_traffic_sweep_2x2x2_free_chi64.json")
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per k_brgemm<float> launch from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, calibrated by the copy probe), or None when
+    the sources have changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != sources_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def make_ctx(lib, dtype):
     ctx = lib.Context(0)
     g2e, g2m = lib.physical_line(1.0, 1.0)
@@ -605,7 +635,7 @@ def main():
             "peak": PEAK["f32"],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK["f32"],
-            "traffic": None,
+            "traffic": recorded_traffic(),
             "launches": r32["gemm_launches"],
             "avg_launch_us": 1e3 * r32["gemm_ms"] / max(1, r32["gemm_launches"]),
         },
