@@ -260,11 +260,19 @@ void Plan::upload(Dev* dev) {
     ntiles.clear();
     shape.clear();
     sumk.clear();
+    flat.clear();
     for (size_t s = 0; s < jobs.size(); ++s) {
         bool only_ident = !jobs[s].empty();
+        double ksum = 0.0, kn = 0.0;
         for (const GProd& p : prods[s])
-            if (!p.ident) only_ident = false;
+            if (!p.ident) {
+                only_ident = false;
+                ksum += (double)p.K * p.nred;
+                kn += 1.0;
+            }
         sumk.push_back(only_ident ? 1 : 0);
+        // short reductions per product: pipeline across products
+        flat.push_back(kn > 0.0 && ksum / kn < 64.0 ? 1 : 0);
         // the tile shape that pads the stage's jobs least
         int best = GEMM_SHAPE_SQUARE;
         double best_area = -1.0;
@@ -326,9 +334,9 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
         launch_sum_stage(dtype, J, Pp, T, ntiles[s], b, st);
         return;
     }
-    if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], st);
+    if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], flat[s] != 0, st);
     else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
-    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], st);
+    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], flat[s] != 0, st);
 }
 
 void Prof::record_begin(hipStream_t s, hipEvent_t& a) {

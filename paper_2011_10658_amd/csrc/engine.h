@@ -19,8 +19,10 @@
 namespace qed {
 
 // ---- kernel launchers (kernels.hip) ----------------------------------
+// flat: products of a job as one pipelined sequence of K chunks (pays off
+// for short reductions); otherwise one pipeline per product
 template <typename T>
-void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape,
+void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape, bool flat,
                    hipStream_t);
 void launch_fill(double*, int64_t, double, hipStream_t);
 void launch_f64_to_f32(const double*, float*, int64_t, hipStream_t);
@@ -181,6 +183,7 @@ struct Plan {
     std::vector<int> ntiles;
     std::vector<int> shape;   // workgroup tile shape per stage
     std::vector<char> sumk;   // stage of identity products only: elementwise sum kernel
+    std::vector<char> flat;   // stage with short reductions: flat product pipeline
     void upload(Dev* dev);
     void run(Dev* dev, void* ws, void* x, void* y);
     void run_stage(Dev* dev, int s, void* ws, void* x, void* y);

@@ -63,7 +63,7 @@ template <typename T> struct GemmK;
 template <> struct GemmK<float> { static constexpr int KC = 16; };
 template <> struct GemmK<double> { static constexpr int KC = 16; };
 
-template <typename T, int WM, int WN, int BM, int BN>
+template <typename T, int WM, int WN, int BM, int BN, bool FLAT>
 __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
                                                 const GProd* __restrict__ prods,
                                                 const GTile* __restrict__ tiles, Bases bases) {
@@ -99,97 +99,234 @@ __global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
     const int t_kc = tid % KC, t_kq = tid / KC;
     const int t_tm = tid % TM, t_tq = tid / TM;
     const int t_tn = tid % TN, t_nq = tid / TN;
-    for (int p = J.p0; p < J.p1; ++p) {
-        const GProd P = prods[p];
-        const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
-        const T alpha = (T)P.alpha;
-        if (P.ident) {
-#pragma unroll
+    if constexpr (!FLAT) {
+        // one product after the other, each with its own pipeline prologue
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd P = prods[p];
+            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            const T alpha = (T)P.alpha;
+            if (P.ident) {
+    #pragma unroll
+                for (int bi = 0; bi < BM; ++bi)
+    #pragma unroll
+                    for (int bj = 0; bj < BN; ++bj) {
+                        const int col = n0 + wn0 + bj * 16 + lr;
+                        const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
+    #pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
+                            if (row < J.M && col < J.N)
+                                acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + co];
+                        }
+                    }
+                continue;
+            }
+            const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
+            const int nchunk = (P.K + KC - 1) / KC;
+            // element e of this thread: A row am0 + e amE, A column (k) ak0 + e akE
+            // within the chunk (and likewise for B), one branch-free form for
+            // both storage orders
+            const int am0 = P.tA ? t_tm : t_kq, amE = P.tA ? 0 : ASA;
+            const int ak0 = P.tA ? t_tq : t_kc, akE = P.tA ? ASB : 0;
+            const int64_t akm = P.tA ? (int64_t)P.lda : 1;
+            const int64_t aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
+            const int64_t abase = P.tA ? (int64_t)ak0 * P.lda + m0 + am0 : (int64_t)(m0 + am0) * P.lda + ak0;
+            const int bn0 = P.tB ? t_kq : t_tn, bnE = P.tB ? BSB : 0;
+            const int bk0 = P.tB ? t_kc : t_nq, bkE = P.tB ? 0 : BSN;
+            const int64_t bkm = P.tB ? 1 : (int64_t)P.ldb;
+            const int64_t bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
+            int64_t bbase;
+            if (P.tB) {
+                bbase = (int64_t)(n0 + bn0) * P.ldb + bk0;
+            } else {
+                const int gn = n0 + bn0;
+                const int64_t col = P.nsb ? (int64_t)(gn / P.nsb) * P.nob + gn % P.nsb : gn;
+                bbase = (int64_t)bk0 * P.ldb + col;
+            }
+            for (int r = 0; r < P.nred; ++r) {
+                const T* A = Ab + (int64_t)r * P.rsA + abase;
+                const T* B = Bb + (int64_t)r * P.rsB + bbase;
+                auto fetch = [&](int c) {
+                    const int k0 = c * KC;
+                    const T* pa = A + k0 * akm;
+                    const T* pb = B + k0 * bkm;
+    #pragma unroll
+                    for (int e = 0; e < AE; ++e) {
+                        T v = (T)0;
+                        if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
+                        ra[e] = v * alpha;
+                    }
+    #pragma unroll
+                    for (int e = 0; e < BE; ++e) {
+                        T v = (T)0;
+                        if (n0 + bn0 + e * bnE < J.N && k0 + bk0 + e * bkE < P.K) v = pb[e * bes];
+                        rb[e] = v;
+                    }
+                };
+                auto stash = [&](int buf) {
+    #pragma unroll
+                    for (int e = 0; e < AE; ++e) As[buf][ak0 + e * akE][am0 + e * amE] = ra[e];
+    #pragma unroll
+                    for (int e = 0; e < BE; ++e) Bs[buf][bk0 + e * bkE][bn0 + e * bnE] = rb[e];
+                };
+                // the previous product's last chunk may still be read from
+                // buffer 0 by other waves
+                __syncthreads();
+                fetch(0);
+                stash(0);
+                __syncthreads();
+                for (int c = 0; c < nchunk; ++c) {
+                    const int cur = c & 1;
+                    if (c + 1 < nchunk) fetch(c + 1);
+    #pragma unroll
+                    for (int kk = 0; kk < KC; kk += 4) {
+                        T a[BM], bb[BN];
+    #pragma unroll
+                        for (int i = 0; i < BM; ++i) a[i] = As[cur][kk + lk][wm0 + i * 16 + lr];
+    #pragma unroll
+                        for (int j = 0; j < BN; ++j) bb[j] = Bs[cur][kk + lk][wn0 + j * 16 + lr];
+    #pragma unroll
+                        for (int i = 0; i < BM; ++i)
+    #pragma unroll
+                            for (int j = 0; j < BN; ++j) acc[i][j] = Mfma<T>::step(a[i], bb[j], acc[i][j]);
+                    }
+                    if (c + 1 < nchunk) stash(cur ^ 1);
+                    __syncthreads();
+                }
+            }
+        }
+    } else {
+        // identity products first (they need no LDS stage)
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd P = prods[p];
+            if (!P.ident) continue;
+            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            const T alpha = (T)P.alpha;
+    #pragma unroll
             for (int bi = 0; bi < BM; ++bi)
-#pragma unroll
+    #pragma unroll
                 for (int bj = 0; bj < BN; ++bj) {
                     const int col = n0 + wn0 + bj * 16 + lr;
                     const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
-#pragma unroll
+    #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
-                        if (row < J.M && col < J.N)
-                            acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + co];
+                        if (row < J.M && col < J.N) acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + co];
                     }
                 }
-            continue;
         }
-        const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
-        const int nchunk = (P.K + KC - 1) / KC;
-        // element e of this thread: A row am0 + e amE, A column (k) ak0 + e akE
-        // within the chunk (and likewise for B), one branch-free form for
-        // both storage orders
-        const int am0 = P.tA ? t_tm : t_kq, amE = P.tA ? 0 : ASA;
-        const int ak0 = P.tA ? t_tq : t_kc, akE = P.tA ? ASB : 0;
-        const int64_t akm = P.tA ? (int64_t)P.lda : 1;
-        const int64_t aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
-        const int64_t abase = P.tA ? (int64_t)ak0 * P.lda + m0 + am0 : (int64_t)(m0 + am0) * P.lda + ak0;
-        const int bn0 = P.tB ? t_kq : t_tn, bnE = P.tB ? BSB : 0;
-        const int bk0 = P.tB ? t_kc : t_nq, bkE = P.tB ? 0 : BSN;
-        const int64_t bkm = P.tB ? 1 : (int64_t)P.ldb;
-        const int64_t bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
-        int64_t bbase;
-        if (P.tB) {
-            bbase = (int64_t)(n0 + bn0) * P.ldb + bk0;
-        } else {
-            const int gn = n0 + bn0;
-            const int64_t col = P.nsb ? (int64_t)(gn / P.nsb) * P.nob + gn % P.nsb : gn;
-            bbase = (int64_t)bk0 * P.ldb + col;
-        }
-        for (int r = 0; r < P.nred; ++r) {
-            const T* A = Ab + (int64_t)r * P.rsA + abase;
-            const T* B = Bb + (int64_t)r * P.rsB + bbase;
-            auto fetch = [&](int c) {
-                const int k0 = c * KC;
-                const T* pa = A + k0 * akm;
-                const T* pb = B + k0 * bkm;
-#pragma unroll
-                for (int e = 0; e < AE; ++e) {
-                    T v = (T)0;
-                    if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
-                    ra[e] = v * alpha;
-                }
-#pragma unroll
-                for (int e = 0; e < BE; ++e) {
-                    T v = (T)0;
-                    if (n0 + bn0 + e * bnE < J.N && k0 + bk0 + e * bkE < P.K) v = pb[e * bes];
-                    rb[e] = v;
-                }
-            };
-            auto stash = [&](int buf) {
-#pragma unroll
-                for (int e = 0; e < AE; ++e) As[buf][ak0 + e * akE][am0 + e * amE] = ra[e];
-#pragma unroll
-                for (int e = 0; e < BE; ++e) Bs[buf][bk0 + e * bkE][bn0 + e * bnE] = rb[e];
-            };
-            // the previous product's last chunk may still be read from
-            // buffer 0 by other waves
+        // The other products run as one flat sequence of (product, reduction,
+        // chunk) steps: the next step's operands are fetched while the current
+        // chunk is multiplied, also across product boundaries.
+        struct Step {
+            const T* A;   // element 0 of this thread at k0 = 0
+            const T* B;
+            int64_t akm, aes, bkm, bes;
+            int am0, amE, ak0, akE, bn0, bnE, bk0, bkE;
+            int K, nchunk, nred;
+            T alpha;
+        };
+        auto describe = [&](int p, int r, Step& D) {
+            const GProd P = prods[p];
+            const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
+            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            D.am0 = P.tA ? t_tm : t_kq;
+            D.amE = P.tA ? 0 : ASA;
+            D.ak0 = P.tA ? t_tq : t_kc;
+            D.akE = P.tA ? ASB : 0;
+            D.akm = P.tA ? (int64_t)P.lda : 1;
+            D.aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
+            const int64_t abase =
+                P.tA ? (int64_t)D.ak0 * P.lda + m0 + D.am0 : (int64_t)(m0 + D.am0) * P.lda + D.ak0;
+            D.bn0 = P.tB ? t_kq : t_tn;
+            D.bnE = P.tB ? BSB : 0;
+            D.bk0 = P.tB ? t_kc : t_nq;
+            D.bkE = P.tB ? 0 : BSN;
+            D.bkm = P.tB ? 1 : (int64_t)P.ldb;
+            D.bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
+            int64_t bbase;
+            if (P.tB) {
+                bbase = (int64_t)(n0 + D.bn0) * P.ldb + D.bk0;
+            } else {
+                const int gn = n0 + D.bn0;
+                const int64_t col = P.nsb ? (int64_t)(gn / P.nsb) * P.nob + gn % P.nsb : gn;
+                bbase = (int64_t)D.bk0 * P.ldb + col;
+            }
+            D.A = Ab + (int64_t)r * P.rsA + abase;
+            D.B = Bb + (int64_t)r * P.rsB + bbase;
+            D.K = P.K;
+            D.nchunk = (P.K + KC - 1) / KC;
+            D.nred = P.nred;
+            D.alpha = (T)P.alpha;
+        };
+        auto fetch = [&](const Step& D, int c) {
+            const int k0 = c * KC;
+            const T* pa = D.A + k0 * D.akm;
+            const T* pb = D.B + k0 * D.bkm;
+    #pragma unroll
+            for (int e = 0; e < AE; ++e) {
+                T v = (T)0;
+                if (m0 + D.am0 + e * D.amE < J.M && k0 + D.ak0 + e * D.akE < D.K) v = pa[e * D.aes];
+                ra[e] = v * D.alpha;
+            }
+    #pragma unroll
+            for (int e = 0; e < BE; ++e) {
+                T v = (T)0;
+                if (n0 + D.bn0 + e * D.bnE < J.N && k0 + D.bk0 + e * D.bkE < D.K) v = pb[e * D.bes];
+                rb[e] = v;
+            }
+        };
+        auto stash = [&](const Step& D, int buf) {
+    #pragma unroll
+            for (int e = 0; e < AE; ++e) As[buf][D.ak0 + e * D.akE][D.am0 + e * D.amE] = ra[e];
+    #pragma unroll
+            for (int e = 0; e < BE; ++e) Bs[buf][D.bk0 + e * D.bkE][D.bn0 + e * D.bnE] = rb[e];
+        };
+        auto next_product = [&](int p) {
+            while (p < J.p1 && prods[p].ident) ++p;
+            return p;
+        };
+        int p = next_product(J.p0);
+        if (p < J.p1) {
+            Step D;
+            describe(p, 0, D);
+            int r = 0, c = 0, cur = 0;
+            fetch(D, 0);
+            stash(D, 0);
             __syncthreads();
-            fetch(0);
-            stash(0);
-            __syncthreads();
-            for (int c = 0; c < nchunk; ++c) {
-                const int cur = c & 1;
-                if (c + 1 < nchunk) fetch(c + 1);
-#pragma unroll
+            while (true) {
+                int np = p, nr = r, nc = c + 1;
+                if (nc >= D.nchunk) {
+                    nc = 0;
+                    if (++nr >= D.nred) {
+                        nr = 0;
+                        np = next_product(p + 1);
+                    }
+                }
+                const bool more = np < J.p1;
+                if (more) {
+                    if (np != p || nr != r) describe(np, nr, D);
+                    fetch(D, nc);
+                }
+    #pragma unroll
                 for (int kk = 0; kk < KC; kk += 4) {
                     T a[BM], bb[BN];
-#pragma unroll
+    #pragma unroll
                     for (int i = 0; i < BM; ++i) a[i] = As[cur][kk + lk][wm0 + i * 16 + lr];
-#pragma unroll
+    #pragma unroll
                     for (int j = 0; j < BN; ++j) bb[j] = Bs[cur][kk + lk][wn0 + j * 16 + lr];
-#pragma unroll
+    #pragma unroll
                     for (int i = 0; i < BM; ++i)
-#pragma unroll
+    #pragma unroll
                         for (int j = 0; j < BN; ++j) acc[i][j] = Mfma<T>::step(a[i], bb[j], acc[i][j]);
                 }
-                if (c + 1 < nchunk) stash(cur ^ 1);
+                if (!more) break;
+                stash(D, cur ^ 1);
                 __syncthreads();
+                cur ^= 1;
+                p = np;
+                r = nr;
+                c = nc;
             }
         }
     }
@@ -256,24 +393,27 @@ void launch_sum_stage(int dtype, const GJob* jobs, const GProd* prods, const GTi
 
 template <typename T>
 void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
-                   const Bases& bases, int shape, hipStream_t st) {
+                   const Bases& bases, int shape, bool flat, hipStream_t st) {
     if (ntiles <= 0) return;
+#define QED_LAUNCH(WM, WN, F) \
+    hipLaunchKernelGGL((k_brgemm<T, WM, WN, 2, 2, F>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases)
     switch (shape) {
         case GEMM_SHAPE_TALL:
-            hipLaunchKernelGGL((k_brgemm<T, 4, 1, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+            if (flat) QED_LAUNCH(4, 1, true); else QED_LAUNCH(4, 1, false);
             break;
         case GEMM_SHAPE_WIDE:
-            hipLaunchKernelGGL((k_brgemm<T, 1, 4, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+            if (flat) QED_LAUNCH(1, 4, true); else QED_LAUNCH(1, 4, false);
             break;
         default:
-            hipLaunchKernelGGL((k_brgemm<T, 2, 2, 2, 2>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases);
+            if (flat) QED_LAUNCH(2, 2, true); else QED_LAUNCH(2, 2, false);
     }
+#undef QED_LAUNCH
 }
 
 template void launch_brgemm<double>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
-                                    hipStream_t);
+                                    bool, hipStream_t);
 template void launch_brgemm<float>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
-                                   hipStream_t);
+                                   bool, hipStream_t);
 
 // ---------------------------------------------------------------------
 // element-wise helpers
