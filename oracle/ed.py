@@ -89,6 +89,8 @@ class OriginalED:
         for i in range(self.dim):
             phi, E = self.phi[i], self.E[i]
             diag = c.m * float(np.dot(sgn, phi)) + 0.5 * c.g2e * float(np.dot(E, E))
+            if c.mu:
+                diag += float(np.dot(np.asarray(c.mu, dtype=float), phi))
             rows.append(i); cols.append(i); vals.append(diag)
             # hopping psi^dag_x U psi_y and its conjugate
             for li, (x, mu, y) in enumerate(self.links):

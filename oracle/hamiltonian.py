@@ -2,7 +2,7 @@
 
 Eq. 1 (Results, "The model"):
     H = -t  sum_{x,mu} (psi_x^dag U_{x,mu} psi_{x+mu} + h.c.)
-        + m sum_x (-1)^x psi_x^dag psi_x
+        + m sum_x (-1)^x psi_x^dag psi_x  [+ sum_x mu_x psi_x^dag psi_x]
         + (g_e^2/2) sum_{x,mu} E_{x,mu}^2
         - (g_m^2/2) sum_x (box_xy + box_xz + box_yz + h.c.)
     box_{a,b} = U_{x,a} U_{x+a,b} U^dag_{x+b,a} U^dag_{x,b}
@@ -44,6 +44,10 @@ class Couplings:
     m: float = 1.0
     g2e: float = 1.0
     g2m: float = 1.0
+    # local chemical potentials mu_x (one per site, or empty for none): the
+    # term sum_x mu_x psi_x^dag psi_x that pins charges (Results, the
+    # capacitor and confinement set-ups)
+    mu: tuple = ()
 
 
 def physical_line(g2, t=1.0):
@@ -109,6 +113,8 @@ class Hamiltonian:
             so = self.site_ops[s]
             p = lat.parity(s)
             h = c.m * (1 - 2 * p) * so.phi()
+            if c.mu:
+                h = h + c.mu[s] * so.phi()
             pres = lat.present(s)
             for j in range(6):
                 Ej = np.eye(so.d) - so.kdiag(j)

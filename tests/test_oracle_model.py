@@ -254,3 +254,27 @@ def test_hamiltonian_is_symmetric_and_gauss_preserving():
     q = product_charges(ham)
     r, c = np.nonzero(np.abs(H) > 0)
     assert np.all(q[r] == q[c])
+
+
+# -- local chemical potentials ---------------------------------------------
+@pytest.mark.parametrize("mu0,mu1", [(0.3, -0.2), (-1.5, 2.0)])
+def test_chemical_potential_two_site_closed_form(mu0, mu1):
+    # vacuum phi = (0, 1), pair phi = (1, 0):
+    # H = [[-m + mu1, -t], [-t, m + g_e^2/2 + mu0]]
+    m, g2e, t = 0.7, 1.3, 0.9
+    c = Couplings(t=t, m=m, g2e=g2e, g2m=0.0, mu=(mu0, mu1))
+    lat = Lattice(2, 1, 1)
+    a, d = -m + mu1, m + 0.5 * g2e + mu0
+    e0 = 0.5 * (a + d) - np.sqrt(0.25 * (d - a) ** 2 + t ** 2)
+    assert abs(DressedED(Hamiltonian(lat, c)).spectrum()[0] - e0) < 1e-13
+    assert abs(OriginalED(lat, c).spectrum()[0] - e0) < 1e-13
+
+
+def test_chemical_potential_both_formulations_2x2x1():
+    mu = tuple(np.random.default_rng(3).uniform(-1.0, 1.0, 4))
+    c = Couplings(t=1.0, m=0.7, g2e=1.3, g2m=0.9, mu=mu)
+    lat = Lattice(2, 2, 1)
+    o, d = OriginalED(lat, c).spectrum(), DressedED(Hamiltonian(lat, c)).spectrum()
+    assert np.abs(o - d).max() < 1e-12
+    # and the potentials matter
+    assert abs(o[0] - OriginalED(lat, CPL).spectrum()[0]) > 1e-3
