@@ -119,6 +119,15 @@ int qed_set_lattice(qed_ctx* ctx, int Lx, int Ly, int Lz, int bc);
  * magnetic g_m^2 (treated as independent, as in the paper). */
 int qed_set_couplings(qed_ctx* ctx, double t, double m, double g2_e, double g2_m);
 
+/* Local chemical potentials: adds sum_x mu_x psi_x^dag psi_x to Eq. 1, the
+ * large boundary or pinning potentials of the capacitor and confinement
+ * set-ups (Results).  mu: host array of Lx*Ly*Lz doubles in site order
+ * (copied), or NULL to remove them.  Needs qed_set_lattice first (which
+ * clears them); takes effect at the next qed_build_hamiltonian.
+ * QED_ERR_BAD_STATE without a lattice, QED_ERR_INVALID_ARG for non-finite
+ * values. */
+int qed_set_chemical_potential(qed_ctx* ctx, const double* mu);
+
 /* Physical line (Results): with a = 1/t, g_e^2 = g^2 t, g_m^2 = 8 t / g^2,
  * so that g_e g_m = 2 sqrt(2) t.  Pure function, no context. */
 int qed_physical_line(double g2, double t, double* g2_e, double* g2_m);

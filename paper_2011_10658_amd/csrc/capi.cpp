@@ -204,6 +204,24 @@ int qed_set_lattice(qed_ctx* ctx, int Lx, int Ly, int Lz, int bc) {
         P.Lz = Lz;
         P.bc = bc;
         P.have_lattice = true;
+        P.mu.clear();   // one potential per site: reset with the lattice
+        C(ctx).built = false;
+        return QED_OK;
+    });
+}
+
+int qed_set_chemical_potential(qed_ctx* ctx, const double* mu) {
+    return guard(ctx, [&] {
+        Params& P = C(ctx).prm;
+        if (!P.have_lattice) fail(QED_ERR_BAD_STATE, "call qed_set_lattice first");
+        const int n = P.Lx * P.Ly * P.Lz;
+        std::vector<double> v;
+        if (mu) {
+            v.assign(mu, mu + n);
+            for (double x : v)
+                if (!std::isfinite(x)) fail(QED_ERR_INVALID_ARG, "chemical potentials must be finite");
+        }
+        P.mu = v;
         C(ctx).built = false;
         return QED_OK;
     });

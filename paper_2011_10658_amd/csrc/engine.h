@@ -323,6 +323,7 @@ struct EnvD {
 struct Params {
     int Lx = 0, Ly = 0, Lz = 0, bc = QED_BC_OPEN_ZERO_FLUX;
     double t = 1, m = 1, g2e = 1, g2m = 1;
+    std::vector<double> mu;   // local chemical potentials, one per site (empty: none)
     double nu_max = 10.0;
     int n_lin = 0, n_quad = 0;
     int Q = 0, chi = 16;

@@ -56,6 +56,7 @@ void Engine::build(Ctx* c) {
     model.m = P.m;
     model.g2e = P.g2e;
     model.g2m = P.g2m;
+    model.mu = P.mu;
     model.build();
     if (P.bc == QED_BC_OPEN_ZERO_FLUX && P.Q != 0)
         fail(QED_ERR_INVALID_ARG, "zero-flux boundaries admit only total charge Q = 0");

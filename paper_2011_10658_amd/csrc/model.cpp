@@ -16,6 +16,7 @@
 //             corners; -(g_m^2/2)(box + box^dag)
 //   onsite    m (-1)^x phi + (g_e^2/2) sum (1 - k_{+mu})^2 over the
 //             site's +mu links (+ dangling half-links under free flux)
+//             [+ mu_x phi with local chemical potentials]
 //   penalty   nu (1 - sum_a P^a_{x,+mu} P^{2-a}_{x+mu,-mu}) per link, built
 //             as nu sum_a P^a_{x,+mu} (1 - P^{2-a}_{x+mu,-mu}) (equal, since
 //             sum_a P^a = 1): three nonnegative terms that vanish on links
@@ -186,6 +187,7 @@ void Model::build() {
         for (int i = 0; i < b.d(); ++i) {
             const auto& r = sites[s].rows[i];
             double v = m * (1 - 2 * p) * r[0];
+            if (!mu.empty()) v += mu[s] * r[0];
             for (int j = 0; j < 6; ++j) {
                 double E = 1.0 - r[1 + j];
                 if ((j >= 3 && present[j]) || (L.bc == QED_BC_OPEN_FREE_FLUX && !present[j]))

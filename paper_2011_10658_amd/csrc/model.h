@@ -67,6 +67,7 @@ struct Term {
 struct Model {
     Lattice lat;
     double t = 1, m = 1, g2e = 1, g2m = 1;
+    std::vector<double> mu;   // local chemical potentials (one per site, or empty)
     std::vector<Site> sites;
     std::vector<Term> terms;
     double offset[2] = {0.0, 0.0};   // constant parts per class

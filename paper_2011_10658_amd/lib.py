@@ -75,6 +75,7 @@ SIGNATURES = {
     "qed_set_stream": [_P, _P],
     "qed_set_lattice": [_P, _I, _I, _I, _I],
     "qed_set_couplings": [_P, _D, _D, _D, _D],
+    "qed_set_chemical_potential": [_P, _DP],
     "qed_physical_line": [_D, _D, _DP, _DP],
     "qed_set_penalty": [_P, _D, _I, _I, _I],
     "qed_set_charge_sector": [_P, _I],
@@ -215,9 +216,20 @@ class Context:
 
     def set_lattice(self, Lx, Ly, Lz, bc=BC_OPEN_ZERO_FLUX):
         self._c(self.lib.qed_set_lattice(self.h, Lx, Ly, Lz, bc))
+        self._nsites = Lx * Ly * Lz
 
     def set_couplings(self, t, m, g2e, g2m):
         self._c(self.lib.qed_set_couplings(self.h, t, m, g2e, g2m))
+
+    def set_chemical_potential(self, mu):
+        """mu: one value per site (site order), or None to remove."""
+        if mu is None:
+            self._c(self.lib.qed_set_chemical_potential(self.h, None))
+            return
+        a = np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)
+        if a.size != getattr(self, "_nsites", -1):
+            raise ValueError("need one chemical potential per site (call set_lattice first)")
+        self._c(self.lib.qed_set_chemical_potential(self.h, a.ctypes.data_as(_DP)))
 
     def set_penalty(self, nu_max, n_linear=0, n_quadratic=0, adaptive=0):
         self._c(self.lib.qed_set_penalty(self.h, nu_max, n_linear, n_quadratic, adaptive))

@@ -200,3 +200,18 @@ def test_checkpoint_file_checks(tmp_path):
     with pytest.raises(lib.QedError) as e:
         ctx.save_state(str(tmp_path / "x.ckpt"))
     assert e.value.code == -2
+
+
+def test_chemical_potential_arguments():
+    ctx = lib.Context(-1)
+    with pytest.raises(lib.QedError) as e:
+        ctx._c(ctx.lib.qed_set_chemical_potential(ctx.h, None))
+    assert e.value.code == -2
+    ctx.set_lattice(2, 2, 1)
+    with pytest.raises(ValueError):
+        ctx.set_chemical_potential([0.1, 0.2])
+    with pytest.raises(lib.QedError) as e:
+        ctx.set_chemical_potential([0.0, float("nan"), 0.0, 0.0])
+    assert e.value.code == -1
+    ctx.set_chemical_potential([0.1, -0.2, 0.3, 0.0])
+    ctx.set_chemical_potential(None)

@@ -377,3 +377,28 @@ def test_config2_zero_flux_against_ed(ctx, g2):
         energies.append(e)
     assert energies[1] <= energies[0] + 1e-9 * abs(e0), energies
     assert energies[1] - e0 <= 1e-2 * abs(e0), (energies, e0)
+
+
+@pytest.mark.parametrize("L,bc,Q", [((2, 1, 1), 0, 0), ((2, 2, 1), 0, 0), ((2, 1, 1), 1, 1)])
+def test_chemical_potential_sweep_equals_ed(ctx, L, bc, Q):
+    """Local chemical potentials (pinning terms): at exact bond dimension the
+    sweep energy equals the original-formulation ED with the same
+    potentials, and the occupations follow them."""
+    n = L[0] * L[1] * L[2]
+    mu = synth.sym_uniform(77, 0, n) * 1.5
+    cpl = Couplings(t=1.0, m=0.7, g2e=1.3, g2m=0.9, mu=tuple(mu))
+    ctx.set_lattice(*L, bc)
+    ctx.set_couplings(cpl.t, cpl.m, cpl.g2e, cpl.g2m)
+    ctx.set_chemical_potential(mu)
+    ctx.set_charge_sector(Q)
+    ctx.set_bond_dim(64)
+    ctx.set_penalty(20.0, 0, 0)
+    ctx.set_lanczos(40, 3, 1e-13)
+    ctx.set_precision(lib.FP64)
+    ctx.build_hamiltonian()
+    ctx.init_state(11)
+    reps = ctx.sweep(3)
+    lat = Lattice(*L, boundary="zero_flux" if bc == 0 else "free_flux")
+    e0 = OriginalED(lat, cpl, Q=Q).spectrum()[0]
+    assert abs(reps[-1]["energy"] - e0) < 1e-10 * abs(e0), (reps[-1]["energy"], e0)
+    ctx.set_chemical_potential(None)
