@@ -231,7 +231,52 @@ int qed_get_energy(qed_ctx* ctx, double* E);
 int qed_get_observables(qed_ctx* ctx, double* occ, double* efield, double* deltaL,
                         double* rho, double* Q);
 
-/* Cumulative counters of the context.  matvec_flops / matvecs: algorithmic
+/* Per-site local charge and flux of the current state: charge[N] =
+ * <q_x> with q_x = psi^dag psi - (1 - (-1)^x)/2 (the charge of Gauss's
+ * law, Results "The model"); flux[6N] = outgoing electric flux on the six
+ * half-links of each site in the order -x, -y, -z, +x, +y, +z (E_{x,mu}
+ * on +mu, -E_{x-mu,mu} on -mu, the dangling flux on a free-flux boundary
+ * half-link, 0 on a zero-flux one).  Gauss's law: sum_h flux = charge.
+ * Any output pointer may be NULL. */
+int qed_get_site_fluxes(qed_ctx* ctx, double* charge, double* flux);
+
+/* Plane profiles along axis a in {0,1,2} (Results, "Quantum capacitor":
+ * charge density and transverse field per plane).  With A the number of
+ * sites of a plane orthogonal to a:
+ *   qc[d] = (2/A) sum_{x in plane d} <q_x>,            d = 0 .. L_a - 1
+ *   ec[d] = (2/A) sum_{x in plane d-1} <E_{x,a}>,      d = 1 .. L_a - 1
+ * and ec[0], ec[L_a] the field through the lower and upper faces (the
+ * dangling half-links; 0 under the zero-flux boundary).  qc holds L_a and
+ * ec L_a + 1 doubles (caller-owned host arrays, either may be NULL).
+ * q_x is the charge of qed_get_site_fluxes: the paper's staggered
+ * psi^dag psi in the convention where the vacuum carries no charge.
+ * Under zero flux, ec[d+1] - ec[d] = qc[d] whenever every link obeys the
+ * rishon constraint L = 2 (the physical subspace); otherwise the
+ * difference is -(2/A) times the sum of <2 - L> over the links that enter
+ * plane d or lie inside it. */
+int qed_get_plane_profiles(qed_ctx* ctx, int axis, double* qc, double* ec);
+
+/* Surface charge density (Results, "Finite density", surface density
+ * equation): sigma[l-1] = mean of <q_x> over the sites whose distance to
+ * the closest boundary is l, l = 1 (surface) .. nshell, with nshell =
+ * 1 + (min(Lx, Ly, Lz) - 1) / 2.  *nshell is written when non-NULL;
+ * sigma (host, nshell doubles) may be NULL to query the count. */
+int qed_get_surface_density(qed_ctx* ctx, double* sigma, int* nshell);
+
+/* Pin static charges with large local chemical potentials (Results,
+ * "Confinement properties" and "Quantum capacitor"): for each i, site
+ * sites[i] gets mu += -lambda when charges[i] + parity = 1 (filled) and
+ * +lambda when it is 0 (empty); +1 needs an even site, -1 an odd site, 0
+ * pins the site's vacuum occupation.  Adds to the potentials already set
+ * (qed_set_chemical_potential; qed_set_lattice clears both); takes effect
+ * at the next qed_build_hamiltonian.  The pinning energy is part of the
+ * ground-state energy, so V(r) = E(r) - E_0 carries the r-independent
+ * constant -lambda per pinned pair.  QED_ERR_INVALID_ARG for a site out of
+ * range or pinned twice, a charge the site's parity cannot hold, or
+ * lambda not finite and positive; QED_ERR_BAD_STATE without a lattice. */
+int qed_pin_charges(qed_ctx* ctx, int n, const int* sites, const int* charges, double lambda);
+
+/* Cumulative counters of the context./* Cumulative counters of the context.  matvec_flops / matvecs: algorithmic
  * work of every H_eff application (sweeps and node-level objects).
  * With profiling on, every launch of the block-GEMM kernel that belongs
  * to an H_eff application is bracketed by HIP events on the context's

@@ -11,7 +11,10 @@ Local inputs are per site x:
                  on a -mu half-link it is -E_{x-mu,mu}; a dangling
                  boundary half-link carries its own flux; a half-link with
                  no field (zero-flux boundary) carries 0.
-Gauss's law reads sum_h flux[x, h] = charge[x] on every site.
+Gauss's law reads sum_h flux[x, h] = charge[x] on every site.  The
+fluxes of the two halves of a link cancel only in the physical subspace
+(rishon number 2 on the link), so plane-summed relations hold exactly
+there and, for a dressed-site state outside it, up to the link defects.
 
 Profiles (Results, "Quantum capacitor" and "Finite density"):
     q_c(d)  = (2/A) sum over plane d of <q_x>,         d = 0 .. L_a - 1

@@ -609,6 +609,129 @@ int qed_get_observables(qed_ctx* ctx, double* occ, double* efield, double* delta
     });
 }
 
+namespace {
+
+// Per-site Gauss-law charge <phi - p> and outgoing half-link fluxes
+// <1 - k_h> (h = -x, -y, -z, +x, +y, +z) of the current state.
+void site_fluxes(qed::Engine& e, std::vector<double>& charge, std::vector<double>& flux) {
+    std::vector<double> s7;
+    e.observables(s7);
+    const qed::Lattice& L = e.model.lat;
+    charge.assign(L.N, 0.0);
+    flux.assign((size_t)L.N * 6, 0.0);
+    for (int x = 0; x < L.N; ++x) {
+        charge[x] = s7[x * 7] - L.parity(x);
+        for (int h = 0; h < 6; ++h) flux[(size_t)x * 6 + h] = 1.0 - s7[x * 7 + 1 + h];
+    }
+}
+
+int shell_count(const qed::Lattice& L) {
+    int m = L.L[0];
+    for (int a = 1; a < 3; ++a) m = std::min(m, L.L[a]);
+    return 1 + (m - 1) / 2;
+}
+
+}  // namespace
+
+int qed_get_site_fluxes(qed_ctx* ctx, double* charge, double* flux) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state");
+        std::vector<double> q, f;
+        site_fluxes(e, q, f);
+        if (charge) std::copy(q.begin(), q.end(), charge);
+        if (flux) std::copy(f.begin(), f.end(), flux);
+        return QED_OK;
+    });
+}
+
+int qed_get_plane_profiles(qed_ctx* ctx, int axis, double* qc, double* ec) {
+    return guard(ctx, [&] {
+        if (axis < 0 || axis > 2) fail(QED_ERR_INVALID_ARG, "axis must be 0, 1 or 2");
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state");
+        std::vector<double> q, f;
+        site_fluxes(e, q, f);
+        const Lattice& L = e.model.lat;
+        const int La = L.L[axis];
+        const double w = 2.0 * La / L.N;  // 2 / (sites per plane)
+        std::vector<double> sq(La, 0.0), se(La + 1, 0.0);
+        for (int x = 0; x < L.N; ++x) {
+            int c[3];
+            L.coords(x, c);
+            const int d = c[axis];
+            sq[d] += q[x];
+            se[d + 1] += f[(size_t)x * 6 + 3 + axis];
+            if (d == 0) se[0] -= f[(size_t)x * 6 + axis];
+        }
+        if (qc)
+            for (int d = 0; d < La; ++d) qc[d] = w * sq[d];
+        if (ec)
+            for (int d = 0; d <= La; ++d) ec[d] = w * se[d];
+        return QED_OK;
+    });
+}
+
+int qed_get_surface_density(qed_ctx* ctx, double* sigma, int* nshell) {
+    return guard(ctx, [&] {
+        need_device(C(ctx));
+        need_built(C(ctx));
+        Engine& e = *C(ctx).eng;
+        if (e.nodes.empty()) fail(QED_ERR_BAD_STATE, "no state");
+        const Lattice& L = e.model.lat;
+        const int ns = shell_count(L);
+        if (nshell) *nshell = ns;
+        if (!sigma) return QED_OK;
+        std::vector<double> q, f;
+        site_fluxes(e, q, f);
+        std::vector<double> tot(ns, 0.0);
+        std::vector<int> cnt(ns, 0);
+        for (int x = 0; x < L.N; ++x) {
+            int c[3];
+            L.coords(x, c);
+            int l = INT32_MAX;
+            for (int a = 0; a < 3; ++a) l = std::min(l, std::min(c[a], L.L[a] - 1 - c[a]));
+            tot[l] += q[x];
+            ++cnt[l];
+        }
+        for (int l = 0; l < ns; ++l) sigma[l] = tot[l] / cnt[l];
+        return QED_OK;
+    });
+}
+
+int qed_pin_charges(qed_ctx* ctx, int n, const int* sites, const int* charges, double lambda) {
+    return guard(ctx, [&] {
+        Params& P = C(ctx).prm;
+        if (!P.have_lattice) fail(QED_ERR_BAD_STATE, "call qed_set_lattice first");
+        if (n < 0 || (n > 0 && (!sites || !charges)))
+            fail(QED_ERR_INVALID_ARG, "need n >= 0 sites and charges");
+        if (!std::isfinite(lambda) || lambda <= 0.0)
+            fail(QED_ERR_INVALID_ARG, "lambda must be finite and positive");
+        const int N = P.Lx * P.Ly * P.Lz;
+        std::vector<double> mu = P.mu.empty() ? std::vector<double>(N, 0.0) : P.mu;
+        std::vector<char> seen(N, 0);
+        for (int i = 0; i < n; ++i) {
+            const int s = sites[i], q = charges[i];
+            if (s < 0 || s >= N) fail(QED_ERR_INVALID_ARG, "site index out of range");
+            if (seen[s]) fail(QED_ERR_INVALID_ARG, "site pinned twice");
+            seen[s] = 1;
+            const int p = (s % P.Lx + (s / P.Lx) % P.Ly + s / (P.Lx * P.Ly)) & 1;
+            const int occ = q + p;
+            if (occ != 0 && occ != 1)
+                fail(QED_ERR_INVALID_ARG, "charge cannot sit on a site of this parity "
+                                          "(+1 needs an even site, -1 an odd site)");
+            mu[s] += occ == 1 ? -lambda : lambda;
+        }
+        P.mu = mu;
+        C(ctx).built = false;
+        return QED_OK;
+    });
+}
+
 int qed_set_profiling(qed_ctx* ctx, int on) {
     return guard(ctx, [&] {
         need_device(C(ctx));

@@ -98,6 +98,10 @@ SIGNATURES = {
     "qed_debug_poison": [_P, _I],
     "qed_get_energy": [_P, _DP],
     "qed_get_observables": [_P, _DP, _DP, _DP, _DP, _DP],
+    "qed_get_site_fluxes": [_P, _DP, _DP],
+    "qed_get_plane_profiles": [_P, C.c_int, _DP, _DP],
+    "qed_get_surface_density": [_P, _DP, _IP],
+    "qed_pin_charges": [_P, C.c_int, _IP, _IP, C.c_double],
     "qed_heff_batch_create": [_P, _I, C.POINTER(HeffDesc), C.POINTER(_P)],
     "qed_heff_batch_destroy": [_P],
     "qed_heff_batch_size": [_P, _LP, _LP],
@@ -217,6 +221,7 @@ class Context:
     def set_lattice(self, Lx, Ly, Lz, bc=BC_OPEN_ZERO_FLUX):
         self._c(self.lib.qed_set_lattice(self.h, Lx, Ly, Lz, bc))
         self._nsites = Lx * Ly * Lz
+        self._dims = (Lx, Ly, Lz)
 
     def set_couplings(self, t, m, g2e, g2m):
         self._c(self.lib.qed_set_couplings(self.h, t, m, g2e, g2m))
@@ -327,6 +332,38 @@ class Context:
                                              C.byref(rho), C.byref(Q)))
         return dict(occ=occ, efield=ef.reshape(ns, 3), deltaL=dL.value, rho=rho.value,
                     Q=Q.value)
+
+    def site_fluxes(self):
+        """(charge[N], flux[N, 6]): Gauss-law charge and outgoing half-link
+        fluxes per site."""
+        ns = self._nsites
+        q, f = np.zeros(ns), np.zeros(6 * ns)
+        self._c(self.lib.qed_get_site_fluxes(self.h, q.ctypes.data_as(_DP), f.ctypes.data_as(_DP)))
+        return q, f.reshape(ns, 6)
+
+    def plane_profiles(self, axis):
+        """(qc[L_a], ec[L_a + 1]) along `axis`."""
+        if axis not in (0, 1, 2):
+            raise ValueError("axis must be 0, 1 or 2")
+        La = self._dims[axis]
+        qc, ec = np.zeros(La), np.zeros(La + 1)
+        self._c(self.lib.qed_get_plane_profiles(self.h, axis, qc.ctypes.data_as(_DP),
+                                                ec.ctypes.data_as(_DP)))
+        return qc, ec
+
+    def surface_density(self):
+        n = C.c_int()
+        self._c(self.lib.qed_get_surface_density(self.h, None, C.byref(n)))
+        sig = np.zeros(n.value)
+        self._c(self.lib.qed_get_surface_density(self.h, sig.ctypes.data_as(_DP), C.byref(n)))
+        return sig
+
+    def pin_charges(self, pins, lam):
+        """pins: {site: charge in (-1, 0, +1)}; adds pinning potentials."""
+        sites = np.ascontiguousarray(list(pins.keys()), dtype=np.int32)
+        qs = np.ascontiguousarray(list(pins.values()), dtype=np.int32)
+        self._c(self.lib.qed_pin_charges(self.h, len(sites), sites.ctypes.data_as(_IP),
+                                         qs.ctypes.data_as(_IP), lam))
 
     def set_profiling(self, on):
         self._c(self.lib.qed_set_profiling(self.h, 1 if on else 0))

@@ -2,6 +2,7 @@
 every symbol the header declares, and its integer work (local bases, tree
 sectors, block tables) is bit-exact against the oracle."""
 
+import ctypes as C
 import os
 import re
 
@@ -215,3 +216,41 @@ def test_chemical_potential_arguments():
     assert e.value.code == -1
     ctx.set_chemical_potential([0.1, -0.2, 0.3, 0.0])
     ctx.set_chemical_potential(None)
+
+
+def test_pin_charges_arguments():
+    ctx = lib.Context(-1)
+    with pytest.raises(lib.QedError) as e:
+        ctx.pin_charges({0: 1}, 10.0)
+    assert e.value.code == -2
+    ctx.set_lattice(4, 1, 1)
+    bad = [({1: +1}, 10.0),          # +1 on an odd site
+           ({0: -1}, 10.0),          # -1 on an even site
+           ({4: 0}, 10.0),           # site out of range
+           ({-1: 0}, 10.0),
+           ({0: 2}, 10.0),
+           ({0: 1}, 0.0),            # lambda must be positive
+           ({0: 1}, float("inf"))]
+    for pins, lam in bad:
+        with pytest.raises(lib.QedError) as e:
+            ctx.pin_charges(pins, lam)
+        assert e.value.code == -1, (pins, lam)
+    sites = (C.c_int * 2)(0, 0)
+    qs = (C.c_int * 2)(1, 1)
+    with pytest.raises(lib.QedError) as e:
+        ctx._c(ctx.lib.qed_pin_charges(ctx.h, 2, sites, qs, 5.0))
+    assert e.value.code == -1
+    ctx.pin_charges({0: 1, 1: -1, 2: 0, 3: 0}, 5.0)
+    ctx.close()
+
+
+def test_profile_arguments():
+    ctx = lib.Context(-1)
+    ctx.set_lattice(2, 2, 1)
+    for axis in (-1, 3):
+        with pytest.raises(lib.QedError) as e:
+            ctx._c(ctx.lib.qed_get_plane_profiles(ctx.h, axis, None, None))
+        assert e.value.code == -1
+    with pytest.raises(ValueError):
+        ctx.plane_profiles(3)
+    ctx.close()
