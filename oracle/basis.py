@@ -13,7 +13,8 @@ Site charge (Results, the Q operator): q = phi - p.
 
 Under the zero-flux boundary reading a half-link with no partner is frozen
 at k = 1 (E = 1 - k = 0), which shrinks the basis; under free-flux it stays
-a free 3-state mode.
+a free 3-state mode.  Periodic lattices freeze only the half-links of axes
+of extent 1 (every other half-link has a partner).
 """
 
 from itertools import product
@@ -41,7 +42,7 @@ def enumerate_states(parity, frozen=(False,) * 6):
 def site_basis(lat, s):
     """Basis rows for site s of Lattice `lat` (respecting the boundary)."""
     p = lat.parity(s)
-    if lat.boundary == "zero_flux":
+    if lat.boundary in ("zero_flux", "periodic"):
         frozen = tuple(not x for x in lat.present(s))
     else:
         frozen = (False,) * 6

@@ -22,6 +22,10 @@ Readings taken where the paper is silent:
   * E^2 of a link is read on the lower site's +mu half-link.
   * Under the free-flux boundary each dangling half-link j carries
     (g_e^2/2) (1 - k_j)^2 and no penalty.
+  * Periodic boundaries: wrapped links get the same hopping, plaquette,
+    electric and penalty terms as interior links (the site operators are
+    bosonic, so no Jordan-Wigner string crosses the lattice); the
+    original-formulation ED, with its explicit fermion signs, pins this.
   * U has unit ladder elements (link-state action in the Methods); the
     alternative S^+/s normalisation is available in the ED module only.
   * The hopping carries no extra staggered phase (none appears in Eq. 1).

@@ -15,12 +15,18 @@ happens to the boundary half-links, see Results "Finite Density"):
     "free_flux": a half-link pointing out of the lattice is a free
                  3-state mode (dangling flux) with electric energy
                  (g_e^2/2) E^2 and no penalty partner.
+    "periodic":  every axis of extent >= 2 wraps around (the zero-charge
+                 transition runs with periodic boundaries, Results); an
+                 axis of extent 1 has no links and its half-links are
+                 frozen as under zero flux.  With extent 2 the two sites
+                 of an axis are joined by two distinct links (the direct
+                 one and the wrapped one).  Only Q = 0 exists.
 """
 
 from itertools import product
 
 AXES = ((1, 0, 0), (0, 1, 0), (0, 0, 1))
-BOUNDARY_MODES = ("zero_flux", "free_flux")
+BOUNDARY_MODES = ("zero_flux", "free_flux", "periodic")
 
 
 class Lattice:
@@ -51,6 +57,8 @@ class Lattice:
         c = list(self.coords(s))
         a = half % 3
         c[a] += 1 if half >= 3 else -1
+        if self.boundary == "periodic" and self.L[a] >= 2:
+            c[a] %= self.L[a]
         return self.index(c) if self.inside(c) else None
 
     # -- links ---------------------------------------------------------
@@ -73,12 +81,11 @@ class Lattice:
         out = []
         for s in range(self.nsites):
             for al, be in ((0, 1), (0, 2), (1, 2)):
-                c = self.coords(s)
-                ca = list(c); ca[al] += 1
-                cb = list(c); cb[be] += 1
-                cab = list(ca); cab[be] += 1
-                if self.inside(ca) and self.inside(cb) and self.inside(cab):
-                    out.append((s, al, be))
+                xa = self.neighbour(s, 3 + al)
+                xb = self.neighbour(s, 3 + be)
+                if xa is None or xb is None or self.neighbour(xa, 3 + be) is None:
+                    continue
+                out.append((s, al, be))
         return out
 
     def all_sites(self):

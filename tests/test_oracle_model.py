@@ -6,7 +6,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import fermions
-from oracle.basis import charge_sectors, enumerate_states
+from oracle.basis import charge_sectors, enumerate_states, site_basis
 from oracle.ed import DressedED, OriginalED, dense_dressed_hamiltonian, product_charges
 from oracle.hamiltonian import Couplings, Hamiltonian, physical_line
 from oracle.lattice import Lattice
@@ -278,3 +278,62 @@ def test_chemical_potential_both_formulations_2x2x1():
     assert np.abs(o - d).max() < 1e-12
     # and the potentials matter
     assert abs(o[0] - OriginalED(lat, CPL).spectrum()[0]) > 1e-3
+
+
+# -- periodic boundaries -----------------------------------------------------
+@pytest.mark.parametrize("L,nlinks,nplaq", [((2, 1, 1), 2, 0), ((4, 1, 1), 4, 0), ((2, 2, 1), 8, 4),
+                                            ((2, 2, 2), 24, 24), ((4, 4, 4), 192, 192),
+                                            ((4, 2, 1), 16, 8)])
+def test_periodic_geometry(L, nlinks, nplaq):
+    lat = Lattice(*L, boundary="periodic")
+    links = lat.links()
+    assert len(links) == nlinks
+    assert len(set((x, mu) for x, mu, _ in links)) == nlinks
+    assert len(lat.plaquettes()) == nplaq
+    for s in range(lat.nsites):
+        for a in range(3):
+            if L[a] >= 2:
+                # the wrap closes every axis
+                y = s
+                for _ in range(L[a]):
+                    y = lat.neighbour(y, 3 + a)
+                assert y == s
+                assert lat.neighbour(lat.neighbour(s, 3 + a), a) == s
+            else:
+                assert lat.neighbour(s, a) is None and lat.neighbour(s, 3 + a) is None
+    # bulk sites everywhere when every extent is >= 2
+    if min(L) >= 2:
+        assert all(site_basis(lat, s).shape[0] == 267 for s in range(lat.nsites))
+
+
+@pytest.mark.parametrize("L", [(2, 1, 1), (4, 1, 1), (2, 2, 1), (1, 2, 2)])
+def test_periodic_dressed_equals_original(L):
+    """Wrapped hopping and plaquettes (and the doubled links of extent-2
+    axes) carry the same signs in both formulations."""
+    lat = Lattice(*L, boundary="periodic")
+    o = OriginalED(lat, CPL).spectrum()
+    d = DressedED(Hamiltonian(lat, CPL)).spectrum()
+    assert len(o) == len(d)
+    assert np.abs(o - d).max() < 1e-11
+    # the wrap matters: the spectrum differs from the open lattice's
+    assert abs(o[0] - OriginalED(Lattice(*L), CPL).spectrum()[0]) > 1e-3
+
+
+def test_periodic_charged_sector_is_empty():
+    lat = Lattice(2, 2, 1, boundary="periodic")
+    assert OriginalED(lat, CPL, Q=1).dim == 0
+    assert DressedED(Hamiltonian(lat, CPL), Q=1).dim == 0
+
+
+@pytest.mark.parametrize("L", [(4, 1, 1), (2, 2, 1)])
+@pytest.mark.parametrize("m", [-2.0, -0.3, 0.4])
+def test_periodic_t0_vacuum_vs_charge_crystal(L, m):
+    """t = 0, g_m = 0 with periodic boundaries: E_v = -m N/2 and the crystal
+    pairs every charge with a neighbour by one unit of flux,
+    E_ch = (m + g_e^2/2) N/2."""
+    g2e = 2.0
+    c = Couplings(t=0.0, m=m, g2e=g2e, g2m=0.0)
+    lat = Lattice(*L, boundary="periodic")
+    N = lat.nsites
+    e0 = DressedED(Hamiltonian(lat, c)).spectrum()[0]
+    assert abs(e0 - min(-m * N / 2, (m + g2e / 2) * N / 2)) < 1e-12

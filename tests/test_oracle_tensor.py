@@ -403,3 +403,16 @@ def test_penalty_schedule_shape():
     assert nus[7] == 40.0 and nus[11] == 40.0
     d = np.diff(nus[3:8])
     assert all(b > a for a, b in zip(d[:-1], d[1:]))  # quadratic stage accelerates
+
+
+@pytest.mark.parametrize("L", [(2, 1, 1), (4, 1, 1), (8, 1, 1)])
+def test_ttn_periodic_exact_bond_dim_equals_ed(L):
+    """Periodic boundaries: wrapped links are terms between distant leaves;
+    at exact bond dimension the sweep reaches the ED ground state."""
+    lat = Lattice(*L, boundary="periodic")
+    e0 = OriginalED(lat, CPL).spectrum()[0]
+    T = _make(lat, CPL, 0, 64)
+    for _ in range(3):
+        E = T.sweep(20.0, m=40, cycles=3, tol=1e-13)
+    assert abs(E - e0) < 1e-10 * abs(e0)
+    assert T.observables()["deltaL"] < 1e-9
