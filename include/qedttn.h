@@ -57,8 +57,10 @@ enum {
  * fixing the outward half-links.  ZERO_FLUX freezes each outward rishon
  * at k = 1 (E = 0; only Q = 0 exists); FREE_FLUX keeps it a free 3-state
  * mode with electric energy (g_e^2/2) E^2 and no penalty partner.
- * PERIODIC (used for the zero-density transition in the paper) is not
- * supported by this version and returns QED_ERR_UNSUPPORTED. */
+ * PERIODIC (the zero-charge transition, Results) wraps every axis of
+ * extent >= 2; an axis of extent 1 has no links and its half-links are
+ * frozen as under ZERO_FLUX.  With extent 2 the two sites of an axis are
+ * joined by two distinct links (direct and wrapped).  Only Q = 0 exists. */
 enum { QED_BC_OPEN_ZERO_FLUX = 0, QED_BC_OPEN_FREE_FLUX = 1, QED_BC_PERIODIC = 2 };
 
 /* Arithmetic of the block GEMMs (H_eff matvec).  Lanczos, QR, the

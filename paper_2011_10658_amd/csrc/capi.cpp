@@ -191,8 +191,7 @@ int qed_set_stream(qed_ctx* ctx, void* stream) {
 
 int qed_set_lattice(qed_ctx* ctx, int Lx, int Ly, int Lz, int bc) {
     return guard(ctx, [&] {
-        if (bc == QED_BC_PERIODIC) fail(QED_ERR_UNSUPPORTED, "periodic boundaries are not supported");
-        if (bc != QED_BC_OPEN_ZERO_FLUX && bc != QED_BC_OPEN_FREE_FLUX)
+        if (bc != QED_BC_OPEN_ZERO_FLUX && bc != QED_BC_OPEN_FREE_FLUX && bc != QED_BC_PERIODIC)
             fail(QED_ERR_INVALID_ARG, "unknown boundary condition");
         if (!pow2(Lx) || !pow2(Ly) || !pow2(Lz))
             fail(QED_ERR_INVALID_ARG, "lattice extents must be powers of two");

@@ -58,8 +58,8 @@ void Engine::build(Ctx* c) {
     model.g2m = P.g2m;
     model.mu = P.mu;
     model.build();
-    if (P.bc == QED_BC_OPEN_ZERO_FLUX && P.Q != 0)
-        fail(QED_ERR_INVALID_ARG, "zero-flux boundaries admit only total charge Q = 0");
+    if (P.bc != QED_BC_OPEN_FREE_FLUX && P.Q != 0)
+        fail(QED_ERR_INVALID_ARG, "zero-flux and periodic boundaries admit only total charge Q = 0");
     tree = Tree();
     tree.build(model.lat);
     std::vector<Leg> sl;

@@ -53,7 +53,7 @@ void build_site(Site& st, int parity, const bool present[6], int bc) {
             bool ok = true;
             for (int j = 0; j < 6; ++j) {
                 sum += r[1 + j];
-                if (bc == QED_BC_OPEN_ZERO_FLUX && !present[j] && r[1 + j] != 1) ok = false;
+                if (bc != QED_BC_OPEN_FREE_FLUX && !present[j] && r[1 + j] != 1) ok = false;
             }
             if (ok && sum == 6 + parity) st.rows.push_back(r);
         }
@@ -161,8 +161,8 @@ struct SiteBuilder {
 
 void Model::build() {
     const Lattice& L = lat;
-    if (L.bc != QED_BC_OPEN_ZERO_FLUX && L.bc != QED_BC_OPEN_FREE_FLUX)
-        fail(QED_ERR_UNSUPPORTED, "only open boundaries are supported");
+    if (L.bc != QED_BC_OPEN_ZERO_FLUX && L.bc != QED_BC_OPEN_FREE_FLUX && L.bc != QED_BC_PERIODIC)
+        fail(QED_ERR_INVALID_ARG, "unknown boundary condition");
     sites.assign(L.N, Site());
     terms.clear();
     offset[0] = offset[1] = 0.0;

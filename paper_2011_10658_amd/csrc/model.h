@@ -26,12 +26,15 @@ struct Lattice {
         coords(s, c);
         return (c[0] + c[1] + c[2]) & 1;
     }
-    // neighbour across half-link h, or -1 at an open boundary
+    // neighbour across half-link h, or -1 at an open boundary; periodic
+    // lattices wrap every axis of extent >= 2 (with extent 2 the wrapped
+    // link is a second link between the same two sites)
     int neighbour(int s, int h) const {
         int c[3];
         coords(s, c);
         int a = h % 3;
         c[a] += h >= 3 ? 1 : -1;
+        if (bc == QED_BC_PERIODIC && L[a] >= 2) c[a] = (c[a] + L[a]) % L[a];
         if (c[a] < 0 || c[a] >= L[a]) return -1;
         return index(c);
     }

@@ -99,8 +99,8 @@ def test_error_paths():
         ctx.set_lattice(3, 2, 2)
     assert e.value.code == -1
     with pytest.raises(lib.QedError) as e:
-        ctx.set_lattice(2, 2, 2, lib.BC_PERIODIC)
-    assert e.value.code == -7
+        ctx.set_lattice(2, 2, 2, 7)
+    assert e.value.code == -1
     with pytest.raises(lib.QedError) as e:
         ctx.build_hamiltonian()
     assert e.value.code == -2
@@ -253,4 +253,23 @@ def test_profile_arguments():
         assert e.value.code == -1
     with pytest.raises(ValueError):
         ctx.plane_profiles(3)
+    ctx.close()
+
+
+@pytest.mark.parametrize("L", [(2, 2, 2), (4, 2, 1), (2, 1, 1), (4, 4, 4)])
+def test_periodic_local_dims_and_charge(L):
+    """Periodic lattices: local dimensions equal the oracle's bases (267
+    wherever every extent is >= 2), and only Q = 0 builds."""
+    ctx = lib.Context(-1)
+    ctx.set_lattice(*L, lib.BC_PERIODIC)
+    ctx.set_couplings(1, 1, 1, 1)
+    ctx.set_bond_dim(16)
+    ctx.build_hamiltonian()
+    lat = Lattice(*L, boundary="periodic")
+    want = [site_basis(lat, s).shape[0] for s in range(lat.nsites)]
+    assert list(ctx.local_dims()) == want
+    ctx.set_charge_sector(2)
+    with pytest.raises(lib.QedError) as e:
+        ctx.build_hamiltonian()
+    assert e.value.code == -1 and "periodic" in str(e.value)
     ctx.close()

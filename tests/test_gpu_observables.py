@@ -44,8 +44,8 @@ def run(ctx, L, bc, cpl, chi, pins=None, lam=0.0, Q=0, sweeps=3, seed=11):
     return ctx.sweep(sweeps)[-1]["energy"]
 
 
-def ed_reference(L, cpl, pins=None, lam=0.0, Q=0):
-    lat = Lattice(*L)
+def ed_reference(L, cpl, pins=None, lam=0.0, Q=0, boundary="zero_flux"):
+    lat = Lattice(*L, boundary=boundary)
     if pins:
         mu = obs.pinning_potentials(L, pins, lam)
         cpl = Couplings(t=cpl.t, m=cpl.m, g2e=cpl.g2e, g2m=cpl.g2m, mu=tuple(mu))
@@ -155,3 +155,23 @@ def test_gauss_relations_4x4x4(ctx):
     assert sig.shape == (2,)
     assert abs(56 * sig[0] + 8 * sig[1] - q.sum()) < 1e-9
     assert np.abs(sig - obs.surface_density(L, q)).max() < 1e-12
+
+
+def test_periodic_ring_profiles_equal_ed(ctx):
+    """A pinned pair on a periodic ring of 8 sites: profiles equal ED's and
+    the two face entries (the wrapped link) coincide."""
+    L = (8, 1, 1)
+    cpl = Couplings(t=0.5, m=1.5, g2e=1.0, g2m=0.0)
+    pins = {2: +1, 5: -1}
+    e = run(ctx, L, lib.BC_PERIODIC, cpl, 64, pins, 20.0)
+    e0, (charge, flux) = ed_reference(L, cpl, pins, 20.0, boundary="periodic")
+    assert abs(e - e0) < 1e-10 * max(1.0, abs(e0)), (e, e0)
+    q, f = ctx.site_fluxes()
+    assert np.abs(q - charge).max() < 1e-8 and np.abs(f - flux).max() < 1e-8
+    qc, ec = ctx.plane_profiles(0)
+    oq, oe = obs.plane_profiles(L, charge, flux, 0)
+    assert np.abs(qc - oq).max() < 1e-8 and np.abs(ec - oe).max() < 1e-8
+    assert abs(ec[0] - ec[-1]) < 1e-12
+    # the string takes the short way round (3 links, not 5)
+    assert np.all(ec[3:6] > 1.5) and np.all(np.abs(ec[[0, 1, 7, 8]]) < 0.2)
+    assert np.abs(np.diff(ec) - qc).max() < 1e-9

@@ -237,13 +237,17 @@ def test_sweep_exact_bond_dim_equals_ed(ctx, L):
     assert ob["deltaL"] < 1e-9
 
 
-@pytest.mark.parametrize("L,bc,Q,chi", [((2, 2, 2), 0, 0, 16), ((2, 2, 1), 1, 1, 24)])
+BC_NAMES = {0: "zero_flux", 1: "free_flux", 2: "periodic"}
+
+
+@pytest.mark.parametrize("L,bc,Q,chi", [((2, 2, 2), 0, 0, 16), ((2, 2, 1), 1, 1, 24),
+                                        ((4, 2, 1), 2, 0, 16)])
 def test_sweep_parity_with_oracle(ctx, L, bc, Q, chi):
     """Same seeded start, same schedule: per-sweep energies and local
     observables agree with the oracle."""
     setup_ctx(ctx, L, bc, Q, chi, CPL, 8.0, steps=20, cycles=1, tol=0.0)
     ctx.init_state(5)
-    T, _ = oracle_ttn(ctx, L, "zero_flux" if bc == 0 else "free_flux", Q, chi, CPL, 5)
+    T, _ = oracle_ttn(ctx, L, BC_NAMES[bc], Q, chi, CPL, 5)
     reps = ctx.sweep(3)
     for s in range(3):
         eo = T.sweep(8.0, m=20, cycles=1, tol=0.0)
@@ -255,6 +259,20 @@ def test_sweep_parity_with_oracle(ctx, L, bc, Q, chi):
     assert abs(ob["deltaL"] - og["deltaL"]) < 1e-8
     assert abs(ob["Q"] - Q) < 1e-10 and abs(og["Q"] - Q) < 1e-10
     assert abs(ob["rho"] - og["rho"]) < 1e-9
+
+
+@pytest.mark.parametrize("L,chi", [((2, 1, 1), 64), ((4, 1, 1), 64), ((2, 2, 1), 256),
+                                   ((1, 2, 2), 256)])
+def test_periodic_sweep_equals_ed(ctx, L, chi):
+    """Periodic boundaries (wrapped and, on extent-2 axes, doubled links):
+    at exact bond dimension the sweep reaches the ED ground state."""
+    setup_ctx(ctx, L, lib.BC_PERIODIC, 0, chi, CPL, 20.0, steps=40, cycles=3, tol=1e-13)
+    ctx.init_state(11)
+    reps = ctx.sweep(3)
+    e0 = OriginalED(Lattice(*L, boundary="periodic"), CPL).spectrum()[0]
+    assert abs(reps[-1]["energy"] - e0) < 1e-10 * abs(e0), (reps[-1]["energy"], e0)
+    ob = ctx.observables()
+    assert abs(ob["Q"]) < 1e-12 and ob["deltaL"] < 1e-9
 
 
 def test_fp32_path_matches_fp64(ctx):
