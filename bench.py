@@ -411,6 +411,98 @@ def finite_density(lib, torch, steps):
     }
 
 
+def observables_workload(lib, torch, steps):
+    """The measurement side of the paper's results on the same kernels:
+    (a) zero-charge transition set-up: 4x4x4 periodic lattice (d = 267 at
+        every site), Q = 0, t = 1, g_e^2/2 = 1, g_m^2 = 4 (physical line),
+        m = 0.2 near the reported critical mass, chi = 64;
+    (b) quantum capacitor: 4x4x4 zero-flux lattice with charged plates on
+        the two x faces pinned by chemical potentials (lambda = 20), m = 3,
+        chi = 64; charge and field profiles along x;
+    (c) confinement: V(r) = E(r) - E_0 of a pinned pair at distance r = 1,
+        3, 5 along x on an 8x2x2 zero-flux lattice (the paper's elongated
+        geometry, thinner), chi = 64, twice as many sweeps.
+    FP32 GEMMs (FP64 Lanczos, QR and energies); `steps` sweeps per ground
+    state from the seeded start; sweep times from the library's clock.  The
+    physics values are those after the given sweeps, not converged results."""
+
+    def ground(L, bc, cpl, chi, pins=None, lam=20.0, prof=False, nsweeps=None):
+        nsw = nsweeps or steps
+        ctx = lib.Context(0)
+        ctx.set_lattice(*L, bc)
+        ctx.set_couplings(*cpl)
+        if pins:
+            ctx.pin_charges(pins, lam)
+        ctx.set_charge_sector(0)
+        ctx.set_bond_dim(chi)
+        ctx.set_penalty(40.0, max(1, nsw // 2), 0)
+        ctx.set_lanczos(16, 1, 1e-8)
+        ctx.set_precision(lib.FP32, 1)
+        ctx.build_hamiltonian()
+        ctx.init_state(SEED)
+        if prof:
+            ctx.set_profiling(True)
+        reps = ctx.sweep(nsw, report=True)
+        st = ctx.stats()
+        return ctx, reps, st
+
+    g2e, g2m = lib.physical_line(2.0, 1.0)
+    out = {}
+    log("== (a) zero-charge transition set-up, 4x4x4 periodic")
+    ctx, reps, st = ground((4, 4, 4), lib.BC_PERIODIC, (1.0, 0.2, g2e, g2m), 64, prof=True)
+    ob = ctx.observables()
+    for i, r in enumerate(reps):
+        log(f"  sweep {i}: E={r['energy']:.10f} {r['seconds']:.2f} s dL={r['deltaL']:.3e}")
+    pbc = dict(sweep_s=[r["seconds"] for r in reps], energies=[r["energy"] for r in reps],
+               rho=ob["rho"], deltaL=ob["deltaL"], Q=ob["Q"],
+               gemm_tflops=st["gemm_flops"] / (st["gemm_ms"] / 1e3) / 1e12 if st["gemm_ms"] else None,
+               matvec_tflops=sum(r["flops"] for r in reps) / sum(r["seconds"] for r in reps) / 1e12)
+    ctx.close()
+    out["zero_charge_pbc"] = pbc
+
+    log("== (b) quantum capacitor, 4x4x4 zero flux, plates on the x faces")
+    pins = {}
+    for k in range(4):
+        for j in range(4):
+            s0, s3 = 0 + 4 * (j + 4 * k), 3 + 4 * (j + 4 * k)
+            pins[s0] = 1 if (j + k) % 2 == 0 else 0      # even sites carry +1
+            pins[s3] = -1 if (3 + j + k) % 2 == 1 else 0  # odd sites carry -1
+    ctx, reps, _ = ground((4, 4, 4), lib.BC_OPEN_ZERO_FLUX, (1.0, 3.0, g2e, g2m), 64, pins)
+    qc, ec = ctx.plane_profiles(0)
+    log(f"  q_c = {np.round(qc, 4).tolist()}  E^c = {np.round(ec, 4).tolist()}")
+    out["capacitor"] = dict(sweep_s=[r["seconds"] for r in reps], energy=reps[-1]["energy"],
+                            q_c=qc.tolist(), E_c=ec.tolist(),
+                            sigma=ctx.surface_density().tolist())
+    ctx.close()
+
+    log("== (c) confinement, 8x2x2 zero flux, pinned pairs")
+    cpl = (1.0, 1.0, g2e, g2m)
+    ctx, reps0, _ = ground((8, 2, 2), lib.BC_OPEN_ZERO_FLUX, cpl, 64, nsweeps=2 * steps)
+    e0 = reps0[-1]["energy"]
+    ctx.close()
+    pot, secs = {}, [r["seconds"] for r in reps0]
+    for r in (1, 3, 5):
+        a = 1 + 8 * (1 + 2 * 0)          # site (1, 1, 0), even: the +1 charge
+        ctx, reps, _ = ground((8, 2, 2), lib.BC_OPEN_ZERO_FLUX, cpl, 64, {a: +1, a + r: -1},
+                              nsweeps=2 * steps)
+        pot[r] = reps[-1]["energy"] - e0
+        secs += [x["seconds"] for x in reps]
+        log(f"  r={r}: E(r)-E0 = {pot[r]:.6f}")
+        ctx.close()
+    out["confinement"] = dict(V_plus_const={str(k): v for k, v in pot.items()}, E0=e0,
+                              sweep_s_mean=sum(secs) / len(secs))
+    return {
+        "metric": METRIC, "value": pbc["matvec_tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "ms_per_step": 1e3 * sum(pbc["sweep_s"]) / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4x4x4 periodic zero-charge sweeps (chi=64, m=0.2, g_e^2=2, "
+                               "g_m^2=4); capacitor and confinement observables",
+                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient"},
+        **out, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def adjoint_workload(lib, torch, steps, warmup, cpu_budget, no_cpu):
     """Differentiation: one node with legs chi = 128 (charges -4..4, sizes
     4,8,16,23,26,23,16,8,4), 24 terms of symmetric sector-preserving factors
@@ -514,7 +606,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("sweep", "batched", "finite_density", "adjoint"),
+    ap.add_argument("--workload", choices=("sweep", "batched", "finite_density", "adjoint",
+                                           "observables"),
                     default="sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one elementwise pass of known size (256 MiB read, 256 MiB "
@@ -540,6 +633,10 @@ def main():
         log("== adjoint workload")
         print(json.dumps(adjoint_workload(lib, torch, a.steps, a.warmup, a.cpu_budget,
                                           a.no_cpu_baseline)), flush=True)
+        return
+    if a.workload == "observables":
+        log("== observables workload")
+        print(json.dumps(observables_workload(lib, torch, a.steps)), flush=True)
         return
     if a.workload == "finite_density":
         log("== finite-density workload")
