@@ -83,6 +83,24 @@ void Heff::build_adjoint() {
                             e, rt[e], outs[e], true);
     J.grads.upload(dev);
     if (dtype != QED_FP64) J.ybc = std::make_shared<DBuf>(dev, tab.size() * es);
+    // c_bar_k = <G_k, A_k> on the term's first present factor; a term with
+    // no factor gets <ybar, x>, whose pointers are bound per call
+    J.dots.clear();
+    for (size_t k = 0; k < terms.size(); ++k) {
+        int first = -1;
+        for (int e = 0; e < 3 && first < 0; ++e)
+            if (J.goff[k][e] >= 0) first = e;
+        AdjSeg s{};
+        s.dot = (int)k;
+        if (first >= 0) {
+            s.src = J.G64->as<double>() + J.goff[k][first];
+            s.a = terms[k].op[first]->f64();
+            s.n = terms[k].op[first]->lay.size;
+        }
+        J.dots.push_back(s);
+    }
+    J.ddots = std::make_shared<DBuf>(dev, std::max<size_t>(1, J.dots.size()) * sizeof(AdjSeg));
+    J.cbar = std::make_shared<DBuf>(dev, std::max<size_t>(1, terms.size()) * sizeof(double));
     J.built = true;
 }
 
@@ -94,6 +112,39 @@ void Heff::adjoint(const double* x, const double* ybar, double* xbar, double* co
     const int dtype = plan.dtype;
     const int es = dtype_size(dtype);
     const int64_t n = tab.size();
+    // segment lists of the gradient post-processing first: their uploads
+    // synchronise the stream, which costs nothing before any work is queued
+    std::vector<AdjSeg> sc;
+    int64_t maxn = 0;
+    if (opbar)
+        for (size_t k = 0; k < terms.size(); ++k)
+            for (int e = 0; e < 3; ++e) {
+                if (J.goff[k][e] < 0 || !opbar[3 * k + e]) continue;
+                AdjSeg sg{};
+                sg.src = J.G64->as<double>() + J.goff[k][e];
+                sg.dst = opbar[3 * k + e];
+                sg.n = terms[k].op[e]->lay.size;
+                sg.scale = terms[k].coef;
+                sg.dot = -1;
+                maxn = std::max(maxn, sg.n);
+                sc.push_back(sg);
+            }
+    void* dsc = nullptr;
+    if (!sc.empty()) {
+        dsc = J.dscale.get(dev, sc.size() * sizeof(AdjSeg));
+        dev->upload(dsc, sc.data(), sc.size() * sizeof(AdjSeg));
+    }
+    if (coefbar) {
+        // terms without a factor contract ybar with x (bound per call)
+        std::vector<AdjSeg> ds = J.dots;
+        for (AdjSeg& sg : ds)
+            if (!sg.src) {
+                sg.src = ybar;
+                sg.a = x;
+                sg.n = n;
+            }
+        dev->upload(J.ddots->p, ds.data(), ds.size() * sizeof(AdjSeg));
+    }
     // operands in the compute dtype
     const void* xc_ = x;
     const void* yb_ = ybar;
@@ -124,29 +175,12 @@ void Heff::adjoint(const double* x, const double* ybar, double* xbar, double* co
     J.grads.run(dev, w, (void*)xc_, (void*)yb_);
     // unscaled gradients in FP64
     launch_scale_to_f64(J.G->p, dtype, J.G64->as<double>(), J.gsize, 1.0, dev->stream);
-    DBuf part(dev, 512 * sizeof(double));
-    DBuf cb(dev, std::max<size_t>(1, terms.size()) * sizeof(double));
-    for (size_t k = 0; k < terms.size(); ++k) {
-        const double c = terms[k].coef;
-        int first = -1;
-        for (int e = 0; e < 3; ++e) {
-            if (J.goff[k][e] < 0) continue;
-            if (first < 0) first = e;
-            if (opbar && opbar[3 * k + e])
-                launch_scale_to_f64(J.G64->as<double>() + J.goff[k][e], QED_FP64, opbar[3 * k + e],
-                                    terms[k].op[e]->lay.size, c, dev->stream);
-        }
-        if (!coefbar) continue;
-        double* dst = cb.as<double>() + k;
-        if (first >= 0) {
-            const int64_t sz = terms[k].op[first]->lay.size;
-            launch_dots(J.G64->as<double>() + J.goff[k][first], sz, 1, terms[k].op[first]->f64(), sz,
-                        part.as<double>(), dst, 0, nullptr, 0, dev->stream);
-        } else {
-            launch_dots(ybar, n, 1, x, n, part.as<double>(), dst, 0, nullptr, 0, dev->stream);
-        }
+    // factor cotangents c_k G: one launch over every requested factor
+    if (dsc) launch_adj_scale((const AdjSeg*)dsc, (int)sc.size(), maxn, dev->stream);
+    if (coefbar) {
+        launch_adj_dots(J.ddots->as<AdjSeg>(), (int)J.dots.size(), J.cbar->as<double>(), dev->stream);
+        dev->download(coefbar, J.cbar->p, terms.size() * sizeof(double));
     }
-    if (coefbar) dev->download(coefbar, cb.p, terms.size() * sizeof(double));
     dev->check(hipGetLastError(), "adjoint");
 }
 

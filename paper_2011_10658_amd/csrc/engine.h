@@ -80,6 +80,8 @@ void launch_f64_to_bf16(const double*, void*, int64_t, hipStream_t);
 void launch_bf16_to_f64(const void*, double*, int64_t, double, hipStream_t);
 void launch_transpose_blocks(const double*, double*, const int64_t*, int, hipStream_t);
 void launch_scale_to_f64(const void*, int, double*, int64_t, double, hipStream_t);
+void launch_adj_scale(const AdjSeg*, int nseg, int64_t maxn, hipStream_t);
+void launch_adj_dots(const AdjSeg*, int nseg, double* out, hipStream_t);
 
 // ---- device memory ---------------------------------------------------
 struct Dev {
@@ -295,6 +297,10 @@ struct Adjoint {
     int64_t gsize = 0;
     BufP G, G64, ybc;
     Arena ws;
+    // coefficient cotangents: one dot segment per term, built once
+    std::vector<AdjSeg> dots;
+    BufP ddots, cbar;
+    Arena dscale;                               // per-call scaling segments
 };
 
 struct Heff {

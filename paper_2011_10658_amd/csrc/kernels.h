@@ -49,6 +49,19 @@ struct GTile {
     int job, b, tm, tn;   // job < 0: an empty slot (the workgroup returns)
 };
 
+// One segment of the adjoint's gradient post-processing: dst[i] =
+// scale * src[i] for i < n (scaling pass, dst may be null), and, in the
+// dot pass, out[dot] = sum_i src[i] * a[i] (dot < 0: none).
+struct AdjSeg {
+    const double* src;
+    double* dst;
+    const double* a;
+    int64_t n;
+    double scale;
+    int dot;
+    int pad;
+};
+
 // Workgroup tile shapes of the block GEMM (rows x cols of the output).
 enum {
     GEMM_SHAPE_SQUARE = 0,   //  64 x  64

@@ -1344,6 +1344,41 @@ void launch_transpose_blocks(const double* src, double* dst, const int64_t* blk,
     hipLaunchKernelGGL(k_transpose_blocks, dim3(nblk), dim3(256), 0, s, src, dst, blk);
 }
 
+// Scaling pass of the adjoint: blockIdx.y selects the segment.
+__global__ __launch_bounds__(256) void k_adj_scale(const AdjSeg* __restrict__ segs) {
+    const AdjSeg S = segs[blockIdx.y];
+    if (!S.dst) return;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * 256)
+        S.dst[i] = S.scale * S.src[i];
+}
+
+// Dot pass: one workgroup per segment, strided partial sums and a fixed
+// tree, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_adj_dots(const AdjSeg* __restrict__ segs, double* out) {
+    const AdjSeg S = segs[blockIdx.x];
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < S.n; i += 256) acc += S.src[i] * S.a[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && S.dot >= 0) out[S.dot] = red[0];
+}
+
+void launch_adj_scale(const AdjSeg* segs, int nseg, int64_t maxn, hipStream_t s) {
+    if (nseg <= 0 || maxn <= 0) return;
+    const int g = (int)std::min<int64_t>(256, (maxn + 255) / 256);
+    hipLaunchKernelGGL(k_adj_scale, dim3(g, nseg), dim3(256), 0, s, segs);
+}
+
+void launch_adj_dots(const AdjSeg* segs, int nseg, double* out, hipStream_t s) {
+    if (nseg <= 0) return;
+    hipLaunchKernelGGL(k_adj_dots, dim3(nseg), dim3(256), 0, s, segs, out);
+}
+
 template <typename S>
 __global__ void k_scale_to_f64(const S* __restrict__ a, double* __restrict__ b, int64_t n, double f) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
