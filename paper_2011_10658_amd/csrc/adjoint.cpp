@@ -77,10 +77,16 @@ void Heff::build_adjoint() {
         }
     J.grads = Plan();
     J.grads.dtype = dtype;
+    // the three legs' contractions are independent: they share stages, so
+    // each stage is one launch with the tiles of all three
+    bool any = false;
     for (int e = 0; e < 3; ++e)
-        if (!rt[e].empty())
+        if (!rt[e].empty()) {
             append_contract(J.grads, legs, tab, GRef{nullptr, 0, TAG_X, 0}, GRef{nullptr, 0, TAG_Y, 0},
-                            e, rt[e], outs[e], true);
+                            e, rt[e], outs[e], false, 0);
+            any = true;
+        }
+    if (any) split_long_reductions(J.grads, 2);
     J.grads.upload(dev);
     if (dtype != QED_FP64) J.ybc = std::make_shared<DBuf>(dev, tab.size() * es);
     // c_bar_k = <G_k, A_k> on the term's first present factor; a term with

@@ -561,9 +561,10 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
 
 void append_contract(Plan& P, const Leg legs[3], const BlockTable& tab, GRef in_base,
                      GRef partner_base, int which, const std::vector<RTerm>& terms,
-                     const std::vector<ContractOut>& outs, bool split) {
+                     const std::vector<ContractOut>& outs, bool split, int base) {
     Builder B(P);
-    const int s0 = (int)P.jobs.size();   // mode stages s0, s0+1; contraction s0+2
+    // mode stages s0, s0+1; contraction s0+2 (new stages, or shared ones)
+    const int s0 = base >= 0 ? base : (int)P.jobs.size();
     B.stage(s0 + 2);
     const int es = B.esize;
     int f1 = which == 0 ? 1 : 0;

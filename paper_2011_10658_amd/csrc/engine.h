@@ -225,11 +225,13 @@ struct ContractOut {
 // Append out[t.out] += coef * sum over the two legs other than `which` of
 // partner (x) (in x_f1 a x_f2 b), both canonical tensors with the given
 // legs and table (renormalisation when partner = in = a node isometry;
-// operator gradients when partner = ybar and in = x).  Uses three new
-// stages (two mode stages, one contraction stage, optionally split-K).
+// operator gradients when partner = ybar and in = x).  Uses three stages
+// (two mode stages, one contraction stage, optionally split-K): new ones
+// appended to the plan, or, with base >= 0, stages base .. base + 2 shared
+// with other independent contractions.
 void append_contract(Plan& P, const Leg legs[3], const BlockTable& tab, GRef in_base,
                      GRef partner_base, int which, const std::vector<RTerm>& terms,
-                     const std::vector<ContractOut>& outs, bool split);
+                     const std::vector<ContractOut>& outs, bool split, int base = -1);
 
 // out_tensor = op applied on leg e of in_tensor (sector preserving op)
 Plan plan_mode(const TensorD& in, int e, const OpP& op, double* out);
