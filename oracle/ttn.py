@@ -42,6 +42,34 @@ that leg renormalised with the new isometry.
 Environments of a link, from either side, hold block Hamiltonians of the
 terms inside that side (one per class: "phys", "pen") and the open part of
 every term that straddles the link.
+
+Subspace expansion (Methods: single-tensor optimisation with subspace
+expansion, which lets bond dimensions grow and symmetry sectors adapt; the
+paper gives no formulas, the reading is this one).  On the first move after
+a node a is updated, from a to its neighbour b across link e (a's leg w):
+  1. e is extended: every charge Q that a's other legs can carry gets
+     n+(Q) = min(n(Q) + delta, rows_a(Q)) columns (never fewer than n(Q)),
+     the old ones first; a and b are zero-padded to the extended leg.
+  2. Z = sum_k c_k (A_k (x) B_k (x) Omega_k) a+, over the terms k of a's
+     H_eff that reach across e (factors A_k, B_k on a's other legs, None =
+     identity), with Omega_k a random operator on the extended leg carrying
+     the term's charge shift, nonzero only from old columns into padded
+     ones (entries uniform in [-1, 1), counter-based generator, stream
+     65536 * (expansion count) + term index, in the canonical operator
+     layout).  Z lives in the padded columns only.
+  3. M = a+ + alpha (|a+| / |Z|) Z; the state is unchanged because b+ has
+     zero rows there.
+  4. Per sector of the extended leg, M matricised against w is M = U S V^T.
+     The largest singular values over all sectors are kept, at most chi_max
+     of them and none below 1e-12 of the largest; the leg becomes the kept
+     counts (empty sectors dropped), a := U_keep, b := (U_keep^T M) b+
+     (= S_keep V_keep^T b+).
+  5. The environment of e from a's side is rebuilt; the one from b's side
+     is rebuilt when the centre next crosses e back.
+With expansion on, every other move of the centre is the same SVD move
+without steps 1-3: it drops zero singular values (and truncates to
+chi_max), so a leg never keeps more columns than the rows behind it, which
+the QR move would require.
 """
 
 import math
@@ -53,6 +81,28 @@ from .heff import mode_l, mode_p, mode_r
 from .lanczos import lowest
 
 SAT = 1 << 62
+M64 = (1 << 64) - 1
+
+
+def _splitmix(z):
+    """SplitMix64 finaliser (Steele, Lea and Flood, 2014)."""
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & M64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def splitmix_sym_uniform(seed, stream, n):
+    """n uniforms in [-1, 1) of the counter-based SplitMix64 stream
+    (seed, stream): key = mix(seed ^ mix(stream + 0x632BE59BD9B4E019)),
+    word_i = mix(key + (i + 1) * 0x9E3779B97F4A7C15), u = (word >> 11) 2^-53."""
+    key = _splitmix((seed ^ _splitmix((stream + 0x632BE59BD9B4E019) & M64)) & M64)
+    out = np.empty(n)
+    for i in range(n):
+        w = _splitmix((key + (i + 1) * 0x9E3779B97F4A7C15) & M64)
+        out[i] = 2.0 * ((w >> 11) * 2.0 ** -53) - 1.0
+    return out
 
 
 # ----------------------------------------------------------------------
@@ -317,6 +367,9 @@ class TTN:
         self.centre = None
         self.energy = None
         self.nu = 0.0
+        self.expand = None          # dict(alpha, delta, chi_max, seed) or None
+        self.n_expand = 0
+        self.last_updated = None
 
     # -- helpers -------------------------------------------------------
     def legs_of(self, n):
@@ -438,7 +491,185 @@ class TTN:
     def move_to(self, target):
         path = self.tree.path(self.centre, target)
         for a, b in zip(path[:-1], path[1:]):
-            self._move(a, b)
+            if self.expand is not None:
+                self._move_expand(a, b, grow=a == self.last_updated)
+            else:
+                self._move(a, b)
+            self.last_updated = None
+
+    # -- subspace expansion (reading in the module docstring) ----------
+    def set_expansion(self, alpha, delta, chi_max, seed):
+        self.expand = dict(alpha=float(alpha), delta=int(delta), chi_max=int(chi_max),
+                           seed=int(seed))
+
+    def _site_shift(self, s, M):
+        q = self.ham.site_charges(s)
+        x, y = np.nonzero(M)
+        return int(q[x[0]] - q[y[0]])
+
+    def _leg_shift(self, n, which, ops):
+        """Charge shift of a term's factor on leg `which` of node n: the
+        shifts of its site operators inside the leg's subtree (for p: inside
+        n's subtree)."""
+        Sl, Sr, _ = self._sides(n)
+        S = {"l": Sl, "r": Sr, "p": Sl | Sr}[which]
+        return sum(self._site_shift(s, M) for s, M in ops.items() if s in S)
+
+    def _rows(self, n, which):
+        """Row count per charge of node n matricised against leg `which`,
+        over all sector pairs of its other two legs."""
+        legs = dict(zip("lrp", (self.legs[e] for e in self.legs_of(n))))
+        o1, o2 = [k for k in "lrp" if k != which]
+        rows = {}
+        for q1, n1 in legs[o1]:
+            for q2, n2 in legs[o2]:
+                if which == "p":
+                    Q = q1 + q2
+                elif which == "l":
+                    Q = q2 - q1          # (r, p): q_l = q_p - q_r
+                else:
+                    Q = q2 - q1          # (l, p): q_r = q_p - q_l
+                rows[Q] = rows.get(Q, 0) + n1 * n2
+        return rows
+
+    @staticmethod
+    def _pad(T, ax, old, new):
+        """Zero-pad axis ax from leg `old` to leg `new` (old columns first
+        in every sector)."""
+        from .blocks import leg_offsets
+        oo, no = leg_offsets(old), leg_offsets(new)
+        shape = list(T.shape)
+        shape[ax] = leg_dim(new)
+        out = np.zeros(shape)
+        for q, n in old:
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            src[ax] = slice(oo[q], oo[q] + n)
+            dst[ax] = slice(no[q], no[q] + n)
+            out[tuple(dst)] = T[tuple(src)]
+        return out
+
+    def _omega(self, leg, old, delta, stream):
+        """Random operator on `leg` with charge shift `delta`, nonzero only
+        from old columns into padded ones."""
+        from .blocks import leg_offsets
+        off = leg_offsets(leg)
+        size = dict(leg)
+        total, lay = 0, []
+        for q, n in leg:                       # canonical layout: input sectors ascending
+            if q + delta in size:
+                lay.append((q, total))
+                total += size[q + delta] * n
+        vals = splitmix_sym_uniform(self.expand["seed"], stream, total)
+        oldn = dict(old)
+        D = np.zeros((leg_dim(leg), leg_dim(leg)))
+        for q, o in lay:
+            qo = q + delta
+            ni, no_ = size[q], size[qo]
+            blk = vals[o:o + no_ * ni].reshape(no_, ni).copy()
+            blk[:oldn.get(qo, 0), :] = 0.0      # existing output columns
+            blk[:, oldn.get(q, 0):] = 0.0       # padded input columns
+            D[off[qo]:off[qo] + no_, off[q]:off[q] + ni] = blk
+        return D
+
+    def _move_expand(self, a, b, grow=True):
+        cfg = self.expand
+        ta, tb = self.tree.nodes[a], self.tree.nodes[b]
+        if tb["l"] == ta["p"] or tb["r"] == ta["p"]:
+            w, wb, link = "p", ("l" if tb["l"] == ta["p"] else "r"), ta["p"]
+        else:
+            w = "l" if ta["l"] == tb["p"] else "r"
+            wb, link = "p", ta[w]
+        ax, axb = "lrp".index(w), "lrp".index(wb)
+        old = list(self.legs[link])
+        ra = self._rows(a, w)
+        oldn = dict(old)
+        sizes = dict(oldn)
+        if grow:
+            for Q in sorted(ra):
+                n = max(oldn.get(Q, 0), min(oldn.get(Q, 0) + cfg["delta"], ra[Q]))
+                if n > 0:
+                    sizes[Q] = n
+        plus = sorted(sizes.items())
+        aP = self._pad(self.nodes[a], ax, old, plus)
+        bP = self._pad(self.nodes[b], axb, old, plus)
+        self.legs[link] = plus
+        self.qv[link] = leg_charges(plus)
+        # Z over the terms of a's H_eff that reach across the link
+        El, Er, Ep = (self._env_for(a, k) for k in "lrp")
+        env = {"l": El, "r": Er, "p": Ep}
+        sides = dict(zip("lrp", self._sides(a)))
+        Z = np.zeros_like(aP)
+        for i, (c, cls, ops) in enumerate(self.terms if grow else []):
+            st = set(ops)
+            touched = {k: bool(st & sides[k]) for k in "lrp"}
+            if not touched[w] or sum(touched.values()) < 2:
+                continue
+            coef = c * (self.nu if cls == "pen" else 1.0)
+            Om = self._omega(plus, old, self._leg_shift(a, w, ops), 65536 * self.n_expand + i)
+            fac = {k: (env[k].open[i] if touched[k] else None) for k in "lrp" if k != w}
+            fac[w] = Om
+            Z += coef * self._apply3(aP, fac["l"], fac["r"], fac["p"])
+        nz = np.linalg.norm(Z)
+        M = aP + (cfg["alpha"] * np.linalg.norm(aP) / nz) * Z if nz > 0 else aP
+        # per-sector SVD of M matricised against w: M = U S V^T
+        qv = {k: self.qv[e] for k, e in zip("lrp", self.legs_of(a))}
+        mask = (qv["l"][:, None, None] + qv["r"][None, :, None] - qv["p"][None, None, :]) == 0
+        moved = np.moveaxis(M, ax, -1)
+        mmask = np.moveaxis(mask, ax, -1)
+        qcol = self.qv[link]
+        parts = []
+        for q in np.unique(qcol):
+            cols = np.nonzero(qcol == q)[0]
+            rows = mmask[..., cols[0]]
+            Mq = moved[rows][:, cols]
+            U, S, _ = np.linalg.svd(Mq, full_matrices=False)
+            parts.append((int(q), cols, rows, Mq, U, S))
+        smax = max((p[5].max() for p in parts if p[5].size), default=0.0)
+        cand = sorted(((S[j], q, j) for q, _, _, _, _, S in parts for j in range(len(S))
+                       if S[j] > 1e-12 * smax), key=lambda t: -t[0])[:cfg["chi_max"]]
+        keep = {}
+        for _, q, j in cand:
+            keep.setdefault(q, []).append(j)
+        new = [(q, len(keep[q])) for q in sorted(keep)]
+        from .blocks import leg_offsets
+        noff = leg_offsets(new)
+        dplus, dnew = leg_dim(plus), leg_dim(new)
+        anew = np.zeros(moved.shape[:-1] + (dnew,))
+        W = np.zeros((dnew, dplus))
+        for q, cols, rows, Mq, U, S in parts:
+            if q not in keep:
+                continue
+            js = sorted(keep[q], key=lambda j: -S[j])
+            Uq = U[:, js]
+            nc = noff[q] + np.arange(len(js))
+            sub = anew[rows]
+            sub[:, nc] = Uq
+            anew[rows] = sub
+            W[np.ix_(nc, cols)] = Uq.T @ Mq
+        self.nodes[a] = np.moveaxis(anew, -1, ax)
+        self.nodes[b] = np.moveaxis(np.tensordot(W, np.moveaxis(bP, axb, 0), axes=(1, 0)), 0, axb)
+        self.legs[link] = new
+        self.qv[link] = leg_charges(new)
+        if w == "p":
+            self.env_up[link] = self._build_env(a, "p")
+            self.env_dn.pop(link, None)
+        else:
+            self.env_dn[link] = self._build_env(a, w)
+            self.env_up.pop(link, None)
+        if grow:
+            self.n_expand += 1
+        self.centre = b
+
+    @staticmethod
+    def _apply3(t, A, B, C):
+        if A is not None:
+            t = mode_l(A, t)
+        if B is not None:
+            t = mode_r(B, t)
+        if C is not None:
+            t = mode_p(C, t)
+        return t
 
     # -- set-up --------------------------------------------------------
     def prepare(self):
@@ -501,6 +732,7 @@ class TTN:
         xd[mask] = u
         self.nodes[n] = xd
         self.energy = theta + self.offset(nu)
+        self.last_updated = n
         return self.energy
 
     def sweep(self, nu, m=30, cycles=1, tol=0.0):

@@ -416,3 +416,72 @@ def test_ttn_periodic_exact_bond_dim_equals_ed(L):
         E = T.sweep(20.0, m=40, cycles=3, tol=1e-13)
     assert abs(E - e0) < 1e-10 * abs(e0)
     assert T.observables()["deltaL"] < 1e-9
+
+
+# -- subspace expansion ------------------------------------------------------
+def _expansion_ttn(L, chi, bc="zero_flux", Q=0, cpl=CPL):
+    lat = Lattice(*L, boundary=bc)
+    return lat, _make(lat, cpl, Q, chi)
+
+
+def test_expansion_move_keeps_state_and_isometry():
+    """An expansion move enlarges the link with directions that b does not
+    see yet: the contracted state is unchanged, a is an isometry toward the
+    link, and the link has grown."""
+    lat, T = _expansion_ttn((2, 2, 1), 2)
+    T.sweep(20.0, m=30, cycles=2, tol=1e-12)
+    T.move_to(0)
+    T.set_expansion(0.1, 4, 1000, 5)
+    T.last_updated = 0                   # as right after an update of node 0
+    link = T.tree.nodes[0]["p"]
+    before = _full_state(T)
+    dim0 = sum(n for _, n in T.legs[link])
+    T.move_to(T.tree.root)
+    after = _full_state(T)
+    assert np.abs(after - before).max() < 1e-12 * np.abs(before).max()
+    assert sum(n for _, n in T.legs[link]) > dim0
+    # node 0 is an isometry toward its parent leg
+    x = T.nodes[0]
+    G = np.tensordot(x, x, axes=([0, 1], [0, 1]))
+    assert np.abs(G - np.eye(G.shape[0])).max() < 1e-12
+
+
+@pytest.mark.parametrize("L,pins", [((2, 2, 1), None), ((4, 1, 1), None),
+                                    ((8, 1, 1), {2: 1, 5: -1})])
+def test_expansion_reaches_ed_from_small_bond_dimension(L, pins):
+    """Bond dimension 2 from the allocation rule cannot hold the ground
+    state; with expansion the sweeps grow the links (and their sectors) to
+    the ED energy, and the links end at the rank of the state."""
+    cpl = CPL
+    if pins:
+        from oracle.observables import pinning_potentials
+        mu = tuple(pinning_potentials(L, pins, 20.0))
+        cpl = Couplings(t=0.5, m=1.0, g2e=1.0, g2m=0.0, mu=mu)
+    lat = Lattice(*L)
+    e0 = OriginalED(lat, cpl).spectrum()[0]
+    plain = _make(lat, cpl, 0, 2)
+    grown = _make(lat, cpl, 0, 2)
+    start = {e: {q for q, _ in leg} for e, leg in grown.legs.items()}
+    grown.set_expansion(1e-2, 8, 64, 99)
+    for _ in range(8):
+        ep = plain.sweep(20.0, m=40, cycles=3, tol=1e-12)
+        eg = grown.sweep(20.0, m=40, cycles=3, tol=1e-12)
+    assert ep > e0 + 1e-3
+    assert abs(eg - e0) < 1e-9 * abs(e0)
+    assert grown.observables()["deltaL"] < 1e-9
+    if pins:
+        # the symmetry sectors adapted: some link carries a charge that the
+        # initial allocation did not give it
+        assert any({q for q, _ in grown.legs[e]} - start[e] for e in start)
+
+
+def test_expansion_respects_chi_max_and_bound():
+    lat, T = _expansion_ttn((2, 2, 1), 2)
+    T.set_expansion(1e-2, 8, 3, 99)
+    e0 = OriginalED(lat, CPL).spectrum()[0]
+    for _ in range(4):
+        E = T.sweep(20.0, m=40, cycles=3, tol=1e-12)
+        for e, leg in T.legs.items():
+            if e >= lat.nsites:
+                assert sum(n for _, n in leg) <= 3
+    assert E >= e0 - 1e-10
