@@ -160,6 +160,24 @@ int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol);
  * tol0 = 0 (the default) switches the schedule off; 0 < factor < 1. */
 int qed_set_lanczos_schedule(qed_ctx* ctx, double tol0, double factor);
 
+/* Subspace expansion (Methods: single-tensor optimisation with subspace
+ * expansion, which lets bond dimensions grow and symmetry sectors adapt).
+ * With on != 0, every move of the isometry centre from node a to b across
+ * link e is an SVD move: per charge sector, a matricised against e is
+ * factored U S V^T, the largest singular values over all sectors are kept
+ * (at most chi_max, 0 = the bond dimension of qed_set_bond_dim; none below
+ * 1e-12 of the largest), a := U_keep and b absorbs S V^T, so the link takes
+ * the kept sector sizes.  On the first move after a was updated, e is
+ * first extended by up to `delta` columns per charge sector a's other legs
+ * can carry (new charges included), filled with alpha |a| / |Z| Z, where
+ * Z = sum_k c_k (A_k (x) B_k (x) Omega_k) a over the H_eff terms of a that
+ * reach across e and Omega_k are random maps into the new columns
+ * (SplitMix64 uniforms in [-1, 1) from `seed`): b does not see the new
+ * columns, so the state is unchanged, and they enter the basis through
+ * the truncation.  Off by default; takes effect at the next move.
+ * QED_ERR_INVALID_ARG for alpha < 0 or not finite, delta < 0, chi_max < 0. */
+int qed_set_expansion(qed_ctx* ctx, int on, double alpha, int delta, int chi_max, uint64_t seed);
+
 /* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16).  refine != 0 adds one
  * FP64 Rayleigh quotient per node update on the reduced-precision paths
  * (the node energy then carries an error second order in the eigenvector

@@ -596,8 +596,7 @@ class TTN:
         self.legs[link] = plus
         self.qv[link] = leg_charges(plus)
         # Z over the terms of a's H_eff that reach across the link
-        El, Er, Ep = (self._env_for(a, k) for k in "lrp")
-        env = {"l": El, "r": Er, "p": Ep}
+        env = {k: self._env_for(a, k) for k in "lrp"} if grow else {}
         sides = dict(zip("lrp", self._sides(a)))
         Z = np.zeros_like(aP)
         for i, (c, cls, ops) in enumerate(self.terms if grow else []):
@@ -678,6 +677,10 @@ class TTN:
         for s in range(self.tree.N):
             self.env_up[s] = self._site_env(s)
         for n in range(len(self.tree.nodes)):
+            if n != self.tree.root and self.expand is not None:
+                # expansion mode: SVD moves throughout (they build the environment)
+                self._move_expand(n, self.tree.up[self.tree.nodes[n]["p"]][0], grow=False)
+                continue
             if n != self.tree.root:
                 nd = self.tree.nodes[n]
                 R = self._qr_toward(n, "p")

@@ -290,6 +290,20 @@ int qed_set_lanczos(qed_ctx* ctx, int steps, int max_cycles, double tol) {
     });
 }
 
+int qed_set_expansion(qed_ctx* ctx, int on, double alpha, int delta, int chi_max, uint64_t seed) {
+    return guard(ctx, [&] {
+        if (!std::isfinite(alpha) || alpha < 0.0 || delta < 0 || chi_max < 0)
+            fail(QED_ERR_INVALID_ARG, "expansion: alpha >= 0, delta >= 0, chi_max >= 0");
+        Params& P = C(ctx).prm;
+        P.exp_on = on != 0;
+        P.exp_alpha = alpha;
+        P.exp_delta = delta;
+        P.exp_chimax = chi_max;
+        P.exp_seed = seed;
+        return QED_OK;
+    });
+}
+
 int qed_set_lanczos_schedule(qed_ctx* ctx, double tol0, double factor) {
     return guard(ctx, [&] {
         if (!(tol0 >= 0.0) || !(factor > 0.0 && factor < 1.0))
@@ -523,10 +537,21 @@ int qed_load_state(qed_ctx* ctx, const char* path) {
                 fail(QED_ERR_INVALID_ARG, "checkpoint is for another lattice, boundary, charge or bond dimension");
         if (nlegs != (int)e.legs.size() || nn != (int)e.tree.nodes.size())
             fail(QED_ERR_INVALID_ARG, "checkpoint tree does not match");
-        for (int i = 0; i < nlegs; ++i)
-            if (legs[i].q != e.legs[i].q || legs[i].n != e.legs[i].n)
-                fail(QED_ERR_INVALID_ARG, "checkpoint leg sectors do not match");
+        // site legs and the root's charge leg are fixed by the model; the
+        // internal legs may differ from the allocation rule (subspace
+        // expansion changes them), but every sector must fit its rows
+        bool same = true;
+        for (int i = 0; i < nlegs; ++i) {
+            const bool fixed = i < e.tree.N || i == e.tree.top;
+            const bool eq = legs[i].q == e.alloc_legs[i].q && legs[i].n == e.alloc_legs[i].n;
+            if (fixed && !eq) fail(QED_ERR_INVALID_ARG, "checkpoint leg sectors do not match");
+            for (int s = 0; s < legs[i].nsec(); ++s)
+                if (legs[i].n[s] < 1 || (s && legs[i].q[s] <= legs[i].q[s - 1]))
+                    fail(QED_ERR_IO, "corrupt checkpoint (leg sectors)");
+            if (!(legs[i].q == e.legs[i].q && legs[i].n == e.legs[i].n)) same = false;
+        }
         if (e.nodes.empty()) e.init_nodes(0);
+        if (!same) e.adopt_legs(legs);
         for (int i = 0; i < nn; ++i) {
             if ((int64_t)data[i].size() != e.nodes[i].tab.size())
                 fail(QED_ERR_INVALID_ARG, "checkpoint node size does not match");

@@ -664,7 +664,9 @@ Plan plan_renorm(const TensorD& n, int which, const std::vector<RTerm>& terms,
     Plan P;
     P.dtype = QED_FP64;
     std::vector<ContractOut> co;
-    for (const OpP& o : outs) co.push_back(ContractOut{o->leg, o->lay, gabs(o->d64->p)});
+    // an output with no block (its charge shift maps no sector of the leg
+    // onto another) has no storage and receives no job
+    for (const OpP& o : outs) co.push_back(ContractOut{o->leg, o->lay, gabs(o->d64 ? o->d64->p : nullptr)});
     append_contract(P, n.legs, n.tab, gabs(n.ptr()), gabs(n.ptr()), which, terms, co, true);
     return P;
 }

@@ -56,6 +56,8 @@ void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_
 void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
+void launch_jacobi_svd(const SvdMat*, int nmats, hipStream_t);
+void launch_axpy(double* y, const double* x, double f, int64_t n, hipStream_t);
 
 void seg_dots(const double*, int64_t, int, const double*, const SegChunk*, int, const int*, int,
               double*, double*, int, int, const LState*, int, hipStream_t);
@@ -339,6 +341,12 @@ struct Params {
     double lz_tol = 0.0;
     double lz_tol0 = 0.0, lz_factor = 0.1;   // per-sweep tolerance schedule (off: tol0 = 0)
     int dtype = QED_FP64, refine = 1;
+    // subspace expansion (off unless set): mixing alpha, columns added per
+    // sector delta, bond-dimension cap chi_max, seed of the random maps
+    bool exp_on = false;
+    double exp_alpha = 0.0;
+    int exp_delta = 0, exp_chimax = 0;
+    uint64_t exp_seed = 0;
     bool have_lattice = false, have_couplings = false;
 };
 
@@ -347,6 +355,7 @@ struct Engine {
     Model model;
     Tree tree;
     std::vector<Leg> legs;
+    std::vector<Leg> alloc_legs;   // legs of the allocation rule (restored by init)
     std::vector<TensorD> nodes;
     std::vector<EnvD> up, dn;
     std::vector<std::vector<OpP>> siteops;   // per site, per op id
@@ -361,6 +370,9 @@ struct Engine {
     LanczosWS lws;
     long long matvecs = 0;
     double flops = 0.0;
+    int last_updated = -1;     // node updated since the centre last moved, or -1
+    long long n_expand = 0;    // expansion moves so far (stream of the random maps)
+    double cur_nu = 0.0;       // penalty of the current sweep
 
     void build(Ctx* c);
     void init_nodes(uint64_t seed);
@@ -377,6 +389,9 @@ struct Engine {
     OpP qr_toward(int n, int which);
     void absorb(int n, int e, const OpP& R);
     void move(int a, int b);
+    // SVD move with optional subspace expansion (expansion mode)
+    void move_svd(int a, int b, bool grow);
+    void adopt_legs(const std::vector<Leg>& nl);
     void move_to(int target);
     void build_env(int n, int which, EnvD& out);
     EnvD& env_for(int n, int which);

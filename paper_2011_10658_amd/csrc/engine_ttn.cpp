@@ -65,6 +65,7 @@ void Engine::build(Ctx* c) {
     std::vector<Leg> sl;
     for (auto& s : model.sites) sl.push_back(s.leg);
     legs = allocate_sectors(tree, sl, P.Q, P.chi);
+    alloc_legs = legs;
     // the charge sector must be reachable: every leg non-empty
     for (int e = 0; e < tree.nlinks(); ++e)
         if (legs[e].nsec() == 0)
@@ -94,6 +95,9 @@ void Engine::build(Ctx* c) {
 
 void Engine::init_nodes(uint64_t seed) {
     Dev* dev = &ctx->dev;
+    legs = alloc_legs;
+    n_expand = 0;
+    last_updated = -1;
     nodes.assign(tree.nodes.size(), TensorD());
     for (int n = 0; n < (int)tree.nodes.size(); ++n) {
         const auto& nd = tree.nodes[n];
@@ -192,9 +196,9 @@ void Engine::absorb(int m, int e, const OpP& R) {
 
 EnvD& Engine::env_for(int n, int which) {
     const auto& nd = tree.nodes[n];
-    if (which == 0) return up[nd.l];
-    if (which == 1) return up[nd.r];
-    return dn[nd.p];
+    EnvD& e = which == 0 ? up[nd.l] : which == 1 ? up[nd.r] : dn[nd.p];
+    if (!e.valid) fail(QED_ERR_BAD_STATE, "environment used before it was rebuilt");
+    return e;
 }
 
 // side membership: 0 = subtree of l, 1 = subtree of r, 2 = outside node n
@@ -279,7 +283,449 @@ void Engine::move(int a, int b) {
 
 void Engine::move_to(int target) {
     std::vector<int> p = tree.path(centre, target);
-    for (size_t i = 0; i + 1 < p.size(); ++i) move(p[i], p[i + 1]);
+    for (size_t i = 0; i + 1 < p.size(); ++i) {
+        if (ctx->prm.exp_on) move_svd(p[i], p[i + 1], p[i] == last_updated);
+        else move(p[i], p[i + 1]);
+        last_updated = -1;
+    }
+}
+
+// ---------------------------------------------------------------------
+// Subspace expansion (Methods: single-tensor optimisation with subspace
+// expansion, bond dimensions growing and sectors adapting).  On the first
+// move after node a was updated, from a to its neighbour b across link e
+// (a's leg w):
+//   1. e is extended: every charge Q that a's other legs can carry gets
+//      min(n(Q) + delta, rows_a(Q)) columns (never fewer than n(Q)), the
+//      old ones first; a is zero-padded to the extended leg;
+//   2. Z = sum_k c_k (A_k (x) B_k (x) Omega_k) a+ over the terms of a's
+//      H_eff that reach across e, Omega_k a random map on the extended leg
+//      with the term's charge shift, nonzero from old into padded columns
+//      only (counter-based SplitMix64 uniforms in [-1, 1), stream
+//      65536 * (expansion count) + term index, canonical operator layout);
+//   3. M = a+ + alpha (|a+| / |Z|) Z: b does not see the padded columns,
+//      so the state is unchanged;
+//   4. per sector, M matricised against w is factored M = U S V^T (QR, then
+//      one-sided Jacobi on R^T; Jacobi on M^T directly for sectors with
+//      fewer rows than columns); the largest singular values over all
+//      sectors are kept, at most chi_max and none below 1e-12 of the
+//      largest; a := U_keep, b := (U_keep^T M) b on the kept leg;
+//   5. the environment of e from a's side is rebuilt; the one from b's side
+//      is invalid until the centre crosses e back.
+// Every other move in expansion mode is the same SVD move without 1-3.
+// ---------------------------------------------------------------------
+namespace {
+
+// rows per charge of a node matricised against leg `which`, over all
+// sector pairs of its other two legs
+std::map<int, int64_t> rows_by_charge(const Leg L[3], int which) {
+    std::map<int, int64_t> r;
+    const int o1 = which == 0 ? 1 : 0, o2 = which == 2 ? 1 : 2;
+    for (int a = 0; a < L[o1].nsec(); ++a)
+        for (int b = 0; b < L[o2].nsec(); ++b) {
+            const int Q = which == 2 ? L[0].q[a] + L[1].q[b] : L[2].q[b] - L[o1].q[a];
+            r[Q] += (int64_t)L[o1].n[a] * L[o2].n[b];
+        }
+    return r;
+}
+
+int64_t get0(const std::map<int, int64_t>& m, int q) {
+    auto it = m.find(q);
+    return it == m.end() ? 0 : it->second;
+}
+
+// node with leg `which` replaced (table rebuilt, data uninitialised)
+TensorD with_leg(Dev* dev, const TensorD& T, int which, const Leg& L) {
+    TensorD R;
+    for (int e = 0; e < 3; ++e) R.legs[e] = T.legs[e];
+    R.legs[which] = L;
+    R.tab = make_table(R.legs[0], R.legs[1], R.legs[2], 0);
+    R.d = std::make_shared<DBuf>(dev, std::max<int64_t>(1, R.tab.size()) * sizeof(double));
+    return R;
+}
+
+// pack descriptors of T matricised against `which`: the sector of charge q
+// is a rows(q) x n(q) column-major matrix at mat(q)
+struct PackList {
+    std::vector<PackBlk> blks;
+    int64_t maxsize = 0;
+};
+
+PackList pack_list(const TensorD& T, int which, const std::map<int, int64_t>& mat,
+                   const std::map<int, int64_t>& rows) {
+    PackList pl;
+    std::map<int, int64_t> row0;
+    const Leg& L = T.legs[which];
+    for (int b = 0; b < T.tab.nblk(); ++b) {
+        PackBlk B{};
+        B.off = T.tab.off[b];
+        for (int e = 0; e < 3; ++e) B.n[e] = T.legs[e].n[T.tab.s[e][b]];
+        const int q = L.q[T.tab.s[which][b]];
+        B.leg = which;
+        B.mat = mat.at(q);
+        B.rows = (int)rows.at(q);
+        B.row0 = (int)row0[q];
+        const int64_t sz = (int64_t)B.n[0] * B.n[1] * B.n[2];
+        row0[q] += sz / B.n[which];
+        pl.maxsize = std::max(pl.maxsize, sz);
+        pl.blks.push_back(B);
+    }
+    return pl;
+}
+
+// host-side bounds check of a pack list against its buffers (element counts)
+void check_pack(const PackList& pl, int64_t tensor_elems, int64_t packed_elems) {
+    for (const PackBlk& B : pl.blks) {
+        const int64_t sz = (int64_t)B.n[0] * B.n[1] * B.n[2];
+        const int64_t brows = sz / B.n[B.leg];
+        if (B.off < 0 || B.off + sz > tensor_elems || B.row0 < 0 || B.row0 + brows > B.rows ||
+            B.mat < 0 || B.mat + (int64_t)(B.n[B.leg] - 1) * B.rows + B.rows > packed_elems)
+            fail(QED_ERR_BAD_STATE, "internal: sector packing out of bounds");
+    }
+}
+
+void run_pack(Dev* dev, const PackList& pl, double* tensor, double* packed, int dir) {
+    if (pl.blks.empty()) return;
+    DBuf d(dev, pl.blks.size() * sizeof(PackBlk));
+    dev->upload(d.p, pl.blks.data(), pl.blks.size() * sizeof(PackBlk));
+    launch_pack(d.as<PackBlk>(), (int)pl.blks.size(), pl.maxsize, tensor, packed, dir, dev->stream);
+    dev->check(hipGetLastError(), "pack");
+}
+
+// sector-matrix offsets of a leg with the given rows per charge
+std::map<int, int64_t> sector_offsets(const Leg& L, const std::map<int, int64_t>& rows, int64_t& tot) {
+    std::map<int, int64_t> mat;
+    tot = 0;
+    for (int s = 0; s < L.nsec(); ++s) {
+        mat[L.q[s]] = tot;
+        tot += get0(rows, L.q[s]) * L.n[s];
+    }
+    return mat;
+}
+
+// C (col-major rows x k, ld rows) = A (col-major rows x kin, ld rows) *
+// Bm (col-major kin x k, ld kin), as the row-major product C^T = Bm^T A^T
+void push_colmajor_gemm(Plan& pl, double* C, const double* A, const double* Bm, int64_t rows, int kin,
+                        int k) {
+    if (rows <= 0 || kin <= 0 || k <= 0 || rows > INT32_MAX)
+        fail(QED_ERR_BAD_STATE, "internal: empty or oversized sector product");
+    GProd pr{};
+    pr.A = GRef{Bm, 0, TAG_ABS, 0};
+    pr.lda = kin;
+    pr.B = GRef{A, 0, TAG_ABS, 0};
+    pr.ldb = (int)rows;
+    pr.K = kin;
+    pr.alpha = 1.0;
+    pr.nred = 1;
+    GJob j{};
+    j.C = GRef{C, 0, TAG_ABS, 0};
+    j.M = k;
+    j.N = (int)rows;
+    j.ldc = (int)rows;
+    j.batch = 1;
+    j.p0 = (int)pl.prods[0].size();
+    pl.prods[0].push_back(pr);
+    j.p1 = j.p0 + 1;
+    pl.jobs[0].push_back(j);
+    pl.stage_flops[0] += 2.0 * rows * kin * k;
+    pl.flops += 2.0 * rows * kin * k;
+}
+
+}  // namespace
+
+void Engine::move_svd(int a, int b, bool grow) {
+    Dev* dev = &ctx->dev;
+    const Params& P = ctx->prm;
+    hipStream_t st = dev->stream;
+    const auto& ta = tree.nodes[a];
+    const auto& tb = tree.nodes[b];
+    int w, wb, link;
+    if (tb.l == ta.p || tb.r == ta.p) {
+        w = 2;
+        wb = tb.l == ta.p ? 0 : 1;
+        link = ta.p;
+    } else {
+        w = ta.l == tb.p ? 0 : 1;
+        wb = 2;
+        link = w == 0 ? ta.l : ta.r;
+    }
+    const Leg old = legs[link];
+    std::map<int, int> oldn;
+    for (int s = 0; s < old.nsec(); ++s) oldn[old.q[s]] = old.n[s];
+    auto nold = [&](int q) { auto it = oldn.find(q); return it == oldn.end() ? 0 : it->second; };
+    // 1. extended leg and the padded node
+    const std::map<int, int64_t> rows = rows_by_charge(nodes[a].legs, w);
+    std::map<int, int> sz = oldn;
+    if (grow)
+        for (const auto& kv : rows) {
+            const int n0 = nold(kv.first);
+            const int64_t n = std::max<int64_t>(n0, std::min<int64_t>((int64_t)n0 + P.exp_delta, kv.second));
+            if (n > 0) sz[kv.first] = (int)n;
+        }
+    Leg plus;
+    for (const auto& kv : sz) {
+        plus.q.push_back(kv.first);
+        plus.n.push_back(kv.second);
+    }
+    TensorD M = with_leg(dev, nodes[a], w, plus);
+    int64_t tot = 0;
+    const std::map<int, int64_t> mat = sector_offsets(plus, rows, tot);
+    DBuf packed(dev, std::max<int64_t>(1, tot) * sizeof(double));
+    launch_fill(packed.as<double>(), tot, 0.0, st);
+    const PackList pl_old = pack_list(nodes[a], w, mat, rows);
+    const PackList pl_m = pack_list(M, w, mat, rows);
+    check_pack(pl_old, nodes[a].tab.size(), tot);
+    check_pack(pl_m, M.tab.size(), tot);
+    run_pack(dev, pl_old, nodes[a].ptr(), packed.as<double>(), 0);
+    run_pack(dev, pl_m, M.ptr(), packed.as<double>(), 1);
+    const int64_t nm = M.tab.size();
+    // 2-3. expansion term
+    if (grow && P.exp_alpha > 0.0 && nm > 0) {
+        std::vector<HTerm> zt;
+        EnvD* E[3] = {&env_for(a, 0), &env_for(a, 1), &env_for(a, 2)};
+        for (int i = 0; i < (int)model.terms.size(); ++i) {
+            const Term& t = model.terms[i];
+            if (t.coef == 0.0) continue;
+            bool touch[3] = {false, false, false};
+            for (int s : tsites[i])
+                for (int side = 0; side < 3; ++side)
+                    if (in_side(*this, a, side, s)) touch[side] = true;
+            if (!touch[w] || touch[0] + touch[1] + touch[2] < 2) continue;
+            OpP om = make_op(dev, plus, E[w]->open.at(i)->lay.delta, false);
+            if (!om->lay.size) continue;
+            std::vector<double> h(om->lay.size, 0.0);
+            const uint64_t stream = (uint64_t)n_expand * 65536ULL + (uint64_t)i;
+            const uint64_t key = mix64(P.exp_seed ^ mix64(stream + 0x632BE59BD9B4E019ULL));
+            bool any = false;
+            for (int s = 0; s < plus.nsec(); ++s) {
+                const int o = om->lay.out_of_in[s];
+                if (o < 0) continue;
+                const int ni = plus.n[s], no = plus.n[o];
+                for (int r = nold(plus.q[o]); r < no; ++r)
+                    for (int c = 0; c < nold(plus.q[s]); ++c) {
+                        const int64_t idx = om->lay.off[s] + (int64_t)r * ni + c;
+                        h[idx] = sym_uniform(key, (uint64_t)idx);
+                        any = true;
+                    }
+            }
+            if (!any) continue;
+            dev->upload(om->d64->p, h.data(), h.size() * sizeof(double));
+            HTerm ht{t.coef * (t.cls == CLS_PEN ? cur_nu : 1.0), {nullptr, nullptr, nullptr}};
+            for (int k = 0; k < 3; ++k)
+                if (k != w && touch[k]) ht.op[k] = E[k]->open.at(i);
+            ht.op[w] = om;
+            zt.push_back(ht);
+        }
+        if (!zt.empty()) {
+            Plan pz = plan_matvec(M.legs, M.tab, zt, QED_FP64);
+            pz.upload(dev);
+            DBuf z(dev, nm * sizeof(double));
+            void* wsp = ws.get(dev, std::max<int64_t>(1, pz.ws_elems) * sizeof(double));
+            pz.run(dev, wsp, M.ptr(), z.p);
+            DBuf part(dev, 512 * sizeof(double)), nr(dev, 2 * sizeof(double));
+            launch_dots(M.ptr(), nm, 1, M.ptr(), nm, part.as<double>(), nr.as<double>(), 1, nullptr, 0, st);
+            launch_dots(z.as<double>(), nm, 1, z.as<double>(), nm, part.as<double>(), nr.as<double>() + 1, 1,
+                        nullptr, 0, st);
+            double h2[2];
+            dev->download(h2, nr.p, sizeof(h2));
+            if (h2[1] > 0.0 && std::isfinite(h2[1])) {
+                launch_axpy(M.ptr(), z.as<double>(), P.exp_alpha * h2[0] / h2[1], nm, st);
+                // the padded columns now carry the expansion: repack M
+                run_pack(dev, pl_m, M.ptr(), packed.as<double>(), 0);
+            }
+        }
+    }
+    // 4. per-sector SVD
+    struct Sec {
+        int q, r, c, m;        // charge, rows, columns, Jacobi columns
+        bool qr;
+        int64_t x, v, s;       // offsets of X (c x m), V (m x m), sigma (m)
+    };
+    std::vector<Sec> secs;
+    int64_t xs = 0, vs = 0, ss = 0;
+    for (int s = 0; s < plus.nsec(); ++s) {
+        Sec S{};
+        S.q = plus.q[s];
+        S.r = (int)get0(rows, S.q);
+        S.c = plus.n[s];
+        if (S.r == 0) continue;
+        S.qr = S.r >= S.c;
+        S.m = S.qr ? S.c : S.r;
+        S.x = xs;
+        S.v = vs;
+        S.s = ss;
+        xs += (int64_t)S.c * S.m;
+        vs += (int64_t)S.m * S.m;
+        ss += S.m;
+        secs.push_back(S);
+    }
+    DBuf X(dev, std::max<int64_t>(1, xs) * sizeof(double));
+    DBuf V(dev, std::max<int64_t>(1, vs) * sizeof(double));
+    DBuf SG(dev, std::max<int64_t>(1, ss) * sizeof(double));
+    std::vector<QRTask> tasks;
+    std::vector<int64_t> tblk;
+    for (const Sec& S : secs) {
+        if (mat.at(S.q) + (int64_t)S.r * S.c > tot || S.x + (int64_t)S.c * S.m > xs ||
+            S.v + (int64_t)S.m * S.m > vs || S.s + S.m > ss)
+            fail(QED_ERR_BAD_STATE, "internal: sector decomposition out of bounds");
+        double* Mq = packed.as<double>() + mat.at(S.q);
+        if (S.qr) {
+            // R row-major (rrs = c, rcs = 1) is R^T column-major: X directly
+            tasks.push_back(QRTask{Mq, S.r, S.c, X.as<double>() + S.x, S.c, 1});
+        } else {
+            // M_q (column-major r x c) is row-major c x r; its transpose is
+            // X = M_q^T column-major (c x r)
+            tblk.insert(tblk.end(), {mat.at(S.q), S.x, (int64_t)S.c, (int64_t)S.r});
+        }
+    }
+    if (!tasks.empty()) tsqr_multi(dev, tasks);
+    if (!tblk.empty()) {
+        DBuf d(dev, tblk.size() * sizeof(int64_t));
+        dev->upload(d.p, tblk.data(), tblk.size() * sizeof(int64_t));
+        launch_transpose_blocks(packed.as<double>(), X.as<double>(), d.as<int64_t>(), (int)tblk.size() / 4, st);
+    }
+    std::vector<SvdMat> sm;
+    for (const Sec& S : secs)
+        sm.push_back(SvdMat{X.as<double>() + S.x, V.as<double>() + S.v, SG.as<double>() + S.s, S.c, S.m});
+    if (!sm.empty()) {
+        DBuf d(dev, sm.size() * sizeof(SvdMat));
+        dev->upload(d.p, sm.data(), sm.size() * sizeof(SvdMat));
+        launch_jacobi_svd(d.as<SvdMat>(), (int)sm.size(), st);
+        dev->check(hipGetLastError(), "jacobi svd");
+    }
+    std::vector<double> hX(xs), hV(vs), hS(ss);
+    if (xs) dev->download(hX.data(), X.p, xs * sizeof(double));
+    if (vs) dev->download(hV.data(), V.p, vs * sizeof(double));
+    if (ss) dev->download(hS.data(), SG.p, ss * sizeof(double));
+    // kept singular values: the largest over all sectors, at most chi_max,
+    // none below 1e-12 of the largest (ties: charge, then position)
+    struct Cand {
+        double s;
+        int sec, j;
+    };
+    double smax = 0.0;
+    for (double v : hS) smax = std::max(smax, v);
+    std::vector<Cand> cand;
+    for (int k = 0; k < (int)secs.size(); ++k) {
+        std::vector<int> js(secs[k].m);
+        for (int j = 0; j < secs[k].m; ++j) js[j] = j;
+        std::stable_sort(js.begin(), js.end(),
+                         [&](int x, int y) { return hS[secs[k].s + x] > hS[secs[k].s + y]; });
+        for (int j : js)
+            if (hS[secs[k].s + j] > 1e-12 * smax) cand.push_back(Cand{hS[secs[k].s + j], k, j});
+    }
+    std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) { return x.s > y.s; });
+    const int chimax = P.exp_chimax > 0 ? P.exp_chimax : P.chi;
+    if ((int)cand.size() > chimax) cand.resize(chimax);
+    if (cand.empty()) fail(QED_ERR_NONFINITE, "subspace expansion: the node has no nonzero singular value");
+    std::map<int, std::vector<int>> keep;   // per section index: kept Jacobi columns, descending sigma
+    for (const Cand& c : cand) keep[c.sec].push_back(c.j);
+    Leg enew;
+    for (int k = 0; k < (int)secs.size(); ++k)
+        if (keep.count(k)) {
+            enew.q.push_back(secs[k].q);
+            enew.n.push_back((int)keep[k].size());
+        }
+    // a := U_keep; b := (U_keep^T M) b on the kept leg
+    TensorD An = with_leg(dev, nodes[a], w, enew);
+    TensorD Bn = with_leg(dev, nodes[b], wb, enew);
+    int64_t tota = 0, totb_old = 0, totb = 0;
+    const std::map<int, int64_t> mata = sector_offsets(enew, rows, tota);
+    const std::map<int, int64_t> rowsb = rows_by_charge(nodes[b].legs, wb);
+    const std::map<int, int64_t> matb_old = sector_offsets(old, rowsb, totb_old);
+    const std::map<int, int64_t> matb = sector_offsets(enew, rowsb, totb);
+    DBuf pa(dev, std::max<int64_t>(1, tota) * sizeof(double));
+    DBuf pbo(dev, std::max<int64_t>(1, totb_old) * sizeof(double));
+    DBuf pb(dev, std::max<int64_t>(1, totb) * sizeof(double));
+    launch_fill(pb.as<double>(), totb, 0.0, st);
+    const PackList pl_bo = pack_list(nodes[b], wb, matb_old, rowsb);
+    check_pack(pl_bo, nodes[b].tab.size(), totb_old);
+    run_pack(dev, pl_bo, nodes[b].ptr(), pbo.as<double>(), 0);
+    std::vector<double> hU, hT;          // host copies of U_keep / T blocks
+    std::vector<int64_t> uo, to;
+    for (const auto& kv : keep) {
+        const Sec& S = secs[kv.first];
+        const std::vector<int>& js = kv.second;
+        const int k = (int)js.size();
+        uo.push_back((int64_t)hU.size());
+        for (int j : js)
+            for (int i = 0; i < S.m; ++i) hU.push_back(hV[S.v + (int64_t)j * S.m + i]);
+        const int n0 = nold(S.q);
+        to.push_back((int64_t)hT.size());
+        for (int j : js)
+            for (int i = 0; i < n0; ++i) hT.push_back(hX[S.x + (int64_t)j * S.c + i]);
+        (void)k;
+    }
+    DBuf dU(dev, std::max<size_t>(1, hU.size()) * sizeof(double));
+    DBuf dT(dev, std::max<size_t>(1, hT.size()) * sizeof(double));
+    if (!hU.empty()) dev->upload(dU.p, hU.data(), hU.size() * sizeof(double));
+    if (!hT.empty()) dev->upload(dT.p, hT.data(), hT.size() * sizeof(double));
+    Plan pl;
+    pl.dtype = QED_FP64;
+    pl.jobs.emplace_back();
+    pl.prods.emplace_back();
+    pl.stage_flops.push_back(0.0);
+    size_t idx = 0;
+    for (const auto& kv : keep) {
+        const Sec& S = secs[kv.first];
+        const int k = (int)kv.second.size();
+        double* Ca = pa.as<double>() + mata.at(S.q);
+        const double* Uk = dU.as<double>() + uo[idx];
+        if (mata.at(S.q) + (int64_t)S.r * k > tota || uo[idx] + (int64_t)S.m * k > (int64_t)hU.size())
+            fail(QED_ERR_BAD_STATE, "internal: expansion output out of bounds");
+        if (S.qr) {
+            // a block = Q (r x c) U_keep (c x k)
+            push_colmajor_gemm(pl, Ca, packed.as<double>() + mat.at(S.q), Uk, S.r, S.c, k);
+        } else {
+            // Q is the identity: a block = U_keep (r x k)
+            dev->check(hipMemcpyAsync(Ca, Uk, (size_t)S.r * k * sizeof(double), hipMemcpyDeviceToDevice, st),
+                       "expansion copy");
+        }
+        const int n0 = nold(S.q);
+        const int64_t rb = get0(rowsb, S.q);
+        if (n0 > 0 && rb > 0 &&
+            (matb.at(S.q) + rb * k > totb || matb_old.at(S.q) + rb * n0 > totb_old ||
+             to[idx] + (int64_t)n0 * k > (int64_t)hT.size()))
+            fail(QED_ERR_BAD_STATE, "internal: expansion output out of bounds");
+        if (n0 > 0 && rb > 0)
+            push_colmajor_gemm(pl, pb.as<double>() + matb.at(S.q), pbo.as<double>() + matb_old.at(S.q),
+                               dT.as<double>() + to[idx], rb, n0, k);
+        ++idx;
+    }
+    if (!pl.jobs[0].empty()) {
+        pl.upload(dev);
+        pl.run(dev, nullptr, nullptr, nullptr);
+    }
+    const PackList pl_a = pack_list(An, w, mata, rows);
+    const PackList pl_b = pack_list(Bn, wb, matb, rowsb);
+    check_pack(pl_a, An.tab.size(), tota);
+    check_pack(pl_b, Bn.tab.size(), totb);
+    run_pack(dev, pl_a, An.ptr(), pa.as<double>(), 1);
+    run_pack(dev, pl_b, Bn.ptr(), pb.as<double>(), 1);
+    // 5. install, environments
+    legs[link] = enew;
+    nodes[a] = An;
+    nodes[b] = Bn;
+    build_env(a, w, w == 2 ? up[link] : dn[link]);
+    (w == 2 ? dn[link] : up[link]) = EnvD();
+    if (grow) ++n_expand;
+    centre = b;
+}
+
+void Engine::adopt_legs(const std::vector<Leg>& nl) {
+    Dev* dev = &ctx->dev;
+    legs = nl;
+    nodes.assign(tree.nodes.size(), TensorD());
+    for (int n = 0; n < (int)tree.nodes.size(); ++n) {
+        const auto& nd = tree.nodes[n];
+        TensorD& T = nodes[n];
+        T.legs[0] = legs[nd.l];
+        T.legs[1] = legs[nd.r];
+        T.legs[2] = legs[nd.p];
+        T.tab = make_table(T.legs[0], T.legs[1], T.legs[2], 0);
+        T.d = std::make_shared<DBuf>(dev, std::max<int64_t>(1, T.tab.size()) * sizeof(double));
+    }
+    invalidate();
 }
 
 void Engine::prepare() {
@@ -357,6 +803,11 @@ void Engine::prepare() {
         if (n == tree.root) continue;
         const auto& nd = tree.nodes[n];
         if (!isometric) {
+            if (ctx->prm.exp_on) {
+                // expansion mode: SVD moves throughout (they build the environment)
+                move_svd(n, tree.parent_node[nd.p], false);
+                continue;
+            }
             OpP R = qr_toward(n, 2);
             absorb(tree.parent_node[nd.p], tree.parent_side[nd.p], R);
         }
@@ -373,6 +824,7 @@ void Engine::prepare() {
 double Engine::update(int n, double nu) {
     Dev* dev = &ctx->dev;
     const Params& P = ctx->prm;
+    cur_nu = nu;
     TensorD& T = nodes[n];
     std::vector<HTerm> ht;
     EnvD* E[3] = {&env_for(n, 0), &env_for(n, 1), &env_for(n, 2)};
@@ -449,6 +901,7 @@ double Engine::update(int n, double nu) {
     }
     energy = theta + model.offset[CLS_PHYS] + nu * model.offset[CLS_PEN];
     have_energy = true;
+    last_updated = n;
     if (std::getenv("QEDTTN_TRACE"))
         std::fprintf(stderr, "[qedttn] update node %d size %lld terms %zu theta %.15g resid %.3g E %.15g\n",
                      n, (long long)n_el, ht.size(), theta, R.resid, energy);

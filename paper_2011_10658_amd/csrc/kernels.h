@@ -62,6 +62,16 @@ struct AdjSeg {
     int pad;
 };
 
+// One matrix of the one-sided Jacobi SVD: X (n x m, column-major, ld n) is
+// overwritten by W = X V with mutually orthogonal columns, V (m x m,
+// column-major) receives the rotations, sigma[j] = |W[:, j]|.
+struct SvdMat {
+    double* x;
+    double* v;
+    double* sigma;
+    int n, m;
+};
+
 // Workgroup tile shapes of the block GEMM (rows x cols of the output).
 enum {
     GEMM_SHAPE_SQUARE = 0,   //  64 x  64

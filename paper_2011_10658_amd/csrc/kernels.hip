@@ -918,6 +918,109 @@ void launch_normalise_sign(double* u, int64_t n, const double* nrm, double* pv, 
 }
 
 // ---------------------------------------------------------------------
+// one-sided Jacobi SVD (Hestenes) of small matrices
+// ---------------------------------------------------------------------
+// One workgroup per matrix.  A sweep visits every column pair once in the
+// round-robin (tournament) order, m' - 1 rounds of m'/2 disjoint pairs
+// (m' = m rounded up to even, the extra column a dummy); each wave rotates
+// its pairs: with a = |x_p|^2, b = |x_q|^2, g = x_p . x_q, the rotation with
+// zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1 / sqrt(1 + t^2), s = c t makes the two columns orthogonal, and is
+// applied to the same columns of V.  Sweeps stop when no pair had
+// |g| > 1e-15 sqrt(a b), or after 60; numerically zero columns are skipped.
+// Fixed order: reproducible.
+__global__ __launch_bounds__(256) void k_jacobi_svd(const SvdMat* __restrict__ mats) {
+    const SvdMat S = mats[blockIdx.x];
+    const int n = S.n, m = S.m;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ int rotated;
+    __shared__ double fro[4];
+    for (int i = threadIdx.x; i < m * m; i += 256) S.v[i] = (i % m == i / m) ? 1.0 : 0.0;
+    // columns below 1e-16 of the Frobenius norm are left alone (they are
+    // numerically zero and get dropped by any truncation)
+    double f2 = 0.0;
+    for (int64_t i = threadIdx.x; i < (int64_t)n * m; i += 256) f2 += S.x[i] * S.x[i];
+    f2 = wave_sum(f2);
+    if (lane == 0) fro[wave] = f2;
+    __syncthreads();
+    const double tiny = 1e-32 * (((fro[0] + fro[1]) + fro[2]) + fro[3]);
+    const int mp = (m + 1) & ~1;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (threadIdx.x == 0) rotated = 0;
+        __syncthreads();
+        for (int r = 0; r < mp - 1; ++r) {
+            for (int k = wave; k < mp / 2; k += 4) {
+                // tournament pairing: position 0 fixed, the others rotate
+                const int a0 = k == 0 ? 0 : 1 + (k - 1 + r) % (mp - 1);
+                const int b0 = 1 + (mp - 2 - k + r) % (mp - 1);
+                const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
+                if (q >= m) continue;
+                double* xp = S.x + (int64_t)p * n;
+                double* xq = S.x + (int64_t)q * n;
+                double sa = 0.0, sb = 0.0, sg = 0.0;
+                for (int i = lane; i < n; i += 64) {
+                    const double u = xp[i], w = xq[i];
+                    sa += u * u;
+                    sb += w * w;
+                    sg += u * w;
+                }
+                sa = wave_sum(sa);
+                sb = wave_sum(sb);
+                sg = wave_sum(sg);
+                sa = __shfl(sa, 0, 64);
+                sb = __shfl(sb, 0, 64);
+                sg = __shfl(sg, 0, 64);
+                if (sa <= tiny || sb <= tiny || fabs(sg) <= 1e-15 * sqrt(sa) * sqrt(sb)) continue;
+                const double zeta = (sb - sa) / (2.0 * sg);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int i = lane; i < n; i += 64) {
+                    const double u = xp[i], w = xq[i];
+                    xp[i] = c * u - s * w;
+                    xq[i] = s * u + c * w;
+                }
+                double* vp = S.v + (int64_t)p * m;
+                double* vq = S.v + (int64_t)q * m;
+                for (int i = lane; i < m; i += 64) {
+                    const double u = vp[i], w = vq[i];
+                    vp[i] = c * u - s * w;
+                    vq[i] = s * u + c * w;
+                }
+                if (lane == 0) rotated = 1;
+            }
+            __syncthreads();
+        }
+        const int any = rotated;
+        __syncthreads();
+        if (!any) break;
+    }
+    for (int j = wave; j < m; j += 4) {
+        const double* x = S.x + (int64_t)j * n;
+        double s2 = 0.0;
+        for (int i = lane; i < n; i += 64) s2 += x[i] * x[i];
+        s2 = wave_sum(s2);
+        if (lane == 0) S.sigma[j] = sqrt(s2);
+    }
+}
+
+void launch_jacobi_svd(const SvdMat* mats, int nmats, hipStream_t s) {
+    if (nmats <= 0) return;
+    hipLaunchKernelGGL(k_jacobi_svd, dim3(nmats), dim3(256), 0, s, mats);
+}
+
+// y += f x
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double f, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += f * x[i];
+}
+
+void launch_axpy(double* y, const double* x, double f, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, x, f, n);
+}
+
+// ---------------------------------------------------------------------
 // QR of the sector matrices of a node matricised along one leg
 // ---------------------------------------------------------------------
 // pack (dir = 0): tensor -> column-major sector matrices; unpack (dir = 1)

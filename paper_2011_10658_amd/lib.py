@@ -99,6 +99,7 @@ SIGNATURES = {
     "qed_get_energy": [_P, _DP],
     "qed_get_observables": [_P, _DP, _DP, _DP, _DP, _DP],
     "qed_get_site_fluxes": [_P, _DP, _DP],
+    "qed_set_expansion": [_P, C.c_int, C.c_double, C.c_int, C.c_int, C.c_uint64],
     "qed_get_plane_profiles": [_P, C.c_int, _DP, _DP],
     "qed_get_surface_density": [_P, _DP, _IP],
     "qed_pin_charges": [_P, C.c_int, _IP, _IP, C.c_double],
@@ -247,6 +248,11 @@ class Context:
 
     def set_lanczos(self, steps, cycles=1, tol=0.0):
         self._c(self.lib.qed_set_lanczos(self.h, steps, cycles, tol))
+
+    def set_expansion(self, alpha, delta, chi_max=0, seed=0, on=True):
+        """Subspace expansion (SVD moves; links grow by up to delta columns
+        per sector on the move after an update); on=False switches it off."""
+        self._c(self.lib.qed_set_expansion(self.h, 1 if on else 0, alpha, delta, chi_max, seed))
 
     def set_lanczos_schedule(self, tol0, factor=0.1):
         self._c(self.lib.qed_set_lanczos_schedule(self.h, tol0, factor))
