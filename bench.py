@@ -503,6 +503,48 @@ def observables_workload(lib, torch, steps):
     }
 
 
+def expansion_workload(lib, torch, steps):
+    """Subspace expansion on the benchmark lattice (2x2x2 free flux, d = 267,
+    Q = 0, m = t = 1, g^2 = 1): the same seeded start at bond dimension 16
+    with expansion (alpha = 1e-2, delta = 8, chi_max = 64) and without, and
+    the fixed allocation at bond dimension 64; FP32 GEMMs, per-sweep
+    energies, link dimensions and seconds from the library's clock."""
+    out = {}
+    g2e, g2m = lib.physical_line(1.0, 1.0)
+    for name, chi, exp in (("chi16_expanded_to_64", 16, True), ("chi16_fixed", 16, False),
+                           ("chi64_fixed", 64, False)):
+        ctx = lib.Context(0)
+        ctx.set_lattice(*L, lib.BC_OPEN_FREE_FLUX)
+        ctx.set_couplings(1.0, 1.0, g2e, g2m)
+        ctx.set_charge_sector(0)
+        ctx.set_bond_dim(chi)
+        ctx.set_penalty(10.0 * max(1.0, 0.5 * g2e, 0.5 * g2m), 4, 4)
+        ctx.set_lanczos(24, 4, 1e-10)
+        ctx.set_lanczos_schedule(1e-4, 0.1)
+        ctx.set_precision(lib.FP32, 1)
+        if exp:
+            ctx.set_expansion(1e-2, 8, 64, 7)
+        ctx.build_hamiltonian()
+        ctx.init_state(SEED)
+        reps = ctx.sweep(steps, report=True)
+        n = L[0] * L[1] * L[2]
+        dims = [sum(q for _, q in ctx.leg_sectors(e)) for e in range(n, 2 * n - 2)]
+        log(f"  {name}: E={reps[-1]['energy']:.10f}, {sum(r['seconds'] for r in reps) / steps * 1e3:.1f} "
+            f"ms/sweep, link dims {dims}")
+        out[name] = dict(energies=[r["energy"] for r in reps], sweep_s=[r["seconds"] for r in reps],
+                         link_dims=dims)
+        ctx.close()
+    e = out["chi16_expanded_to_64"]
+    return {
+        "metric": METRIC, "value": None, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": 1e3 * sum(e["sweep_s"]) / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "TTN sweeps with subspace expansion, 2x2x2 free-flux lattice QED "
+                               "(d=267), Q=0, m=t=1, g^2=1, chi 16 -> 64"},
+        **out, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def adjoint_workload(lib, torch, steps, warmup, cpu_budget, no_cpu):
     """Differentiation: one node with legs chi = 128 (charges -4..4, sizes
     4,8,16,23,26,23,16,8,4), 24 terms of symmetric sector-preserving factors
@@ -607,7 +649,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--workload", choices=("sweep", "batched", "finite_density", "adjoint",
-                                           "observables"),
+                                           "observables", "expansion"),
                     default="sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one elementwise pass of known size (256 MiB read, 256 MiB "
@@ -633,6 +675,10 @@ def main():
         log("== adjoint workload")
         print(json.dumps(adjoint_workload(lib, torch, a.steps, a.warmup, a.cpu_budget,
                                           a.no_cpu_baseline)), flush=True)
+        return
+    if a.workload == "expansion":
+        log("== subspace expansion workload")
+        print(json.dumps(expansion_workload(lib, torch, a.steps)), flush=True)
         return
     if a.workload == "observables":
         log("== observables workload")
