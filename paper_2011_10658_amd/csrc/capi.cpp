@@ -158,7 +158,11 @@ int qed_destroy(qed_ctx* ctx) {
             (void)hipStreamSynchronize(ctx->c.dev.stream);
         }
         ctx->c.eng.reset();
-        if (!ctx->c.host_only) (void)hipStreamSynchronize(ctx->c.dev.stream);
+        if (!ctx->c.host_only) {
+            (void)hipStreamSynchronize(ctx->c.dev.stream);
+            ctx->c.dev.trim();
+            (void)hipStreamSynchronize(ctx->c.dev.stream);
+        }
     } catch (...) {
     }
     delete ctx;
@@ -185,6 +189,7 @@ int qed_set_stream(qed_ctx* ctx, void* stream) {
         need_device(C(ctx));
         C(ctx).dev.sync();
         C(ctx).dev.stream = (hipStream_t)stream;
+        C(ctx).dev.restream((hipStream_t)stream);
         return QED_OK;
     });
 }

@@ -31,6 +31,23 @@ void Dev::check(hipError_t e, const char* what) {
         fail(QED_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// size class of a request: multiples of 256 B up to 4 KiB, above that
+// eight classes per power of two (at most 12.5% unused)
+static size_t size_class(size_t bytes) {
+    if (bytes <= 4096) return std::max<size_t>(256, (bytes + 255) / 256 * 256);
+    int k = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = (size_t)1 << (k - 3);
+    return (bytes + step - 1) / step * step;
+}
+
+// blocks above this total go straight back to the pool
+static constexpr size_t CACHE_LIMIT = (size_t)8 << 30;
+
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 void* Dev::alloc(size_t bytes) {
     if (device < 0) fail(QED_ERR_BAD_STATE, "host-only context has no device memory");
     used = true;
@@ -40,9 +57,32 @@ void* Dev::alloc(size_t bytes) {
         if (!p) fail(QED_ERR_OOM, "allocator hook returned NULL");
         return p;
     }
-    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (capturing(stream)) {
+        // a graph owns what is allocated during its capture
+        check(hipMallocAsync(&p, bytes, stream), "hipMallocAsync");
+        return p;
+    }
+    const size_t cls = size_class(bytes);
+    auto range = cache.equal_range(cls);
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second.stream == stream) {
+            p = it->second.p;
+            cache.erase(it);
+            cached_bytes -= cls;
+            live[p] = cls;
+            return p;
+        }
+    hipError_t e = hipMallocAsync(&p, cls, stream);
+    if (e == hipErrorOutOfMemory && !cache.empty()) {
+        (void)hipGetLastError();
+        sync();
+        trim();
+        sync();
+        e = hipMallocAsync(&p, cls, stream);
+    }
     if (e == hipErrorOutOfMemory) fail(QED_ERR_OOM, "out of device memory");
     check(e, "hipMallocAsync");
+    live[p] = cls;
     return p;
 }
 
@@ -52,7 +92,34 @@ void Dev::release(void* p) {
         ufree(p, (void*)stream, user);
         return;
     }
-    (void)hipFreeAsync(p, stream);
+    auto it = live.find(p);
+    if (it == live.end()) {   // allocated during a capture
+        (void)hipFreeAsync(p, stream);
+        return;
+    }
+    const size_t cls = it->second;
+    live.erase(it);
+    if (capturing(stream) || cached_bytes + cls > CACHE_LIMIT) {
+        (void)hipFreeAsync(p, stream);
+        return;
+    }
+    cache.emplace(cls, Cached{p, stream});
+    cached_bytes += cls;
+}
+
+void Dev::trim() {
+    for (auto& kv : cache) (void)hipFreeAsync(kv.second.p, kv.second.stream);
+    cache.clear();
+    cached_bytes = 0;
+}
+
+void Dev::restream(hipStream_t s) {
+    for (auto& kv : cache) kv.second.stream = s;
+}
+
+Dev::~Dev() {
+    // the streams may be gone by now: synchronous frees
+    for (auto& kv : cache) (void)hipFree(kv.second.p);
 }
 
 void Dev::sync() { check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
@@ -254,9 +321,11 @@ static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
 }
 
 void Plan::upload(Dev* dev) {
+    hold.clear();
     dj.clear();
     dp.clear();
     dt.clear();
+    std::vector<std::vector<GTile>> tiles;
     ntiles.clear();
     shape.clear();
     sumk.clear();
@@ -286,24 +355,43 @@ void Plan::upload(Dev* dev) {
                 best = sh;
             }
         }
-        std::vector<GTile> tiles = only_ident ? make_sum_tiles(jobs[s]) : make_tiles(jobs[s], best);
-        auto bj = std::make_shared<DBuf>(dev, jobs[s].size() * sizeof(GJob));
-        auto bp = std::make_shared<DBuf>(dev, std::max<size_t>(1, prods[s].size()) * sizeof(GProd));
-        auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
-        dev->check(hipMemcpyAsync(bj->p, jobs[s].data(), jobs[s].size() * sizeof(GJob),
-                                  hipMemcpyHostToDevice, dev->stream), "plan upload");
-        if (!prods[s].empty())
-            dev->check(hipMemcpyAsync(bp->p, prods[s].data(), prods[s].size() * sizeof(GProd),
-                                      hipMemcpyHostToDevice, dev->stream), "plan upload");
-        dev->check(hipMemcpyAsync(bt->p, tiles.data(), tiles.size() * sizeof(GTile),
-                                  hipMemcpyHostToDevice, dev->stream), "plan upload");
-        dj.push_back(bj);
-        dp.push_back(bp);
-        dt.push_back(bt);
-        ntiles.push_back((int)tiles.size());
+        tiles.push_back(only_ident ? make_sum_tiles(jobs[s]) : make_tiles(jobs[s], best));
+        ntiles.push_back((int)tiles.back().size());
         shape.push_back(best);
     }
-    dev->sync();  // host vectors of this plan may change afterwards
+    // one device buffer and one copy for the whole plan; arrays at 256-byte
+    // aligned offsets
+    const size_t S = jobs.size();
+    std::vector<size_t> oj(S), op(S), ot(S);
+    size_t total = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = total;
+        total += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    for (size_t s = 0; s < S; ++s) {
+        oj[s] = place(jobs[s].size() * sizeof(GJob));
+        op[s] = place(prods[s].size() * sizeof(GProd));
+        ot[s] = place(tiles[s].size() * sizeof(GTile));
+    }
+    std::vector<unsigned char> host(total);
+    for (size_t s = 0; s < S; ++s) {
+        if (!jobs[s].empty()) std::memcpy(&host[oj[s]], jobs[s].data(), jobs[s].size() * sizeof(GJob));
+        if (!prods[s].empty()) std::memcpy(&host[op[s]], prods[s].data(), prods[s].size() * sizeof(GProd));
+        if (!tiles[s].empty()) std::memcpy(&host[ot[s]], tiles[s].data(), tiles[s].size() * sizeof(GTile));
+    }
+    auto buf = std::make_shared<DBuf>(dev, total);
+    if (total)
+        dev->check(hipMemcpyAsync(buf->p, host.data(), total, hipMemcpyHostToDevice, dev->stream),
+                   "plan upload");
+    const unsigned char* base = buf->as<unsigned char>();
+    for (size_t s = 0; s < S; ++s) {
+        dj.push_back((const GJob*)(base + oj[s]));
+        dp.push_back((const GProd*)(base + op[s]));
+        dt.push_back((const GTile*)(base + ot[s]));
+    }
+    hold.push_back(buf);
+    dev->sync();  // the host copy is a local
 }
 
 void Plan::set_shape(Dev* dev, int s, int sh) {
@@ -311,7 +399,8 @@ void Plan::set_shape(Dev* dev, int s, int sh) {
     std::vector<GTile> tiles = make_tiles(jobs[s], sh);
     auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
     dev->upload(bt->p, tiles.data(), tiles.size() * sizeof(GTile));
-    dt[s] = bt;
+    hold.push_back(bt);
+    dt[s] = bt->as<GTile>();
     ntiles[s] = (int)tiles.size();
     shape[s] = sh;
 }
@@ -327,9 +416,9 @@ void Plan::run_stage(Dev* dev, int s, void* ws, void* x, void* y) {
 }
 
 void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
-    const GJob* J = dj[s]->as<GJob>();
-    const GProd* Pp = dp[s]->as<GProd>();
-    const GTile* T = dt[s]->as<GTile>();
+    const GJob* J = dj[s];
+    const GProd* Pp = dp[s];
+    const GTile* T = dt[s];
     if (sumk[s]) {
         launch_sum_stage(dtype, J, Pp, T, ntiles[s], b, st);
         return;

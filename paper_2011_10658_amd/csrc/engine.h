@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -93,13 +94,27 @@ struct Dev {
     void (*ufree)(void*, void*, void*) = nullptr;
     void* user = nullptr;
     bool used = false;
+    // Released blocks kept for reuse, keyed by size class.  A block is
+    // handed out again only to an allocation on the stream that released
+    // it, so stream order alone separates its old and new users (the same
+    // rule as the stream-ordered pool, without an API call per buffer).
+    struct Cached {
+        void* p;
+        hipStream_t stream;
+    };
+    std::multimap<size_t, Cached> cache;
+    std::unordered_map<void*, size_t> live;   // cacheable blocks in use -> size class
+    size_t cached_bytes = 0;
 
     void check(hipError_t e, const char* what);
     void* alloc(size_t bytes);
     void release(void* p);
+    void trim();   // return every cached block to the pool (stream-ordered)
+    void restream(hipStream_t s);   // after a sync: cached blocks move to stream s
     void sync();
     void upload(void* dst, const void* src, size_t bytes);
     void download(void* dst, const void* src, size_t bytes);
+    ~Dev();
 };
 
 struct DBuf {
@@ -182,8 +197,12 @@ struct Plan {
     int64_t ws_elems = 0;
     double flops = 0.0;
     double bytes = 0.0;
-    // device copies
-    std::vector<BufP> dj, dp, dt;
+    // device copies: every stage's jobs, products and tiles in one buffer
+    // (one copy per plan), plus re-tiled stages
+    std::vector<BufP> hold;
+    std::vector<const GJob*> dj;
+    std::vector<const GProd*> dp;
+    std::vector<const GTile*> dt;
     std::vector<int> ntiles;
     std::vector<int> shape;   // workgroup tile shape per stage
     std::vector<char> sumk;   // stage of identity products only: elementwise sum kernel
