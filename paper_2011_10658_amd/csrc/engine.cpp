@@ -20,6 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <tuple>
 
 namespace qed {
 
@@ -280,27 +281,71 @@ int64_t key3(int a, int b, int c) { return ((int64_t)a * 4096 + b) * 4096 + c; }
 
 }  // namespace
 
-// Tile order of a launch.  The tiles of one output column panel (same job,
-// batch entry and column tile; all row tiles) read the same B panel, so
-// they are kept on one XCD: workgroup i runs on XCD i mod 8, and each
-// XCD's tile list takes whole panels, least-loaded XCD first.  Slot
-// 8 k + x holds the k-th tile of XCD x; XCDs with fewer tiles are padded
-// with empty tiles (job -1), which return at once.
+// Tile order of a launch.  Workgroup i runs on XCD i mod 8; tiles that
+// read the same operand panel are kept on one XCD, one after another, so
+// the panel is fetched from HBM once and then served by that XCD's L2.
+// Usually the shared panel is B: the tiles of one output column panel
+// (same job, batch entry and column tile; all row tiles).  Where many jobs
+// multiply the same A operand (the first mode product of an H_eff
+// application: every term's factor on the last leg applied to the same
+// input block), the shared panel is A instead: the tiles of one row tile
+// across all those jobs and their column tiles.  Panels go to the
+// least-loaded XCD; slot 8 k + x holds the k-th tile of XCD x, and XCDs
+// with fewer tiles are padded with empty tiles (job -1), which return at
+// once.
 constexpr int NXCD = 8;
 
-static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, int sh) {
+static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, const std::vector<GProd>& prods,
+                                     int sh) {
     const int TM = gemm_tm(sh), TN = gemm_tn(sh);
     std::vector<std::vector<GTile>> per(NXCD);
-    for (size_t j = 0; j < jobs.size(); ++j) {
+    auto least = [&]() {
+        int x = 0;
+        for (int y = 1; y < NXCD; ++y)
+            if (per[y].size() < per[x].size()) x = y;
+        return x;
+    };
+    // jobs grouped by their A operand (all products of a job must agree)
+    std::map<std::tuple<const void*, int64_t, int, int, int64_t>, std::vector<int>> by_a;
+    bool a_ok = true;
+    for (size_t j = 0; j < jobs.size() && a_ok; ++j) {
         const GJob& J = jobs[j];
-        const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
-        for (int b = 0; b < J.batch; ++b)
-            for (int c = 0; c < tn; ++c) {
-                int x = 0;
-                for (int y = 1; y < NXCD; ++y)
-                    if (per[y].size() < per[x].size()) x = y;
-                for (int a = 0; a < tm; ++a) per[x].push_back(GTile{(int)j, b, a, c});
+        if (J.p1 <= J.p0 || J.batch != 1) {
+            a_ok = false;
+            break;
+        }
+        const GProd& f = prods[J.p0];
+        for (int q = J.p0; q < J.p1; ++q) {
+            const GProd& P = prods[q];
+            if (P.ident || P.A.abs != f.A.abs || P.A.off != f.A.off || P.A.tag != f.A.tag ||
+                P.lda != f.lda || P.tA != f.tA || P.rsA != f.rsA)
+                a_ok = false;
+        }
+        by_a[std::make_tuple(f.A.abs, f.A.off, f.A.tag, f.lda, f.rsA)].push_back((int)j);
+    }
+    if (a_ok && !jobs.empty() && by_a.size() * 2 <= jobs.size()) {
+        for (const auto& g : by_a) {
+            int tmax = 0;
+            for (int j : g.second) tmax = std::max(tmax, (jobs[j].M + TM - 1) / TM);
+            for (int a = 0; a < tmax; ++a) {
+                const int x = least();
+                for (int j : g.second) {
+                    if (a >= (jobs[j].M + TM - 1) / TM) continue;
+                    const int tn = (jobs[j].N + TN - 1) / TN;
+                    for (int c = 0; c < tn; ++c) per[x].push_back(GTile{j, 0, a, c});
+                }
             }
+        }
+    } else {
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const GJob& J = jobs[j];
+            const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
+            for (int b = 0; b < J.batch; ++b)
+                for (int c = 0; c < tn; ++c) {
+                    const int x = least();
+                    for (int a = 0; a < tm; ++a) per[x].push_back(GTile{(int)j, b, a, c});
+                }
+        }
     }
     size_t slots = 0;
     for (const auto& v : per) slots = std::max(slots, v.size());
@@ -355,7 +400,7 @@ void Plan::upload(Dev* dev) {
                 best = sh;
             }
         }
-        tiles.push_back(only_ident ? make_sum_tiles(jobs[s]) : make_tiles(jobs[s], best));
+        tiles.push_back(only_ident ? make_sum_tiles(jobs[s]) : make_tiles(jobs[s], prods[s], best));
         ntiles.push_back((int)tiles.back().size());
         shape.push_back(best);
     }
@@ -396,7 +441,7 @@ void Plan::upload(Dev* dev) {
 
 void Plan::set_shape(Dev* dev, int s, int sh) {
     if (shape[s] == sh || sumk[s]) return;
-    std::vector<GTile> tiles = make_tiles(jobs[s], sh);
+    std::vector<GTile> tiles = make_tiles(jobs[s], prods[s], sh);
     auto bt = std::make_shared<DBuf>(dev, tiles.size() * sizeof(GTile));
     dev->upload(bt->p, tiles.data(), tiles.size() * sizeof(GTile));
     hold.push_back(bt);
