@@ -1183,12 +1183,13 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const dou
             apply(vj, w);
             ++R.matvecs;
             launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
-            // three-term recurrence, two passes of classical Gram-Schmidt
-            // against V, norm: fused so that each pass reads the basis once
-            // (same arithmetic as the separate kernels)
-            if (launch_lz_fused(0, w, V, ld, 0, j, al, be, nullptr, n, part, co, st, s)) {
-                launch_lz_fused(1, w, V, ld, j + 1, j, al, be, co, n, part, co2, st, s);
-                launch_lz_fused(2, w, V, ld, j + 1, j, al, be, co2, n, part, sc + 1, st, s);
+            // three-term recurrence, classical Gram-Schmidt against V, a
+            // second pass where the first removed more than half of |w|^2
+            // (decided on the device), norm: fused so that each pass reads
+            // the basis once
+            if (launch_lz_fused(0, w, V, ld, 0, j, al, be, nullptr, nullptr, n, part, co, st, s)) {
+                launch_lz_fused(1, w, V, ld, j + 1, j, al, be, co, co, n, part, co2, st, s);
+                launch_lz_fused(2, w, V, ld, j + 1, j, al, be, co2, co, n, part, sc + 1, st, s);
             } else {
                 launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
                 for (int pass = 0; pass < 2; ++pass) {

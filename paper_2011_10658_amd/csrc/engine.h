@@ -36,8 +36,8 @@ void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64
 // workgroup per SUM_TILE consecutive output elements of a job
 void launch_sum_stage(int dtype, const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
 bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
-                     const double* alpha, const double* beta, const double* c, int64_t n,
-                     double* partial, double* out, const LState* st, hipStream_t s);
+                     const double* alpha, const double* beta, const double* c, const double* cf,
+                     int64_t n, double* partial, double* out, const LState* st, hipStream_t s);
 void launch_lz_three_term(double*, const double*, int64_t, int, const double*, const double*,
                           int64_t, const LState*, hipStream_t);
 void launch_lz_subtract(double*, const double*, int64_t, int, const double*, int64_t,

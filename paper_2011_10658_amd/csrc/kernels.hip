@@ -787,36 +787,61 @@ __global__ void k_scale_by(double* __restrict__ u, int64_t n, const double* fac)
 }
 
 // Fused Lanczos vector update + dot products, one pass over the basis:
-//   mode 0: w -= alpha_j v_j + beta_{j-1} v_{j-1}, then partials of V[r].w, r <= j
-//   mode 1: w -= sum_{r < nrows} c[r] V[r],       then partials of V[r].w, r < nrows
-//   mode 2: w -= sum_{r < nrows} c[r] V[r],       then the partial of w.w
+//   mode 0: w -= alpha_j v_j + beta_{j-1} v_{j-1}, then partials of V[r].w,
+//           r <= j, and of w.w (row j + 1)
+//   mode 1: w -= sum_{r < nrows} c[r] V[r], then, if a second Gram-Schmidt
+//           pass is needed, partials of V[r].w, r < nrows; otherwise the
+//           partial of w.w in row 0 (other rows zero)
+//   mode 2: if the second pass is needed, w -= sum_{r < nrows} c[r] V[r]
+//           and the partial of w.w; otherwise w is final and the partials
+//           forward c[0] (the norm from mode 1) unchanged
+// The second pass follows the criterion of Daniel, Gragg, Kaufman and
+// Stewart (Math. Comp. 30, 1976): with a = |w|^2 before the projection and
+// p = sum_r c_r^2 the squared length removed by it, |w'|^2 = a - p; the
+// projection is repeated only when it removed more than half of |w|^2
+// (|w'| < |w| / sqrt 2).  Both modes evaluate the test from the mode-0
+// coefficients `cf` (c_r, r < nrows, and a in entry nrows) with the same
+// arithmetic, so they agree everywhere.
 // The element partition (contiguous slice per workgroup, stride 256 inside),
 // the per-row accumulation order and the wave/block reduction are those of
 // k_dot_partial, and the update expressions those of k_lz_three_term and
-// k_lz_subtract, so the results equal the unfused kernels' bit for bit; each
-// basis element is loaded once for both the update and the dots.
+// k_lz_subtract; each basis element is loaded once for both the update and
+// the dots.
+__device__ __forceinline__ bool lz_second_pass(const double* cf, int nrows) {
+    double p = 0.0;
+    for (int r = 0; r < nrows; ++r) p += cf[r] * cf[r];
+    return 2.0 * p > cf[nrows];
+}
+
 template <int MAXR>
 __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const double* __restrict__ V,
                                                   int64_t ldv, int mode, int nrows, int j,
                                                   const double* __restrict__ alpha,
                                                   const double* __restrict__ beta,
-                                                  const double* __restrict__ c, int64_t n,
+                                                  const double* __restrict__ c,
+                                                  const double* __restrict__ cf, int64_t n,
                                                   double* __restrict__ partial, const LState* st) {
     if (st->broken) return;
     __shared__ double sh[MAXR][4];
     const int G = gridDim.x;
+    const bool second = mode == 0 || lz_second_pass(cf, nrows);
+    if (mode == 2 && !second) {
+        if (threadIdx.x == 0) partial[blockIdx.x] = blockIdx.x == 0 ? c[0] : 0.0;
+        return;
+    }
     const int64_t chunk = (n + G - 1) / G;
     const int64_t lo = blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     const int nr = mode == 0 ? j + 1 : nrows;          // rows in the update / dots
-    const int nd = mode == 2 ? 1 : nr;                  // dot rows
+    const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;   // partial rows written
+    const bool norm_only = mode == 2 || !second;         // mode 1 without a second pass
     const double a = mode == 0 ? alpha[j] : 0.0;
     const double b = (mode == 0 && j > 0) ? beta[j - 1] : 0.0;
     double s[MAXR];
 #pragma unroll
     for (int q = 0; q < MAXR; ++q) s[q] = 0.0;
-    // up to 16 rows the element's basis entries stay in registers between
-    // the update and the dots; beyond, the second read hits the cache
+    // up to 32 rows the element's basis entries stay in registers between
+    // the update and the dots
     constexpr bool CACHE = MAXR <= 32;
     for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
         constexpr int NV = CACHE ? MAXR : 1;
@@ -840,12 +865,17 @@ __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const 
             wi -= t;
         }
         w[i] = wi;
-        if (mode == 2) {
+        if (norm_only) {
             s[0] += wi * wi;
         } else {
 #pragma unroll
             for (int r = 0; r < MAXR; ++r)
-                if (r < nd) s[r] += QED_ROW(r) * wi;
+                if (r < nr) s[r] += QED_ROW(r) * wi;
+            if (mode == 0) {
+#pragma unroll
+                for (int r = 0; r < MAXR; ++r)
+                    if (r == nr) s[r] += wi * wi;
+            }
         }
     }
 #undef QED_ROW
@@ -863,18 +893,18 @@ __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const 
 }
 
 bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
-                     const double* alpha, const double* beta, const double* c, int64_t n,
-                     double* partial, double* out, const LState* st, hipStream_t s) {
+                     const double* alpha, const double* beta, const double* c, const double* cf,
+                     int64_t n, double* partial, double* out, const LState* st, hipStream_t s) {
     const int nr = mode == 0 ? j + 1 : nrows;
-    if (nr > 32) return false;
+    if (nr + 1 > 32) return false;   // mode 0 also needs the row of w.w
     const int G = dot_grid(n);
-    if (nr <= 16)
+    if (nr + 1 <= 16)
         hipLaunchKernelGGL(k_lz_fused<16>, dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
-                           beta, c, n, partial, st);
+                           beta, c, cf, n, partial, st);
     else
         hipLaunchKernelGGL(k_lz_fused<32>, dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
-                           beta, c, n, partial, st);
-    const int nd = mode == 2 ? 1 : nr;
+                           beta, c, cf, n, partial, st);
+    const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;
     hipLaunchKernelGGL(k_dot_final, dim3(nd), dim3(256), 0, s, partial, G, nd, out, 0, st, 1);
     return true;
 }
