@@ -366,7 +366,22 @@ __global__ __launch_bounds__(256) void k_sum_stage(const GJob* __restrict__ jobs
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
         const int row = (int)(e / J.N), col = (int)(e % J.N);
         T acc = (T)0;
-        for (int p = J.p0; p < J.p1; ++p) {
+        // four loads in flight, then the additions in product order
+        int p = J.p0;
+        for (; p + 4 <= J.p1; p += 4) {
+            T v[4], al[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const GProd& P = prods[p + u];
+                const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+                const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
+                v[u] = Bb[(int64_t)row * P.ldb + co];
+                al[u] = (T)P.alpha;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += al[u] * v[u];
+        }
+        for (; p < J.p1; ++p) {
             const GProd P = prods[p];
             const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
             const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
@@ -1114,6 +1129,7 @@ __device__ __forceinline__ void apply_panel(double* X, int64_t ld, int row0, int
     double* x1 = x0 + ld;
 #pragma unroll
     for (int t = 0; t < QR_RPL; ++t) {
+        if (64 * t >= mr) break;   // uniform: the wave's rows end here
         const int r = lane + 64 * t;
         a0[t] = r < mr ? x0[r] : 0.0;
         a1[t] = (two && r < mr) ? x1[r] : 0.0;
@@ -1123,6 +1139,7 @@ __device__ __forceinline__ void apply_panel(double* X, int64_t ld, int row0, int
     for (int k = 0; k < QB; ++k) w0[k] = w1[k] = 0.0;
 #pragma unroll
     for (int t = 0; t < QR_RPL; ++t) {
+        if (64 * t >= mr) break;
         const int r = lane + 64 * t;
         if (r < mr) {
 #pragma unroll
@@ -1151,6 +1168,7 @@ __device__ __forceinline__ void apply_panel(double* X, int64_t ld, int row0, int
     }
 #pragma unroll
     for (int t = 0; t < QR_RPL; ++t) {
+        if (64 * t >= mr) break;
         const int r = lane + 64 * t;
         if (r < mr) {
             double d0 = 0.0, d1 = 0.0;
