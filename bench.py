@@ -757,7 +757,7 @@ def main():
             "lattice": "2x2x2", "bond_dim": CHI, "charge": 0, "seed": SEED,
             "lanczos": "24 steps x <=4 cycles, tol max(1e-10, 1e-4 10^-s) in sweep s "
                        "(FP32 floor 2e-6, BF16 floor 3.9e-3), "
-                       "FP64 Rayleigh quotient per update",
+                       "FP64 Rayleigh quotient for the sweep energy (last update)",
             "timed": "sweeps resumed from the converged FP64 state (checkpoint after the "
                      "warm-up trajectory), after one untimed sweep",
         },

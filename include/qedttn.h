@@ -178,10 +178,11 @@ int qed_set_lanczos_schedule(qed_ctx* ctx, double tol0, double factor);
  * QED_ERR_INVALID_ARG for alpha < 0 or not finite, delta < 0, chi_max < 0. */
 int qed_set_expansion(qed_ctx* ctx, int on, double alpha, int delta, int chi_max, uint64_t seed);
 
-/* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16).  refine != 0 adds one
- * FP64 Rayleigh quotient per node update on the reduced-precision paths
- * (the node energy then carries an error second order in the eigenvector
- * error). */
+/* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16).  refine != 0 makes the
+ * reduced-precision paths compute the energy of each sweep (that of its
+ * last node update, the root) as an FP64 Rayleigh quotient of the Ritz
+ * vector, so that it carries an error second order in the eigenvector
+ * error; the other updates of a sweep keep their Ritz values. */
 int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine);
 
 /* Build the dressed-site bases, local operators, the term list, the tree

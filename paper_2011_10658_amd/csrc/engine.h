@@ -414,7 +414,7 @@ struct Engine {
     void move_to(int target);
     void build_env(int n, int which, EnvD& out);
     EnvD& env_for(int n, int which);
-    double update(int n, double nu);
+    double update(int n, double nu, bool refine_here = true);
 };
 
 // ---- segmented Lanczos: independent recurrences on segments of one

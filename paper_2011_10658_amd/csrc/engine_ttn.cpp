@@ -821,7 +821,7 @@ void Engine::prepare() {
     centre = tree.root;
 }
 
-double Engine::update(int n, double nu) {
+double Engine::update(int n, double nu, bool refine_here) {
     Dev* dev = &ctx->dev;
     const Params& P = ctx->prm;
     cur_nu = nu;
@@ -883,7 +883,7 @@ double Engine::update(int n, double nu) {
     ctx->mv_count += R.matvecs;
     ctx->mv_flops += R.matvecs * plan.flops;
     double theta = R.theta;
-    if (dtype != QED_FP64 && P.refine) {
+    if (dtype != QED_FP64 && P.refine && refine_here) {
         // FP64 Rayleigh quotient of the (normalised) Ritz vector
         Plan p64 = plan_matvec(T.legs, T.tab, ht, QED_FP64);
         p64.upload(dev);
@@ -928,7 +928,9 @@ void Engine::sweep(int s_index, qed_sweep_report* rep) {
                          std::chrono::duration<double>(b - a).count());
             a = b;
         }
-        update(n, nu);
+        // the energy of the sweep is that of its last update: only there
+        // does the reduced-precision path add the FP64 Rayleigh quotient
+        update(n, nu, n + 1 == (int)tree.nodes.size());
         if (trace) {
             dev->sync();
             std::fprintf(stderr, "[qedttn] update node %d: %.3f s\n", n,
