@@ -403,7 +403,7 @@ def finite_density(lib, torch, steps):
         "data": "synthetic",
         "config": {"workload": "TTN sweeps, 4x4x4 open-lattice compact QED, free-flux boundary "
                                "(d=267), Q=+8, m=t=1, g^2=1, chi=256, BF16 vs FP32 vs FP64 GEMMs",
-                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient"},
+                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient for the sweep energy"},
         "fp64_path": dict(sweep_s=res["f64"]["seconds"], energies=res["f64"]["energies"],
                           Q=res["f64"]["Q"], rho=res["f64"]["rho"]),
         "f32_path": out["f32"], "bf16_path": out["bf16"],
@@ -510,7 +510,7 @@ def observables_workload(lib, torch, steps):
         "data": "synthetic",
         "config": {"workload": "4x4x4 periodic zero-charge sweeps (chi=64, m=0.2, g_e^2=2, "
                                "g_m^2=4); capacitor and confinement observables",
-                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient"},
+                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient for the sweep energy"},
         **out, "roofline": None, "cpu_baseline": None,
     }
 
