@@ -1116,7 +1116,28 @@ constexpr int QB = 8;
 constexpr int QR_RPL = QR_ROWS / 64;   // rows per lane in the column passes
 constexpr int QB_PAIRS = QB * (QB - 1) / 2;
 
-__device__ __forceinline__ double wave_bcast_sum(double v) { return __shfl(wave_sum(v), 0, 64); }
+// Sum over the 64 lanes, the same value in every lane.  A butterfly whose
+// every step adds the partner lane's partial, so both partners form the
+// same sum (addition commutes) and all lanes end bit-identical: the first
+// four steps move data inside rows of 16 lanes with DPP (quad_perm [1,0,3,2]
+// and [2,3,0,1], row_half_mirror, row_mirror; no LDS traffic), the last two
+// exchange across rows with shuffles.  Needs every lane active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_allsum(double v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_move<0x141>(v);   // row_half_mirror: the other quad of 8 lanes
+    v += dpp_move<0x140>(v);   // row_mirror: the other half of 16 lanes
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_bcast_sum(double v) { return wave_allsum(v); }
 
 // y <- y - V S y for the QB-column panel V in LDS (rows r >= k of column k;
 // r relative to the panel's first row), S = T^T (trans = 1) or T, on the
@@ -1208,7 +1229,7 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
         for (int i = 0; i < w; ++i) {
             double s = 0.0;
             for (int r = i + tid; r < mr; r += 256) s += Vp[r * QB + i] * Vp[r * QB + i];
-            s = wave_sum(s);
+            s = wave_allsum(s);
             if (lane == 0) red[wave][0] = s;
             __syncthreads();
             if (tid == 0) {
@@ -1242,7 +1263,7 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
 #pragma unroll
                 for (int k = 0; k < QB; ++k) {
                     if (k <= i) continue;
-                    const double t = wave_sum(d[k]);
+                    const double t = wave_allsum(d[k]);
                     if (lane == 0) red[wave][k] = t;
                 }
                 __syncthreads();
@@ -1279,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_householder_qr(const QRMat* __restrict_
         }
 #pragma unroll
         for (int q = 0; q < QB_PAIRS; ++q) {
-            const double t = wave_sum(g[q]);
+            const double t = wave_allsum(g[q]);
             if (lane == 0) red[wave][q] = t;
         }
         __syncthreads();
