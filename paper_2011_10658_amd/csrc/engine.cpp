@@ -474,7 +474,13 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
 }
 
 void Prof::record_begin(hipStream_t s, hipEvent_t& a) {
-    (void)hipEventCreate(&a);
+    // harvested events are recorded again instead of being recreated
+    if (!pool.empty()) {
+        a = pool.back();
+        pool.pop_back();
+    } else {
+        (void)hipEventCreate(&a);
+    }
     (void)hipEventRecord(a, s);
 }
 
@@ -487,8 +493,8 @@ void Prof::harvest() {
         k[0] += 1.0;
         k[1] += t;
         k[2] += ev_flops[i];
-        (void)hipEventDestroy(ev[i].first);
-        (void)hipEventDestroy(ev[i].second);
+        pool.push_back(ev[i].first);
+        pool.push_back(ev[i].second);
     }
     ev.clear();
     ev_flops.clear();
@@ -518,6 +524,7 @@ Prof::~Prof() {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
 void Plan::run(Dev* dev, void* ws, void* x, void* y) {

@@ -175,6 +175,7 @@ struct TensorD {
 struct Prof {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<hipEvent_t> pool;        // harvested events, reused
     std::vector<double> ev_flops;
     std::vector<int> ev_key;             // stage index * 16 + tile shape
     long long launches = 0;

@@ -878,6 +878,9 @@ double Engine::update(int n, double nu, bool refine_here) {
     const double tol = dtype == QED_FP64 ? tol_s
                        : std::max(tol_s, dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32);
     LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol);
+    // the Lanczos run ended in a synchronising download: every GEMM event
+    // recorded so far has completed, and its pair can be reused
+    if (ctx->prof.on) ctx->prof.harvest();
     matvecs += R.matvecs;
     flops += R.matvecs * plan.flops;
     ctx->mv_count += R.matvecs;
