@@ -1165,8 +1165,8 @@ void LanczosWS::ensure(Dev* dev, int mm, int64_t nn) {
     scal = std::make_shared<DBuf>(dev, 8 * sizeof(double));
 }
 
-LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const double*, double*)>& apply,
-                      double* x, int64_t n, int m, int cycles, double tol) {
+LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double* x, int64_t n, int m,
+                      int cycles, double tol) {
     if (n <= 0) fail(QED_ERR_INVALID_ARG, "empty eigenproblem");
     m = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(m, 64), n));
     W.ensure(dev, m, n);
@@ -1187,16 +1187,16 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const dou
         launch_lz_start(V, x, sc + 0, n, st, m, s);
         for (int j = 0; j < m; ++j) {
             double* vj = V + (int64_t)j * ld;
-            apply(vj, w);
+            if (apply(vj, w, part)) launch_dot_final(part, n, 1, al + j, 0, st, 1, s);
+            else launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
             ++R.matvecs;
-            launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
             // three-term recurrence, classical Gram-Schmidt against V, a
             // second pass where the first removed more than half of |w|^2
             // (decided on the device), norm: fused so that each pass reads
             // the basis once
             if (launch_lz_fused(0, w, V, ld, 0, j, al, be, nullptr, nullptr, n, part, co, st, s)) {
                 launch_lz_fused(1, w, V, ld, j + 1, j, al, be, co, co, n, part, co2, st, s);
-                launch_lz_fused(2, w, V, ld, j + 1, j, al, be, co2, co, n, part, sc + 1, st, s);
+                launch_lz_norm_beta(w, V, ld, j + 1, j, al, be, co2, co, n, part, sc + 1, st, 1e-14, s);
             } else {
                 launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
                 for (int pass = 0; pass < 2; ++pass) {
@@ -1204,8 +1204,8 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const std::function<void(const dou
                     launch_lz_subtract(w, V, ld, j + 1, co, n, st, s);
                 }
                 launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
+                launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
             }
-            launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
             launch_lz_next(V, ld, j, w, be, n, st, s);
         }
         launch_tridiag(al, be, W.sv->as<double>(), st, W.work->as<double>(), s);

@@ -38,6 +38,17 @@ void launch_sum_stage(int dtype, const GJob*, const GProd*, const GTile*, int, c
 bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
                      const double* alpha, const double* beta, const double* c, const double* cf,
                      int64_t n, double* partial, double* out, const LState* st, hipStream_t s);
+// mode 2 of launch_lz_fused with the beta step of launch_lz_beta fused into
+// its final reduction
+bool launch_lz_norm_beta(double* w, const double* V, int64_t ldv, int nrows, int j, double* alpha,
+                         double* beta, const double* c, const double* cf, int64_t n, double* partial,
+                         double* ww, LState* st, double tol, hipStream_t s);
+// w = (double) a with the partials of v . w (layout of launch_dots, one row)
+void launch_f32_to_f64_dot(const float* a, double* w, const double* v, int64_t n, double* partial,
+                           const LState* st, hipStream_t s);
+// the final pass of launch_dots alone
+void launch_dot_final(const double* partial, int64_t n, int nrows, double* out, int mode,
+                      const LState* st, int skip, hipStream_t s);
 void launch_lz_three_term(double*, const double*, int64_t, int, const double*, const double*,
                           int64_t, const LState*, hipStream_t);
 void launch_lz_subtract(double*, const double*, int64_t, int, const double*, int64_t,
@@ -300,8 +311,11 @@ struct LanczosResult {
 
 // Lowest eigenpair; x (device FP64, length n) is the start vector and
 // receives the normalised Ritz vector.
-LanczosResult lanczos(Dev* dev, LanczosWS& ws, const std::function<void(const double*, double*)>& apply,
-                      double* x, int64_t n, int m, int cycles, double tol);
+// apply(v, y, part) computes y = H v; it may also leave the partials of
+// v . y in part (the layout of launch_dots, one row) and then returns true.
+using LanczosApply = std::function<bool(const double*, double*, double*)>;
+LanczosResult lanczos(Dev* dev, LanczosWS& ws, const LanczosApply& apply, double* x, int64_t n, int m,
+                      int cycles, double tol);
 
 // ---- node-level effective Hamiltonian (C ABI object) ------------------
 struct Ctx;

@@ -860,14 +860,20 @@ double Engine::update(int n, double nu, bool refine_here) {
         yc = std::make_shared<DBuf>(dev, n_el * dtype_size(dtype));
     }
     void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(dtype));
-    auto apply = [&](const double* v, double* y) {
+    auto apply = [&](const double* v, double* y, double* part) {
         if (dtype == QED_FP64) {
             plan.run(dev, w, (void*)v, (void*)y);
-        } else {
-            to_compute(dtype, v, xc->p, n_el, dev->stream);
-            plan.run(dev, w, xc->p, yc->p);
-            from_compute(dtype, yc->p, y, n_el, dev->stream);
+            return false;
         }
+        to_compute(dtype, v, xc->p, n_el, dev->stream);
+        plan.run(dev, w, xc->p, yc->p);
+        if (dtype == QED_FP32) {   // conversion back fused with the alpha dot
+            launch_f32_to_f64_dot((const float*)yc->p, y, v, n_el, part, lws.st->as<LState>(),
+                                  dev->stream);
+            return true;
+        }
+        from_compute(dtype, yc->p, y, n_el, dev->stream);
+        return false;
     };
     // an FP32 Krylov recurrence cannot resolve residuals below ~eps32 |H|:
     // restarts past that point only repeat work (the FP64 Rayleigh quotient

@@ -554,6 +554,44 @@ void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64
                        mode, st, skip);
 }
 
+// w = (double) a, and the partials of v . w with the partition and
+// reduction of k_dot_partial (one row): the FP32 matvec's conversion and
+// the Lanczos alpha dot in one pass, with the same results as the two
+// separate kernels
+__global__ __launch_bounds__(256) void k_f32_to_f64_dot(const float* __restrict__ a,
+                                                        double* __restrict__ w,
+                                                        const double* __restrict__ v, int64_t n,
+                                                        double* __restrict__ partial,
+                                                        const LState* st) {
+    if (st->broken) return;
+    __shared__ double sh[4];
+    const int G = gridDim.x;
+    const int64_t chunk = (n + G - 1) / G;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const double wi = (double)a[i];
+        w[i] = wi;
+        s += v[i] * wi;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+void launch_f32_to_f64_dot(const float* a, double* w, const double* v, int64_t n, double* partial,
+                           const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_f32_to_f64_dot, dim3(dot_grid(n)), dim3(256), 0, s, a, w, v, n, partial, st);
+}
+
+void launch_dot_final(const double* partial, int64_t n, int nrows, double* out, int mode,
+                      const LState* st, int skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_final, dim3(nrows), dim3(256), 0, s, partial, dot_grid(n), nrows, out,
+                       mode, st, skip);
+}
+
 // ---------------------------------------------------------------------
 // Lanczos step kernels (all no-ops once the state has broken down)
 // ---------------------------------------------------------------------
@@ -907,6 +945,35 @@ __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const 
             ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
 }
 
+// The mode-2 pass's final sum (|w|^2 into *ww) followed by the step of
+// k_lz_beta (beta_j = |w|, or breakdown) in the same single workgroup.
+__global__ __launch_bounds__(256) void k_dot_final_beta(const double* __restrict__ partial, int G,
+                                                        double* __restrict__ ww, double* alpha,
+                                                        double* beta, int j, LState* st,
+                                                        double tol) {
+    if (st->broken) return;
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < G; b += 256) s += partial[b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double t = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    *ww = t;
+    const double b = sqrt(t);
+    double scale = 1.0;
+    for (int i = 0; i <= j; ++i) scale = fmax(scale, fabs(alpha[i]));
+    for (int i = 0; i < j; ++i) scale = fmax(scale, beta[i]);
+    if (b <= tol * scale) {
+        beta[j] = 0.0;
+        st->broken = 1;
+        st->k = j + 1;
+    } else {
+        beta[j] = b;
+    }
+}
+
 bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
                      const double* alpha, const double* beta, const double* c, const double* cf,
                      int64_t n, double* partial, double* out, const LState* st, hipStream_t s) {
@@ -921,6 +988,22 @@ bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrow
                            beta, c, cf, n, partial, st);
     const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;
     hipLaunchKernelGGL(k_dot_final, dim3(nd), dim3(256), 0, s, partial, G, nd, out, 0, st, 1);
+    return true;
+}
+
+bool launch_lz_norm_beta(double* w, const double* V, int64_t ldv, int nrows, int j, double* alpha,
+                         double* beta, const double* c, const double* cf, int64_t n, double* partial,
+                         double* ww, LState* st, double tol, hipStream_t s) {
+    if (nrows + 1 > 32) return false;
+    const int G = dot_grid(n);
+    if (nrows + 1 <= 16)
+        hipLaunchKernelGGL(k_lz_fused<16>, dim3(G), dim3(256), 0, s, w, V, ldv, 2, nrows, j, alpha,
+                           beta, c, cf, n, partial, st);
+    else
+        hipLaunchKernelGGL(k_lz_fused<32>, dim3(G), dim3(256), 0, s, w, V, ldv, 2, nrows, j, alpha,
+                           beta, c, cf, n, partial, st);
+    hipLaunchKernelGGL(k_dot_final_beta, dim3(1), dim3(256), 0, s, partial, G, ww, alpha, beta, j, st,
+                       tol);
     return true;
 }
 
