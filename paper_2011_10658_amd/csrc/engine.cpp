@@ -1166,7 +1166,7 @@ void LanczosWS::ensure(Dev* dev, int mm, int64_t nn) {
 }
 
 LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double* x, int64_t n, int m,
-                      int cycles, double tol) {
+                      int cycles, double tol, float* vc) {
     if (n <= 0) fail(QED_ERR_INVALID_ARG, "empty eigenproblem");
     m = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(m, 64), n));
     W.ensure(dev, m, n);
@@ -1187,7 +1187,7 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double*
         launch_lz_start(V, x, sc + 0, n, st, m, s);
         for (int j = 0; j < m; ++j) {
             double* vj = V + (int64_t)j * ld;
-            if (apply(vj, w, part)) launch_dot_final(part, n, 1, al + j, 0, st, 1, s);
+            if (apply(vj, w, part, vc && j > 0)) launch_dot_final(part, n, 1, al + j, 0, st, 1, s);
             else launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
             ++R.matvecs;
             // three-term recurrence, classical Gram-Schmidt against V, a
@@ -1206,7 +1206,7 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double*
                 launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
                 launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
             }
-            launch_lz_next(V, ld, j, w, be, n, st, s);
+            launch_lz_next(V, ld, j, w, be, n, st, s, vc);
         }
         launch_tridiag(al, be, W.sv->as<double>(), st, W.work->as<double>(), s);
         launch_ritz(x, V, ld, W.sv->as<double>(), n, st, s);

@@ -55,7 +55,7 @@ void launch_lz_subtract(double*, const double*, int64_t, int, const double*, int
                         const LState*, hipStream_t);
 void launch_lz_beta(const double*, double*, double*, int, LState*, double, hipStream_t);
 void launch_lz_next(double*, int64_t, int, const double*, const double*, int64_t, const LState*,
-                    hipStream_t);
+                    hipStream_t, float* vc = nullptr);
 void launch_lz_start(double*, const double*, const double*, int64_t, LState*, int, hipStream_t);
 void launch_tridiag(const double*, const double*, double*, LState*, double*, hipStream_t);
 void launch_ritz(double*, const double*, int64_t, const double*, int64_t, const LState*,
@@ -311,11 +311,13 @@ struct LanczosResult {
 
 // Lowest eigenpair; x (device FP64, length n) is the start vector and
 // receives the normalised Ritz vector.
-// apply(v, y, part) computes y = H v; it may also leave the partials of
-// v . y in part (the layout of launch_dots, one row) and then returns true.
-using LanczosApply = std::function<bool(const double*, double*, double*)>;
+// apply(v, y, part, pre) computes y = H v; it may also leave the partials
+// of v . y in part (the layout of launch_dots, one row) and then returns
+// true.  With vc set, each new basis vector is also written to vc in FP32,
+// and pre = true tells apply that vc already holds v.
+using LanczosApply = std::function<bool(const double*, double*, double*, bool)>;
 LanczosResult lanczos(Dev* dev, LanczosWS& ws, const LanczosApply& apply, double* x, int64_t n, int m,
-                      int cycles, double tol);
+                      int cycles, double tol, float* vc = nullptr);
 
 // ---- node-level effective Hamiltonian (C ABI object) ------------------
 struct Ctx;

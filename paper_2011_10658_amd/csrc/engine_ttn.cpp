@@ -860,12 +860,12 @@ double Engine::update(int n, double nu, bool refine_here) {
         yc = std::make_shared<DBuf>(dev, n_el * dtype_size(dtype));
     }
     void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(dtype));
-    auto apply = [&](const double* v, double* y, double* part) {
+    auto apply = [&](const double* v, double* y, double* part, bool pre) {
         if (dtype == QED_FP64) {
             plan.run(dev, w, (void*)v, (void*)y);
             return false;
         }
-        to_compute(dtype, v, xc->p, n_el, dev->stream);
+        if (!pre) to_compute(dtype, v, xc->p, n_el, dev->stream);
         plan.run(dev, w, xc->p, yc->p);
         if (dtype == QED_FP32) {   // conversion back fused with the alpha dot
             launch_f32_to_f64_dot((const float*)yc->p, y, v, n_el, part, lws.st->as<LState>(),
@@ -883,7 +883,10 @@ double Engine::update(int n, double nu, bool refine_here) {
     if (P.lz_tol0 > 0.0) tol_s = std::max(tol_s, P.lz_tol0 * std::pow(P.lz_factor, (double)sweeps_done));
     const double tol = dtype == QED_FP64 ? tol_s
                        : std::max(tol_s, dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32);
-    LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol);
+    // the FP32 path takes each new basis vector's FP32 copy from the
+    // Lanczos step that writes it
+    LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol,
+                              dtype == QED_FP32 ? (float*)xc->p : nullptr);
     // the Lanczos run ended in a synchronising download: every GEMM event
     // recorded so far has completed, and its pair can be reused
     if (ctx->prof.on) ctx->prof.harvest();

@@ -643,15 +643,20 @@ __global__ void k_lz_beta(const double* ww, double* alpha, double* beta, int j, 
 }
 
 // V[j+1] = w / beta[j]
+// (and, with vc, its FP32 copy for the next matvec: the value the separate
+// conversion would write)
 __global__ void k_lz_next(double* __restrict__ V, int64_t ldv, int j,
                           const double* __restrict__ w, const double* __restrict__ beta,
-                          int64_t n, const LState* st) {
+                          int64_t n, const LState* st, float* __restrict__ vc) {
     if (st->broken) return;
     const double inv = 1.0 / beta[j];
     double* v = V + (int64_t)(j + 1) * ldv;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        v[i] = w[i] * inv;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double t = w[i] * inv;
+        v[i] = t;
+        if (vc) vc[i] = (float)t;
+    }
 }
 
 // dst = src / *nrm  (start vector); records the norm
@@ -1022,8 +1027,8 @@ void launch_lz_beta(const double* ww, double* alpha, double* beta, int j, LState
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, s, ww, alpha, beta, j, st, tol);
 }
 void launch_lz_next(double* V, int64_t ldv, int j, const double* w, const double* beta, int64_t n,
-                    const LState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_next, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, j, w, beta, n, st);
+                    const LState* st, hipStream_t s, float* vc) {
+    hipLaunchKernelGGL(k_lz_next, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, j, w, beta, n, st, vc);
 }
 void launch_lz_start(double* dst, const double* src, const double* nrm, int64_t n, LState* st,
                      int m, hipStream_t s) {
