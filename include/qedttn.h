@@ -97,15 +97,21 @@ int qed_destroy(qed_ctx* ctx);
 const char* qed_last_error(const qed_ctx* ctx);
 
 /* Device allocator hook: alloc(bytes, stream, user) returns device
- * memory or NULL; free(ptr, stream, user) releases it.  Both NULL
- * restores the default (hipMallocAsync / hipFreeAsync on the stream).
- * Must be called before any device allocation of the context. */
+ * memory or NULL; free(ptr, stream, user) releases it (every block by
+ * qed_destroy at the latest).  Both NULL restores the default: blocks from
+ * hipMallocAsync on the context's stream, kept after release in a cache of
+ * the context and handed out again to allocations of the same size class
+ * on the stream that released them, returned to the pool by qed_destroy or
+ * when an allocation runs out of memory.  Must be called before any device
+ * allocation of the context. */
 int qed_set_allocator(qed_ctx* ctx,
                       void* (*alloc)(uint64_t bytes, void* stream, void* user),
                       void (*free_fn)(void* ptr, void* stream, void* user),
                       void* user);
 
-/* HIP stream (hipStream_t as void*) for all work of the context. */
+/* HIP stream (hipStream_t as void*) for all work of the context.  The
+ * previous stream is synchronised first; cached blocks then belong to the
+ * new stream. */
 int qed_set_stream(qed_ctx* ctx, void* hip_stream);
 
 /* ---------------------------------------------------------------- */
