@@ -677,11 +677,21 @@ __global__ void k_lz_start(double* __restrict__ dst, const double* __restrict__ 
 // multisection on one wave (64 shifts per round, the interval shrinks 65x),
 // to full precision, then inverse iteration with a pivoted tridiagonal LU
 // by lane 0.  Writes s[0..k), st->theta and st->resid.
-__global__ void k_tridiag_lowest(const double* alpha, const double* beta, double* s, LState* st,
+// alpha, beta, the LU factors and the vector live in LDS (k <= 64): the
+// serial steps below read no global memory
+__global__ void k_tridiag_lowest(const double* alpha_g, const double* beta_g, double* s_g, LState* st,
                                  double* work) {
-    if (blockIdx.x != 0 || threadIdx.x >= 64) return;
+    (void)work;
+    if (blockIdx.x != 0) return;
+    __shared__ double alpha[64], beta[64], dl[64], dd[64], du[64], du2[64], s[64];
+    __shared__ int piv[64];
     const int lane = threadIdx.x;
     const int k = st->k;
+    if (lane < k) {
+        alpha[lane] = alpha_g[lane];
+        beta[lane] = beta_g[lane];
+    }
+    __syncthreads();
     double lo = 0.0, hi = 0.0, tnorm = 0.0;
     for (int i = 0; i < k; ++i) {
         double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < k - 1 ? fabs(beta[i]) : 0.0);
@@ -716,11 +726,6 @@ __global__ void k_tridiag_lowest(const double* alpha, const double* beta, double
     if (lane != 0) return;
     const double theta = 0.5 * (lo + hi);
     // inverse iteration on (T - theta I)
-    double* dl = work;
-    double* dd = work + 64;
-    double* du = work + 128;
-    double* du2 = work + 192;
-    int piv[64];
     for (int i = 0; i < k; ++i) s[i] = 1.0;
     const double eps = 2.3e-16 * (tnorm > 0 ? tnorm : 1.0);
     for (int iter = 0; iter < 3; ++iter) {
@@ -768,6 +773,7 @@ __global__ void k_tridiag_lowest(const double* alpha, const double* beta, double
         nrm = sqrt(nrm);
         for (int i = 0; i < k; ++i) s[i] /= nrm;
     }
+    for (int i = 0; i < k; ++i) s_g[i] = s[i];
     st->theta = theta;
     st->resid = fabs(beta[k - 1] * s[k - 1]);
 }
