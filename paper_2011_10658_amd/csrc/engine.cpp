@@ -121,12 +121,50 @@ void Dev::restream(hipStream_t s) {
 Dev::~Dev() {
     // the streams may be gone by now: synchronous frees
     for (auto& kv : cache) (void)hipFree(kv.second.p);
+    if (ring) {
+        (void)hipDeviceSynchronize();
+        (void)hipHostFree(ring);
+    }
 }
 
-void Dev::sync() { check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+void Dev::sync() {
+    check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (stream == ring_stream) ring_pos = 0;   // every staged copy has completed
+}
+
+static constexpr size_t RING_BYTES = (size_t)64 << 20;
+
+bool Dev::stage(void* dst, const void* src, size_t bytes) {
+    if (bytes > RING_BYTES / 4 || ring_failed || capturing(stream)) return false;
+    if (!ring) {
+        if (hipHostMalloc((void**)&ring, RING_BYTES, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ring = nullptr;
+            ring_failed = true;
+            return false;
+        }
+        ring_stream = stream;
+        ring_pos = 0;
+    }
+    if (stream != ring_stream) {   // copies staged on another stream: let them finish
+        if (ring_pos) check(hipStreamSynchronize(ring_stream), "hipStreamSynchronize");
+        ring_stream = stream;
+        ring_pos = 0;
+    }
+    size_t at = (ring_pos + 255) & ~(size_t)255;
+    if (at + bytes > RING_BYTES) {
+        sync();
+        at = 0;
+    }
+    std::memcpy(ring + at, src, bytes);
+    check(hipMemcpyAsync(dst, ring + at, bytes, hipMemcpyHostToDevice, stream), "upload");
+    ring_pos = at + bytes;
+    return true;
+}
 
 void Dev::upload(void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
+    if (stage(dst, src, bytes)) return;
     check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream), "upload");
     sync();  // the host buffer may be temporary
 }
@@ -426,9 +464,7 @@ void Plan::upload(Dev* dev) {
         if (!tiles[s].empty()) std::memcpy(&host[ot[s]], tiles[s].data(), tiles[s].size() * sizeof(GTile));
     }
     auto buf = std::make_shared<DBuf>(dev, total);
-    if (total)
-        dev->check(hipMemcpyAsync(buf->p, host.data(), total, hipMemcpyHostToDevice, dev->stream),
-                   "plan upload");
+    dev->upload(buf->p, host.data(), total);   // staged (asynchronous) or synchronous
     const unsigned char* base = buf->as<unsigned char>();
     for (size_t s = 0; s < S; ++s) {
         dj.push_back((const GJob*)(base + oj[s]));
@@ -436,7 +472,6 @@ void Plan::upload(Dev* dev) {
         dt.push_back((const GTile*)(base + ot[s]));
     }
     hold.push_back(buf);
-    dev->sync();  // the host copy is a local
 }
 
 void Plan::set_shape(Dev* dev, int s, int sh) {

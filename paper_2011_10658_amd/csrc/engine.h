@@ -120,6 +120,15 @@ struct Dev {
     void check(hipError_t e, const char* what);
     void* alloc(size_t bytes);
     void release(void* p);
+    // Pinned upload ring: small host-to-device copies are staged here and
+    // run asynchronously in stream order.  A region is written again only
+    // after the staging stream has been synchronised (every Dev::sync of
+    // that stream, or a wrap of the ring, which syncs).
+    unsigned char* ring = nullptr;
+    size_t ring_pos = 0;
+    hipStream_t ring_stream = nullptr;
+    bool ring_failed = false;
+    bool stage(void* dst, const void* src, size_t bytes);   // false: not staged
     void trim();   // return every cached block to the pool (stream-ordered)
     void restream(hipStream_t s);   // after a sync: cached blocks move to stream s
     void sync();
