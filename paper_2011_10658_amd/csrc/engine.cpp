@@ -197,6 +197,20 @@ void from_compute(int dtype, const void* a, double* b, int64_t n, hipStream_t s)
     else fail(QED_ERR_INVALID_ARG, "from_compute: FP64 needs no conversion");
 }
 
+void prepare_f32_copies(Dev* dev, const std::vector<LegOpD*>& ops) {
+    std::vector<ConvSeg> segs;
+    for (LegOpD* o : ops) {
+        if (!o || o->d32 || !o->lay.size || !o->d64) continue;
+        o->d32 = std::make_shared<DBuf>(dev, o->lay.size * sizeof(float));
+        segs.push_back(ConvSeg{o->f64(), o->d32->p, o->lay.size});
+    }
+    if (segs.empty()) return;
+    DBuf list(dev, segs.size() * sizeof(ConvSeg));
+    dev->upload(list.p, segs.data(), segs.size() * sizeof(ConvSeg));
+    launch_f64_to_f32_segs(list.as<ConvSeg>(), (int)segs.size(), dev->stream);
+    dev->check(hipGetLastError(), "conversion launch");
+}
+
 OpP make_op(Dev* dev, const Leg& leg, int delta, bool zero) {
     auto o = std::make_shared<LegOpD>();
     o->dev = dev;

@@ -27,6 +27,7 @@ void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, i
                    hipStream_t);
 void launch_fill(double*, int64_t, double, hipStream_t);
 void launch_f64_to_f32(const double*, float*, int64_t, hipStream_t);
+void launch_f64_to_f32_segs(const ConvSeg* segs, int nseg, hipStream_t);
 void launch_f32_to_f64(const float*, double*, int64_t, hipStream_t);
 int dot_grid(int64_t n);
 void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64_t n,
@@ -175,6 +176,9 @@ struct LegOpD {
 using OpP = std::shared_ptr<LegOpD>;
 
 OpP make_op(Dev* dev, const Leg& leg, int delta, bool zero = true);
+// The FP32 copies that ops still lack, made in one launch (instead of one
+// lazy conversion per op when a plan first asks for it).
+void prepare_f32_copies(Dev* dev, const std::vector<LegOpD*>& ops);
 
 // Element size of a GEMM operand type and conversions between FP64
 // vectors and the operand type (FP32: round to nearest; BF16: FP32 first,

@@ -850,6 +850,13 @@ double Engine::update(int n, double nu, bool refine_here) {
         ht.push_back(h);
     }
     const int dtype = P.dtype;
+    if (dtype == QED_FP32) {
+        std::vector<LegOpD*> ops;
+        for (const HTerm& h : ht)
+            for (int e = 0; e < 3; ++e)
+                if (h.op[e]) ops.push_back(h.op[e].get());
+        prepare_f32_copies(dev, ops);
+    }
     Plan plan = plan_matvec(T.legs, T.tab, ht, dtype);
     plan.upload(dev);
     plan.prof = &ctx->prof;

@@ -44,6 +44,13 @@ struct GJob {
     int M, N, ldc, batch, p0, p1, acc, nsc;
 };
 
+// One array of a batched FP64 -> FP32 conversion.
+struct ConvSeg {
+    const double* src;
+    void* dst;
+    int64_t n;
+};
+
 // Work item of one workgroup: tile (tm, tn) of batch item b of job j.
 struct GTile {
     int job, b, tm, tn;   // job < 0: an empty slot (the workgroup returns)

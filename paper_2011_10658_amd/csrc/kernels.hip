@@ -462,6 +462,18 @@ void launch_fill(double* x, int64_t n, double v, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, x, n, v);
 }
+// FP32 copies of several FP64 arrays in one launch, one workgroup per array
+// (the same rounding as k_f64_to_f32)
+__global__ __launch_bounds__(256) void k_f64_to_f32_segs(const ConvSeg* __restrict__ segs) {
+    const ConvSeg S = segs[blockIdx.x];
+    float* d = (float*)S.dst;
+    for (int64_t i = threadIdx.x; i < S.n; i += 256) d[i] = (float)S.src[i];
+}
+
+void launch_f64_to_f32_segs(const ConvSeg* segs, int nseg, hipStream_t st) {
+    if (nseg > 0) hipLaunchKernelGGL(k_f64_to_f32_segs, dim3(nseg), dim3(256), 0, st, segs);
+}
+
 void launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, st, a, b, n);
