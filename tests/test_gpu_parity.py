@@ -187,6 +187,43 @@ def test_lanczos_breakdown_small_space(ctx):
     assert np.array_equal(x.cpu().numpy(), [0.0, 1.0])
 
 
+@pytest.mark.parametrize("dtype,tol", [(lib.FP64, 1e-12), (lib.FP32, 2e-6)])
+def test_lanczos_exhausted_krylov_space(ctx, dtype, tol):
+    """More steps than the space has dimensions (12-dimensional H_eff, 24
+    steps asked, 12 taken): the last recurrences leave a remainder at the
+    rounding level of the matvec, the regime where the second Gram-Schmidt
+    pass is taken (FP32 products).  The Ritz value equals the lowest
+    eigenvalue of the dense operator and the Ritz vector is a unit
+    eigenvector."""
+    ctx.set_precision(dtype)
+    ctx.set_lanczos(24, 1, 0.0)
+    leg = [(0, 2), (1, 1)]
+    rng = np.random.default_rng(12)
+    terms = []
+    for k in range(3):
+        ops = []
+        for e in range(3):
+            blocks = {}
+            for q, n in leg:
+                m = rng.normal(size=(n, n))
+                blocks[q] = m + m.T
+            ops.append(blocks)
+        terms.append((float(rng.normal()), tuple(ops), (0, 0, 0)))
+    legs = (leg, leg, leg)
+    h, keep = make_heff(ctx, legs, terms)
+    n = h.size
+    H = oheff.matrix(legs, oracle_dense_terms(legs, terms))
+    assert H.shape == (n, n) and n <= 24
+    lam, vec = np.linalg.eigh(H)
+    x = dev(rng.normal(size=n))
+    ev, res, rc = h.lanczos(x.data_ptr(), 24)
+    scale = np.abs(lam).max()
+    assert abs(ev - lam[0]) <= tol * scale, (ev, lam[0])
+    u = x.cpu().numpy()
+    assert abs(np.linalg.norm(u) - 1.0) < 1e-12
+    assert np.linalg.norm(H @ u - lam[0] * u) <= 50 * tol * scale
+
+
 # ----------------------------------------------------------------------
 # TTN sweeps
 # ----------------------------------------------------------------------
