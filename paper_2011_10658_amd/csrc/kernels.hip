@@ -63,8 +63,11 @@ template <typename T> struct GemmK;
 template <> struct GemmK<float> { static constexpr int KC = 16; };
 template <> struct GemmK<double> { static constexpr int KC = 16; };
 
+// Occupancy hint of five waves per SIMD: the FP32 instances fit in 96 VGPRs
+// without spills (four waves otherwise); measured faster on the sweep, the
+// batched matvec and the adjoint.
 template <typename T, int WM, int WN, int BM, int BN, bool FLAT>
-__global__ __launch_bounds__(256) void k_brgemm(const GJob* __restrict__ jobs,
+__global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs,
                                                 const GProd* __restrict__ prods,
                                                 const GTile* __restrict__ tiles, Bases bases) {
     typedef typename Mfma<T>::v4 v4;
