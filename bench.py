@@ -156,57 +156,6 @@ def timed_from(lib, torch, dtype, ckpt, steps):
     return out
 
 
-def bottom_node_pattern(lat_L):
-    """Factor pattern (which legs carry a factor, with charge shifts) of the
-    effective Hamiltonian of bottom node 0 (sites 0 and 1) of the lattice,
-    from the support of every term: hopping pairs (shifts +1/-1), penalty
-    pairs, plaquettes, plus one block Hamiltonian per leg and class."""
-    Lx, Ly, Lz = lat_L
-
-    def idx(i, j, k):
-        return i + Lx * (j + Ly * k)
-
-    def inside(i, j, k):
-        return 0 <= i < Lx and 0 <= j < Ly and 0 <= k < Lz
-
-    def side(s):
-        return 0 if s == 0 else (1 if s == 1 else 2)
-
-    metas = [(True, 0, False, 0, False, 0), (False, 0, True, 0, False, 0),
-             (False, 0, False, 0, True, 0)] * 2
-    for k in range(Lz):
-        for j in range(Ly):
-            for i in range(Lx):
-                x = idx(i, j, k)
-                for mu in range(3):
-                    c = [i, j, k]
-                    c[mu] += 1
-                    if not inside(*c):
-                        continue
-                    y = idx(*c)
-                    sx, sy = side(x), side(y)
-                    if sx == sy:
-                        continue
-                    for dx, dy in ((1, -1), (-1, 1), (0, 0), (0, 0), (0, 0)):
-                        has = [False] * 3
-                        d = [0, 0, 0]
-                        has[sx], d[sx] = True, dx if sx < 2 else -dx
-                        has[sy], d[sy] = True, dy if sy < 2 else -dy
-                        metas.append((has[0], d[0], has[1], d[1], has[2], d[2]))
-                for a, b in ((0, 1), (0, 2), (1, 2)):
-                    c1 = [i, j, k]; c1[a] += 1
-                    c2 = [i, j, k]; c2[b] += 1
-                    c3 = list(c1); c3[b] += 1
-                    if not (inside(*c1) and inside(*c2) and inside(*c3)):
-                        continue
-                    sides = {side(x), side(idx(*c1)), side(idx(*c2)), side(idx(*c3))}
-                    if len(sides) < 2:
-                        continue
-                    for _ in range(2):
-                        metas.append((0 in sides, 0, 1 in sides, 0, 2 in sides, 0))
-    return metas
-
-
 def cpu_baseline(legs, budget_s=15.0):
     """The oracle's H_eff application (dense definition, NumPy float64) at
     the shape of bottom node 0 of the benchmark tree with its factor
@@ -215,21 +164,12 @@ def cpu_baseline(legs, budget_s=15.0):
     from oracle import heff as oh
     from paper_2011_10658_amd import synth
 
-    metas = bottom_node_pattern(L)
+    metas = synth.bottom_node_pattern(L)
     dims = [ob.leg_dim(g) for g in legs]
     terms = []
-    for t, (hA, dA, hB, dB, hC, dC) in enumerate(metas):
-        ops = []
-        for e, (h, d) in enumerate(((hA, dA), (hB, dB), (hC, dC))):
-            if not h:
-                ops.append(None)
-                continue
-            blk = {}
-            sizes = dict(legs[e])
-            for q, n in legs[e]:
-                if q + d in sizes:
-                    blk[q] = synth.normal(7, 1000 * t + 10 * e + q + 5, sizes[q + d] * n).reshape(sizes[q + d], n)
-            ops.append(ob.op_to_dense(blk, legs[e], d))
+    for (hA, dA, hB, dB, hC, dC), blks in zip(metas, synth.pattern_op_blocks(7, legs, metas)):
+        ops = [None if b is None else ob.op_to_dense(b, legs[e], d)
+               for e, (b, d) in enumerate(zip(blks, (dA, dB, dC)))]
         terms.append((1.0, *ops))
     mask = ob.allowed_mask(*legs)
     x = synth.normal(7, 3, int(mask.sum()))

@@ -303,18 +303,23 @@ int qed_get_surface_density(qed_ctx* ctx, double* sigma, int* nshell);
  * lambda not finite and positive; QED_ERR_BAD_STATE without a lattice. */
 int qed_pin_charges(qed_ctx* ctx, int n, const int* sites, const int* charges, double lambda);
 
-/* Cumulative counters of the context./* Cumulative counters of the context.  matvec_flops / matvecs: algorithmic
+/* Cumulative counters of the context.  matvec_flops / matvecs: algorithmic
  * work of every H_eff application (sweeps and node-level objects).
- * With profiling on, every launch of the block-GEMM kernel that belongs
- * to an H_eff application is bracketed by HIP events on the context's
- * stream: gemm_launches, gemm_ms (sum of the event intervals) and
- * gemm_flops (algorithmic flops of those launches). */
+ * With profiling on, every contraction launch that belongs to an H_eff
+ * application (block-GEMM and fused kernels) is bracketed by HIP events
+ * on the context's stream: gemm_launches, gemm_ms (sum of the event
+ * intervals) and gemm_flops (algorithmic flops of those launches) count
+ * all of them; fused_launches, fused_ms and fused_flops count the fused
+ * kernel's launches alone. */
 typedef struct {
     double matvec_flops;
     long long matvecs;
     long long gemm_launches;
     double gemm_ms;
     double gemm_flops;
+    long long fused_launches;
+    double fused_ms;
+    double fused_flops;
 } qed_stats;
 
 /* Profiling switch (0/1) for the H_eff block-GEMM launches; resets the

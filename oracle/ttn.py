@@ -760,8 +760,8 @@ class TTN:
             nd = self.tree.nodes[n]
             x = self.nodes[n]
             rp = rho[nd["p"]]
-            rho[nd["l"]] = np.einsum("abc,cd,xbd->ax", x, rp, x)
-            rho[nd["r"]] = np.einsum("abc,cd,axd->bx", x, rp, x)
+            rho[nd["l"]] = np.einsum("abc,cd,xbd->ax", x, rp, x, optimize=True)
+            rho[nd["r"]] = np.einsum("abc,cd,axd->bx", x, rp, x, optimize=True)
         return {s: rho[s] for s in range(self.tree.N)}
 
     def observables(self):

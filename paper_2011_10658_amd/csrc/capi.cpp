@@ -783,6 +783,9 @@ int qed_get_stats(qed_ctx* ctx, qed_stats* out) {
         out->gemm_launches = C(ctx).prof.launches;
         out->gemm_ms = C(ctx).prof.ms;
         out->gemm_flops = C(ctx).prof.flops;
+        out->fused_launches = C(ctx).prof.f_launches;
+        out->fused_ms = C(ctx).prof.f_ms;
+        out->fused_flops = C(ctx).prof.f_flops;
         return QED_OK;
     });
 }

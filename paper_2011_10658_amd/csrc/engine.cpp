@@ -254,6 +254,11 @@ struct Builder {
             P.prods.emplace_back();
             P.stage_flops.push_back(0.0);
         }
+        while ((int)P.fjobs.size() <= s) {
+            P.fjobs.emplace_back();
+            P.fprods.emplace_back();
+            P.fstage_flops.push_back(0.0);
+        }
     }
     void add_flops(int s, double f) {
         stage(s);
@@ -310,7 +315,7 @@ struct Builder {
     }
     // fresh-workspace mode product; returns false if the output sector
     // does not exist
-    bool mode(int s, const BV& in, int e, LegOpD& op, const Leg& leg, BV& out) {
+    bool mode(int s, const BV& in, int e, LegOpD& op, const Leg& leg, BV& out, bool count = true) {
         const int so = op.lay.out_of_in[in.s[e]];
         if (so < 0) return false;
         const int nout = leg.n[so];
@@ -324,7 +329,7 @@ struct Builder {
         out.p = ws(sz);
         GProd p = mode_prod(in, e, opblk, nout, 1.0, M, N, ldc, batch, bsC);
         job1(s, out.p, M, N, ldc, batch, bsC, p);
-        add_flops(s, 2.0 * in.n[0] * in.n[1] * in.n[2] * nout);
+        if (count) add_flops(s, 2.0 * in.n[0] * in.n[1] * in.n[2] * nout);
         return true;
     }
 };
@@ -407,6 +412,29 @@ static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, const std::v
     return tiles;
 }
 
+// Tiles of fused jobs: per job, its group tiles in order, each with all
+// of its row tiles one after another on the least-loaded XCD (the row
+// tiles of a group tile read the same input columns).
+static std::vector<GTile> make_fused_tiles(const std::vector<FJob>& jobs) {
+    std::vector<std::vector<GTile>> per(NXCD);
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const FJob& J = jobs[j];
+        const int tm = (J.M + FUSED_TM - 1) / FUSED_TM, tn = (J.G + J.ng - 1) / J.ng;
+        for (int c = 0; c < tn; ++c) {
+            int x = 0;
+            for (int y = 1; y < NXCD; ++y)
+                if (per[y].size() < per[x].size()) x = y;
+            for (int a = 0; a < tm; ++a) per[x].push_back(GTile{(int)j, 0, a, c});
+        }
+    }
+    size_t slots = 0;
+    for (const auto& v : per) slots = std::max(slots, v.size());
+    std::vector<GTile> tiles(slots * NXCD, GTile{-1, 0, 0, 0});
+    for (int x = 0; x < NXCD; ++x)
+        for (size_t k = 0; k < per[x].size(); ++k) tiles[k * NXCD + x] = per[x][k];
+    return tiles;
+}
+
 static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
     std::vector<GTile> tiles;
     for (size_t j = 0; j < jobs.size(); ++j) {
@@ -415,6 +443,28 @@ static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
             for (int64_t c = 0; c * SUM_TILE < n; ++c) tiles.push_back(GTile{(int)j, b, (int)c, 0});
     }
     return tiles;
+}
+
+// QEDTTN_GEMM_PIPELINE=flat or =loop forces one GEMM pipeline on every
+// stage of the plans built afterwards; anything else (or unset) chooses per
+// stage by the mean reduction length.
+static int forced_pipeline() {
+    const char* v = std::getenv("QEDTTN_GEMM_PIPELINE");
+    if (!v) return -1;
+    if (!std::strcmp(v, "flat")) return 1;
+    if (!std::strcmp(v, "loop")) return 0;
+    return -1;
+}
+
+// QEDTTN_HEFF_FUSED=1 plans the terms with a bond-leg factor of every FP32
+// and FP64 H_eff as fused stages where they apply; otherwise (the default)
+// every H_eff runs as three mode-product stages.  On the d = 267 nodes the
+// fused stages move about 3.5 times fewer bytes but run slower (each term's
+// short reduction waits on fresh operand loads), so they are not the
+// default.
+static bool fused_enabled() {
+    const char* v = std::getenv("QEDTTN_HEFF_FUSED");
+    return v && !std::strcmp(v, "1");
 }
 
 void Plan::upload(Dev* dev) {
@@ -437,8 +487,11 @@ void Plan::upload(Dev* dev) {
                 kn += 1.0;
             }
         sumk.push_back(only_ident ? 1 : 0);
-        // short reductions per product: pipeline across products
-        flat.push_back(kn > 0.0 && ksum / kn < 64.0 ? 1 : 0);
+        // short reductions per product: pipeline across products (the
+        // environment may force either pipeline, to compare the two on one
+        // plan)
+        const int forced = forced_pipeline();
+        flat.push_back(forced >= 0 ? forced : (kn > 0.0 && ksum / kn < 64.0 ? 1 : 0));
         // the tile shape that pads the stage's jobs least
         int best = GEMM_SHAPE_SQUARE;
         double best_area = -1.0;
@@ -456,10 +509,31 @@ void Plan::upload(Dev* dev) {
         ntiles.push_back((int)tiles.back().size());
         shape.push_back(best);
     }
+    // fused jobs of each stage
+    const size_t S = jobs.size();
+    fjobs.resize(S);
+    fprods.resize(S);
+    fstage_flops.resize(S, 0.0);
+    std::vector<std::vector<GTile>> ftiles(S);
+    dfj.clear();
+    dfp.clear();
+    dft.clear();
+    nftiles.clear();
+    fcs_rows.assign(S, 0);
+    fcs_cols.assign(S, 0);
+    for (size_t s = 0; s < S; ++s) {
+        ftiles[s] = make_fused_tiles(fjobs[s]);
+        nftiles.push_back((int)ftiles[s].size());
+        for (const FJob& J : fjobs[s])
+            for (int p = J.p0; p < J.p1; ++p)
+                if (fprods[s][p].hasC) {
+                    fcs_rows[s] = std::max(fcs_rows[s], fprods[s][p].np_in);
+                    fcs_cols[s] = std::max(fcs_cols[s], (J.np + 15) & ~15);
+                }
+    }
     // one device buffer and one copy for the whole plan; arrays at 256-byte
     // aligned offsets
-    const size_t S = jobs.size();
-    std::vector<size_t> oj(S), op(S), ot(S);
+    std::vector<size_t> oj(S), op(S), ot(S), ofj(S), ofp(S), oft(S);
     size_t total = 0;
     auto place = [&](size_t bytes) {
         const size_t at = total;
@@ -470,12 +544,21 @@ void Plan::upload(Dev* dev) {
         oj[s] = place(jobs[s].size() * sizeof(GJob));
         op[s] = place(prods[s].size() * sizeof(GProd));
         ot[s] = place(tiles[s].size() * sizeof(GTile));
+        ofj[s] = place(fjobs[s].size() * sizeof(FJob));
+        ofp[s] = place(fprods[s].size() * sizeof(FProd));
+        oft[s] = place(ftiles[s].size() * sizeof(GTile));
     }
     std::vector<unsigned char> host(total);
+    auto put = [&](size_t at, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(&host[at], src, bytes);
+    };
     for (size_t s = 0; s < S; ++s) {
-        if (!jobs[s].empty()) std::memcpy(&host[oj[s]], jobs[s].data(), jobs[s].size() * sizeof(GJob));
-        if (!prods[s].empty()) std::memcpy(&host[op[s]], prods[s].data(), prods[s].size() * sizeof(GProd));
-        if (!tiles[s].empty()) std::memcpy(&host[ot[s]], tiles[s].data(), tiles[s].size() * sizeof(GTile));
+        put(oj[s], jobs[s].data(), jobs[s].size() * sizeof(GJob));
+        put(op[s], prods[s].data(), prods[s].size() * sizeof(GProd));
+        put(ot[s], tiles[s].data(), tiles[s].size() * sizeof(GTile));
+        put(ofj[s], fjobs[s].data(), fjobs[s].size() * sizeof(FJob));
+        put(ofp[s], fprods[s].data(), fprods[s].size() * sizeof(FProd));
+        put(oft[s], ftiles[s].data(), ftiles[s].size() * sizeof(GTile));
     }
     auto buf = std::make_shared<DBuf>(dev, total);
     dev->upload(buf->p, host.data(), total);   // staged (asynchronous) or synchronous
@@ -484,6 +567,9 @@ void Plan::upload(Dev* dev) {
         dj.push_back((const GJob*)(base + oj[s]));
         dp.push_back((const GProd*)(base + op[s]));
         dt.push_back((const GTile*)(base + ot[s]));
+        dfj.push_back((const FJob*)(base + ofj[s]));
+        dfp.push_back((const FProd*)(base + ofp[s]));
+        dft.push_back((const GTile*)(base + oft[s]));
     }
     hold.push_back(buf);
 }
@@ -505,8 +591,16 @@ void Plan::run_stage(Dev* dev, int s, void* ws, void* x, void* y) {
     b.b[TAG_WS] = ws;
     b.b[TAG_X] = x;
     b.b[TAG_Y] = y;
-    if (!ntiles[s]) return;
-    launch_stage(s, b, dev->stream);
+    if (ntiles[s]) launch_stage(s, b, dev->stream);
+    launch_fused(s, b, dev->stream);
+}
+
+void Plan::launch_fused(size_t s, const Bases& b, hipStream_t st) const {
+    if (s >= nftiles.size() || !nftiles[s]) return;
+    if (dtype == QED_FP64)
+        launch_heff_fused<double>(dfj[s], dfp[s], dft[s], nftiles[s], b, fcs_rows[s], fcs_cols[s], st);
+    else
+        launch_heff_fused<float>(dfj[s], dfp[s], dft[s], nftiles[s], b, fcs_rows[s], fcs_cols[s], st);
 }
 
 void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
@@ -538,6 +632,10 @@ void Prof::harvest() {
         float t = 0.0f;
         if (hipEventElapsedTime(&t, ev[i].first, ev[i].second) == hipSuccess) ms += t;
         flops += ev_flops[i];
+        if (i < ev_key.size() && ev_key[i] % 16 == FUSED_KEY) {
+            f_ms += t;
+            f_flops += ev_flops[i];
+        }
         auto& k = by_key[i < ev_key.size() ? ev_key[i] : -1];
         k[0] += 1.0;
         k[1] += t;
@@ -556,7 +654,8 @@ void Prof::report() const {
         const int st = kv.first / 16, sh = kv.first % 16;
         const auto& v = kv.second;
         std::fprintf(stderr, "[qedttn] gemm stage %d tile %s: %.0f launches, %.3f ms, %.3e flops, %.2f TFLOP/s\n",
-                     st, sh < 3 ? shapes[sh] : "?", v[0], v[1], v[2], v[1] > 0 ? v[2] / v[1] / 1e9 : 0.0);
+                     st, sh < 3 ? shapes[sh] : (sh == FUSED_KEY ? "fused" : "?"), v[0], v[1], v[2],
+                     v[1] > 0 ? v[2] / v[1] / 1e9 : 0.0);
     }
 }
 
@@ -566,6 +665,8 @@ void Prof::reset() {
     by_key.clear();
     launches = 0;
     ms = flops = 0.0;
+    f_launches = 0;
+    f_ms = f_flops = 0.0;
 }
 
 Prof::~Prof() {
@@ -583,25 +684,40 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
     b.b[TAG_X] = x;
     b.b[TAG_Y] = y;
     for (size_t s = 0; s < dj.size(); ++s) {
-        if (!ntiles[s]) continue;
-        // summation stages run another kernel: only GEMM launches are timed
-        const bool timed = prof && prof->on && !sumk[s];
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) prof->record_begin(dev->stream, e0);
-        launch_stage(s, b, dev->stream);
-        if (timed) {
-            prof->record_begin(dev->stream, e1);
-            prof->ev.push_back({e0, e1});
-            prof->ev_flops.push_back(s < stage_flops.size() ? stage_flops[s] : 0.0);
-            prof->ev_key.push_back((int)s * 16 + shape[s]);
-            prof->launches += 1;
+        if (ntiles[s]) {
+            // summation stages run another kernel: only GEMM launches are timed
+            const bool timed = prof && prof->on && !sumk[s];
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) prof->record_begin(dev->stream, e0);
+            launch_stage(s, b, dev->stream);
+            if (timed) {
+                prof->record_begin(dev->stream, e1);
+                prof->ev.push_back({e0, e1});
+                prof->ev_flops.push_back(s < stage_flops.size() ? stage_flops[s] : 0.0);
+                prof->ev_key.push_back((int)s * 16 + shape[s]);
+                prof->launches += 1;
+            }
+        }
+        if (s < nftiles.size() && nftiles[s]) {
+            const bool timed = prof && prof->on;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) prof->record_begin(dev->stream, e0);
+            launch_fused(s, b, dev->stream);
+            if (timed) {
+                prof->record_begin(dev->stream, e1);
+                prof->ev.push_back({e0, e1});
+                prof->ev_flops.push_back(s < fstage_flops.size() ? fstage_flops[s] : 0.0);
+                prof->ev_key.push_back((int)s * 16 + Prof::FUSED_KEY);
+                prof->launches += 1;
+                prof->f_launches += 1;
+            }
         }
     }
     dev->check(hipGetLastError(), "brgemm launch");
 }
 
-void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
-                   const std::vector<HTerm>& terms, int64_t xoff) {
+void append_matvec_staged(Plan& P, const Leg legs[3], const BlockTable& tab,
+                          const std::vector<HTerm>& terms, int64_t xoff) {
     Builder B(P);
     B.stage(2);
     std::map<int64_t, int> bidx;
@@ -737,6 +853,309 @@ void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
             if (t.op[e] && t.coef != 0.0) P.bytes += t.op[e]->lay.size * es;
 }
 
+// Algorithmic flops of one term on one block, by the definition's order:
+// the factor on p first, then r, then l, each a dense product on the
+// extents the previous one produced (n: input extents, no: output).
+static void term_block_flops(const int n[3], const int no[3], bool hA, bool hB, bool hC,
+                             double& fA, double& fB, double& fC) {
+    const double n0 = n[0], n1 = n[1], n2 = n[2];
+    fC = hC ? 2.0 * n0 * n1 * n2 * no[2] : 0.0;
+    const double c2 = hC ? no[2] : n2;
+    fB = hB ? 2.0 * n0 * n1 * no[1] * c2 : 0.0;
+    const double b2 = hB ? no[1] : n1;
+    fA = hA ? 2.0 * n0 * no[0] * b2 * c2 : 0.0;
+}
+
+// The same product as a block-GEMM product (no bond factor): F X on the
+// row leg, or alpha X for an identity F.  X of a dense L job is read as
+// rows (ldx) by contiguous columns; X of a dense R job as rows (ldx) by
+// groups of np_in (stride gox) split like the output.
+static GProd as_gprod(const FProd& f, bool split) {
+    GProd g{};
+    g.alpha = f.alpha;
+    g.nred = 1;
+    if (f.identF) {
+        g.ident = 1;
+        g.B = f.X;
+        g.ldb = (int)f.ldx;
+    } else {
+        g.A = f.F;
+        g.lda = f.lda;
+        g.tA = 0;
+        g.B = f.X;
+        g.ldb = (int)f.ldx;
+        g.tB = 0;
+        g.K = f.K;
+    }
+    if (split) {
+        g.nsb = f.np_in;
+        g.nob = f.gox;
+    }
+    return g;
+}
+
+bool append_matvec_fused(Plan& P, const Leg legs[3], const BlockTable& tab,
+                         const std::vector<HTerm>& terms, int64_t xoff) {
+    if (P.dtype != QED_FP32 && P.dtype != QED_FP64) return false;
+    const int WCc = P.dtype == QED_FP32 ? FUSED_COLS_F32 : FUSED_COLS_F64;
+    // every bond sector must fit one 16-padded group of a tile
+    for (int v : legs[2].n)
+        if (((v + 15) & ~15) > WCc) return false;
+    Builder B(P);
+    B.stage(1);
+    const int es = B.esize;
+    const int nb = tab.nblk();
+    std::map<int64_t, int> bidx;
+    for (int b = 0; b < nb; ++b) bidx[key3(tab.s[0][b], tab.s[1][b], tab.s[2][b])] = b;
+    // per output block: products of the R job (factor on r, none on l; their
+    // sum P_R is added in the L job) and of the L job (everything else)
+    std::vector<std::vector<FProd>> Rp(nb), Lp(nb);
+    std::vector<char> Rc(nb, 0), Lc(nb, 0);
+    std::vector<double> rfl(nb, 0.0), lfl(nb, 0.0);
+    auto opblk = [&](const OpP& op, int s_in) {
+        return gabs((const char*)op->data(P.dtype) + op->lay.off[s_in] * es);
+    };
+    for (const HTerm& t : terms) {
+        if (t.coef == 0.0) continue;
+        for (int b = 0; b < nb; ++b) {
+            int s[3], n[3], os[3], no[3];
+            bool ok = true;
+            for (int e = 0; e < 3; ++e) {
+                s[e] = tab.s[e][b];
+                n[e] = legs[e].n[s[e]];
+                os[e] = t.op[e] ? t.op[e]->lay.out_of_in[s[e]] : s[e];
+                if (os[e] < 0) ok = false;
+                else no[e] = legs[e].n[os[e]];
+            }
+            if (!ok) continue;
+            auto it = bidx.find(key3(os[0], os[1], os[2]));
+            if (it == bidx.end()) continue;
+            const int ob = it->second;
+            const bool hA = (bool)t.op[0], hB = (bool)t.op[1], hC = (bool)t.op[2];
+            double fA, fB, fC;
+            term_block_flops(n, no, hA, hB, hC, fA, fB, fC);
+            const GRef xb = gtag(TAG_X, xoff + tab.off[b]);
+            FProd f{};
+            f.alpha = t.coef;
+            f.hasC = hC ? 1 : 0;
+            if (hC) f.Cb = opblk(t.op[2], s[2]);
+            f.np_in = n[2];
+            if (hB && !hA) {
+                // rows r', reduction over r, groups l: P_R(l, r', p') of the block
+                f.F = opblk(t.op[1], s[1]);
+                f.lda = n[1];
+                f.K = n[1];
+                f.X = xb;
+                f.ldx = n[2];
+                f.gox = (int64_t)n[1] * n[2];
+                Rp[ob].push_back(f);
+                Rc[ob] |= hC ? 1 : 0;
+                rfl[ob] += fB + fC;
+                continue;
+            }
+            GRef xin = xb;
+            int nr = n[1];
+            if (hB) {
+                // l and r factors: B x_r x into a workspace block first
+                BV cur, nxt;
+                cur.p = xb;
+                for (int e = 0; e < 3; ++e) {
+                    cur.s[e] = s[e];
+                    cur.n[e] = n[e];
+                }
+                B.mode(0, cur, 1, *t.op[1], legs[1], nxt, false);
+                B.add_flops(0, fB);
+                xin = nxt.p;
+                nr = nxt.n[1];
+            }
+            // rows l', reduction over l, groups r, bond entries p
+            if (hA) {
+                f.F = opblk(t.op[0], s[0]);
+                f.lda = n[0];
+            } else {
+                f.identF = 1;
+            }
+            f.K = n[0];
+            f.X = xin;
+            f.ldx = (int64_t)nr * n[2];
+            f.gox = n[2];
+            Lp[ob].push_back(f);
+            Lc[ob] |= hC ? 1 : 0;
+            lfl[ob] += fA + fC;
+        }
+    }
+    auto choose_ng = [&](int np, const std::vector<FProd>& ps, int G) {
+        const int p16 = (np + 15) & ~15;
+        int maxin = 1;
+        for (const FProd& f : ps) maxin = std::max(maxin, f.np_in);
+        int ng = std::min(WCc / p16, WCc / maxin);
+        return std::max(1, std::min(ng, G));
+    };
+    auto add_fjob = [&](int st, FJob J, const std::vector<FProd>& ps) {
+        J.p0 = (int)P.fprods[st].size();
+        for (const FProd& f : ps) P.fprods[st].push_back(f);
+        J.p1 = (int)P.fprods[st].size();
+        P.fjobs[st].push_back(J);
+    };
+    for (int ob = 0; ob < nb; ++ob) {
+        const int n0 = legs[0].n[tab.s[0][ob]], n1 = legs[1].n[tab.s[1][ob]],
+                  n2 = legs[2].n[tab.s[2][ob]];
+        if (!Rp[ob].empty()) {
+            const GRef pr = B.ws((int64_t)n0 * n1 * n2);
+            if (Rc[ob]) {
+                FJob J{};
+                J.Y = pr;
+                J.ldy = n2;
+                J.goy = (int64_t)n1 * n2;
+                J.M = n1;
+                J.G = n0;
+                J.np = n2;
+                J.ng = choose_ng(n2, Rp[ob], n0);
+                add_fjob(0, J, Rp[ob]);
+                P.fstage_flops[0] += rfl[ob];
+                P.flops += rfl[ob];
+            } else {
+                GJob J{};
+                J.C = pr;
+                J.M = n1;
+                J.N = n0 * n2;
+                J.ldc = n2;
+                J.nsc = n2;
+                J.noc = (int64_t)n1 * n2;
+                J.batch = 1;
+                J.p0 = (int)P.prods[0].size();
+                for (const FProd& f : Rp[ob]) P.prods[0].push_back(as_gprod(f, true));
+                J.p1 = (int)P.prods[0].size();
+                P.jobs[0].push_back(J);
+                B.add_flops(0, rfl[ob]);
+            }
+            FProd add{};
+            add.identF = 1;
+            add.alpha = 1.0;
+            add.X = pr;
+            add.K = n0;
+            add.ldx = (int64_t)n1 * n2;
+            add.gox = n2;
+            add.np_in = n2;
+            Lp[ob].push_back(add);
+        }
+        const GRef yb = gtag(TAG_Y, xoff + tab.off[ob]);
+        if (Lc[ob]) {
+            FJob J{};
+            J.Y = yb;
+            J.ldy = (int64_t)n1 * n2;
+            J.goy = n2;
+            J.M = n0;
+            J.G = n1;
+            J.np = n2;
+            J.ng = choose_ng(n2, Lp[ob], n1);
+            add_fjob(1, J, Lp[ob]);
+            P.fstage_flops[1] += lfl[ob];
+            P.flops += lfl[ob];
+        } else {
+            GJob J{};
+            J.C = yb;
+            J.M = n0;
+            J.N = n1 * n2;
+            J.ldc = n1 * n2;
+            J.batch = 1;
+            J.p0 = (int)P.prods[1].size();
+            for (const FProd& f : Lp[ob]) P.prods[1].push_back(as_gprod(f, false));
+            J.p1 = (int)P.prods[1].size();
+            P.jobs[1].push_back(J);
+            B.add_flops(1, lfl[ob]);
+        }
+    }
+    // algorithmic bytes: x, y and the operator blocks in the GEMM dtype
+    P.bytes += 2.0 * tab.size() * es;
+    for (const HTerm& t : terms)
+        for (int e = 0; e < 3; ++e)
+            if (t.op[e] && t.coef != 0.0) P.bytes += t.op[e]->lay.size * es;
+    return true;
+}
+
+void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
+                   const std::vector<HTerm>& terms, int64_t xoff) {
+    if (fused_enabled() && append_matvec_fused(P, legs, tab, terms, xoff)) return;
+    append_matvec_staged(P, legs, tab, terms, xoff);
+}
+
+// When the fused jobs of the last stage s have fewer than target tiles,
+// split every job's products into up to 8 contiguous groups of about equal
+// work, each written to a workspace block by a partial job (stage s), and
+// add the partial blocks in a new stage s + 1, in a fixed order.
+static bool split_fused_for_occupancy(Plan& P, int64_t target) {
+    const int s = (int)P.jobs.size() - 1;
+    if (s < 0 || (int)P.fjobs.size() <= s || P.fjobs[s].empty()) return false;
+    auto tiles_of = [](const FJob& J) {
+        return (int64_t)((J.M + FUSED_TM - 1) / FUSED_TM) * ((J.G + J.ng - 1) / J.ng);
+    };
+    int64_t T = 0;
+    for (const FJob& J : P.fjobs[s]) T += tiles_of(J);
+    if (T == 0 || T >= target) return false;
+    const int S = (int)std::min<int64_t>(8, (target + T - 1) / T);
+    if (S < 2) return false;
+    Builder B(P);
+    B.stage(s + 1);
+    std::vector<FJob> old = P.fjobs[s];
+    std::vector<FProd> oldp = P.fprods[s];
+    P.fjobs[s].clear();
+    P.fprods[s].clear();
+    auto work = [](const FProd& f) { return (int64_t)(f.identF ? 1 : f.K) + (f.hasC ? f.np_in : 0); };
+    for (const FJob& J : old) {
+        const int nprod = J.p1 - J.p0;
+        const int parts = std::min(S, nprod);
+        if (parts < 2) {
+            FJob j = J;
+            j.p0 = (int)P.fprods[s].size();
+            for (int p = J.p0; p < J.p1; ++p) P.fprods[s].push_back(oldp[p]);
+            j.p1 = (int)P.fprods[s].size();
+            P.fjobs[s].push_back(j);
+            continue;
+        }
+        int64_t W = 0;
+        for (int p = J.p0; p < J.p1; ++p) W += work(oldp[p]);
+        // the sum job reads Y's block densely: rows of G * np entries
+        GJob sum{};
+        sum.C = J.Y;
+        sum.M = J.M;
+        sum.N = J.G * J.np;
+        sum.ldc = (int)J.ldy;
+        sum.batch = 1;
+        sum.acc = J.acc;
+        sum.p0 = (int)P.prods[s + 1].size();
+        int q = J.p0;
+        int64_t done = 0;
+        for (int g = 0; g < parts && q < J.p1; ++g) {
+            const int64_t goal = W * (g + 1) / parts;
+            const GRef part = B.ws((int64_t)J.M * J.G * J.np);
+            FJob pj = J;
+            pj.Y = part;
+            pj.ldy = (int64_t)J.G * J.np;
+            pj.goy = J.np;
+            pj.acc = 0;
+            pj.p0 = (int)P.fprods[s].size();
+            do {
+                P.fprods[s].push_back(oldp[q]);
+                done += work(oldp[q]);
+                ++q;
+            } while (q < J.p1 && (done < goal || g == parts - 1));
+            pj.p1 = (int)P.fprods[s].size();
+            P.fjobs[s].push_back(pj);
+            GProd add{};
+            add.ident = 1;
+            add.B = part;
+            add.ldb = J.G * J.np;
+            add.alpha = 1.0;
+            add.nred = 1;
+            P.prods[s + 1].push_back(add);
+        }
+        sum.p1 = (int)P.prods[s + 1].size();
+        P.jobs[s + 1].push_back(sum);
+    }
+    return true;
+}
+
 Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
                  int dtype) {
     Plan P;
@@ -745,7 +1164,7 @@ Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTe
     // a single node's last stage has one job per output block, each summing
     // every term: too few tiles to fill the chip, so the term sums are split
     // into partial jobs and added in a final stage
-    split_for_occupancy(P, (int)P.jobs.size() - 1, 2048);
+    if (!split_fused_for_occupancy(P, 3072)) split_for_occupancy(P, (int)P.jobs.size() - 1, 2048);
     return P;
 }
 

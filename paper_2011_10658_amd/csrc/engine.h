@@ -25,6 +25,13 @@ namespace qed {
 template <typename T>
 void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape, bool flat,
                    hipStream_t);
+// fused H_eff stage: per output tile, every term's child-leg product and
+// bond-leg epilogue (heff_fused.hip)
+// (cs_rows x cs_cols: the largest bond-factor block of the launch, input
+// sector by 16-padded output sector)
+template <typename T>
+void launch_heff_fused(const FJob*, const FProd*, const GTile*, int, const Bases&, int cs_rows,
+                       int cs_cols, hipStream_t);
 void launch_fill(double*, int64_t, double, hipStream_t);
 void launch_f64_to_f32(const double*, float*, int64_t, hipStream_t);
 void launch_f64_to_f32_segs(const ConvSeg* segs, int nseg, hipStream_t);
@@ -201,9 +208,12 @@ struct Prof {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<hipEvent_t> pool;        // harvested events, reused
     std::vector<double> ev_flops;
-    std::vector<int> ev_key;             // stage index * 16 + tile shape
+    std::vector<int> ev_key;             // stage index * 16 + tile shape (FUSED_KEY: fused)
     long long launches = 0;
     double ms = 0.0, flops = 0.0;
+    long long f_launches = 0;            // the fused kernel's share of the above
+    double f_ms = 0.0, f_flops = 0.0;
+    static constexpr int FUSED_KEY = 15;
     std::map<int, std::array<double, 3>> by_key;   // launches, ms, flops per stage and shape
     void record_begin(hipStream_t s, hipEvent_t& a);
     void harvest();     // fold finished event pairs into ms (stream synced)
@@ -232,10 +242,22 @@ struct Plan {
     std::vector<int> shape;   // workgroup tile shape per stage
     std::vector<char> sumk;   // stage of identity products only: elementwise sum kernel
     std::vector<char> flat;   // stage with short reductions: flat product pipeline
+    // fused H_eff jobs (k_heff_fused) of each stage, launched after the
+    // stage's GEMM jobs; stages without them have empty lists (the lists
+    // may be shorter than `jobs`)
+    std::vector<std::vector<FJob>> fjobs;
+    std::vector<std::vector<FProd>> fprods;
+    std::vector<double> fstage_flops;
+    std::vector<const FJob*> dfj;
+    std::vector<const FProd*> dfp;
+    std::vector<const GTile*> dft;
+    std::vector<int> nftiles;
+    std::vector<int> fcs_rows, fcs_cols;   // largest bond block per stage
     void upload(Dev* dev);
     void run(Dev* dev, void* ws, void* x, void* y);
     void run_stage(Dev* dev, int s, void* ws, void* x, void* y);
     void launch_stage(size_t s, const Bases& b, hipStream_t st) const;
+    void launch_fused(size_t s, const Bases& b, hipStream_t st) const;
     void set_shape(Dev* dev, int s, int sh);   // re-tile one stage
 };
 
@@ -248,9 +270,17 @@ struct HTerm {
 Plan plan_matvec(const Leg legs[3], const BlockTable& tab, const std::vector<HTerm>& terms,
                  int dtype);
 // Append the jobs of one node's H_eff to P, with x and y at element offset
-// xoff of the bound vectors (batched plans concatenate nodes).
+// xoff of the bound vectors (batched plans concatenate nodes).  By default
+// every node runs as mode products in three GEMM stages
+// (append_matvec_staged); with QEDTTN_HEFF_FUSED=1, FP32 and FP64 plans of
+// nodes whose bond sectors fit a fused tile run the terms with a bond-leg
+// factor in fused stages (append_matvec_fused).
 void append_matvec(Plan& P, const Leg legs[3], const BlockTable& tab,
                    const std::vector<HTerm>& terms, int64_t xoff);
+void append_matvec_staged(Plan& P, const Leg legs[3], const BlockTable& tab,
+                          const std::vector<HTerm>& terms, int64_t xoff);
+bool append_matvec_fused(Plan& P, const Leg legs[3], const BlockTable& tab,
+                         const std::vector<HTerm>& terms, int64_t xoff);
 
 // Renormalised operators n^T (A (x) B) n on leg `which` of node tensor n.
 struct RTerm {

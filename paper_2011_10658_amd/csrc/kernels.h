@@ -44,6 +44,32 @@ struct GJob {
     int M, N, ldc, batch, p0, p1, acc, nsc;
 };
 
+// Fused H_eff stages (terms with a factor on the bond leg).  The output
+// block Y is read as rows m < M (stride ldy) of G groups (stride goy) of np
+// contiguous entries.  A product is  W = alpha F X  on the row leg (F:
+// M x K row-major with leading dimension lda, or the identity), with X
+// element (k, g, c) at k * ldx + g * gox + c (c < np_in), followed by
+// Y(m, g, :) += W(m, g, :) C^T with C the np x np_in bond block (row-major,
+// leading dimension np_in), or by Y += W when the product has no bond
+// factor (then np_in = np).
+struct FProd {
+    GRef F, X, Cb;
+    int64_t ldx, gox;
+    double alpha;
+    int K, lda, np_in, identF, hasC, pad;
+};
+
+// One output block of a fused stage: the sum of products [p0, p1), added
+// to Y (acc = 1) or written over it.  A workgroup tile covers 64 rows and
+// ng consecutive groups; in the tile every group takes np rounded up to a
+// multiple of 16 columns, so that a bond-factor product is a whole number
+// of MFMA column blocks per group.
+struct FJob {
+    GRef Y;
+    int64_t ldy, goy;
+    int M, G, np, ng, p0, p1, acc, pad;
+};
+
 // One array of a batched FP64 -> FP32 conversion.
 struct ConvSeg {
     const double* src;
@@ -78,6 +104,12 @@ struct SvdMat {
     double* sigma;
     int n, m;
 };
+
+// Rows of a fused-stage tile, and its widest W (dense groups) and Y
+// (16-padded groups) column spans per operand type.
+constexpr int FUSED_TM = 64;
+constexpr int FUSED_COLS_F32 = 128;
+constexpr int FUSED_COLS_F64 = 64;
 
 // Workgroup tile shapes of the block GEMM (rows x cols of the output).
 enum {

@@ -40,7 +40,8 @@ class SweepReport(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("matvec_flops", C.c_double), ("matvecs", C.c_longlong),
                 ("gemm_launches", C.c_longlong), ("gemm_ms", C.c_double),
-                ("gemm_flops", C.c_double)]
+                ("gemm_flops", C.c_double), ("fused_launches", C.c_longlong),
+                ("fused_ms", C.c_double), ("fused_flops", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -146,3 +146,78 @@ def batched_nodes(seed, nnodes, chis=(32, 48, 64, 96, 128), kmin=12, kmax=24,
             terms.append((1.0, ops[0], ops[1], ops[2]))
         out.append((legs, terms))
     return out
+
+
+def bottom_node_pattern(lat_L):
+    """Factor pattern of the effective Hamiltonian of the first bottom node
+    (sites 0 and 1, the pair merged along x) of an open lattice: per term
+    (hasA, dA, hasB, dB, hasC, dC), which legs carry a factor and its
+    charge shift.  One block Hamiltonian per leg and class (physics,
+    penalty); per link between two sides, two hopping terms (shifts +1/-1
+    and -1/+1, the parent side's shift negated) and three penalty terms;
+    per plaquette touching two or three sides, two terms."""
+    Lx, Ly, Lz = lat_L
+
+    def idx(i, j, k):
+        return i + Lx * (j + Ly * k)
+
+    def inside(i, j, k):
+        return 0 <= i < Lx and 0 <= j < Ly and 0 <= k < Lz
+
+    def side(s):
+        return 0 if s == 0 else (1 if s == 1 else 2)
+
+    metas = [(True, 0, False, 0, False, 0), (False, 0, True, 0, False, 0),
+             (False, 0, False, 0, True, 0)] * 2
+    for k in range(Lz):
+        for j in range(Ly):
+            for i in range(Lx):
+                x = idx(i, j, k)
+                for mu in range(3):
+                    c = [i, j, k]
+                    c[mu] += 1
+                    if not inside(*c):
+                        continue
+                    y = idx(*c)
+                    sx, sy = side(x), side(y)
+                    if sx == sy:
+                        continue
+                    for dx, dy in ((1, -1), (-1, 1), (0, 0), (0, 0), (0, 0)):
+                        has = [False] * 3
+                        d = [0, 0, 0]
+                        has[sx], d[sx] = True, dx if sx < 2 else -dx
+                        has[sy], d[sy] = True, dy if sy < 2 else -dy
+                        metas.append((has[0], d[0], has[1], d[1], has[2], d[2]))
+                for a, b in ((0, 1), (0, 2), (1, 2)):
+                    c1 = [i, j, k]; c1[a] += 1
+                    c2 = [i, j, k]; c2[b] += 1
+                    c3 = list(c1); c3[b] += 1
+                    if not (inside(*c1) and inside(*c2) and inside(*c3)):
+                        continue
+                    sides = {side(x), side(idx(*c1)), side(idx(*c2)), side(idx(*c3))}
+                    if len(sides) < 2:
+                        continue
+                    for _ in range(2):
+                        metas.append((0 in sides, 0, 1 in sides, 0, 2 in sides, 0))
+    return metas
+
+
+def pattern_op_blocks(seed, legs, metas):
+    """Random dense blocks for every factor of a pattern: per term and leg
+    with a factor, {q: (n_{q+d} x n_q) N(0,1) block} for every input sector
+    q whose shifted charge q + d is a sector (None for identities)."""
+    out = []
+    for t, (hA, dA, hB, dB, hC, dC) in enumerate(metas):
+        ops = []
+        for e, (h, d) in enumerate(((hA, dA), (hB, dB), (hC, dC))):
+            if not h:
+                ops.append(None)
+                continue
+            blk = {}
+            sizes = dict(legs[e])
+            for q, n in legs[e]:
+                if q + d in sizes:
+                    blk[q] = normal(seed, 1000 * t + 10 * e + q + 5, sizes[q + d] * n).reshape(sizes[q + d], n)
+            ops.append(blk)
+        out.append(ops)
+    return out

@@ -1,6 +1,9 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
 same seeded inputs."""
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -313,14 +316,27 @@ def test_periodic_sweep_equals_ed(ctx, L, chi):
 
 
 def test_fp32_path_matches_fp64(ctx):
-    """FP32-MFMA matvecs with the FP64 Rayleigh quotient: at the converged
-    FP64 state, FP32 sweeps keep the energy within 1e-8 relative; from the
-    same random start the FP32 path converges to the same energy."""
+    """FP32-MFMA matvecs with the FP64 Rayleigh quotient.
+    (1) At the converged FP64 state, FP32 sweeps keep the energy within
+    1e-8 relative (the energy error is second order in the eigenvector
+    error there).
+    (2) An independent FP32 trajectory from the same seeded start agrees
+    with the FP64 trajectory sweep by sweep while both are still far from a
+    fixed point (first two sweeps, within 1e-4 relative).  The FP32 Lanczos
+    stops at a residual floor of 2e-6 |theta|; the eigenvector error that
+    leaves (residual over the local gap) enters every later environment at
+    first order, since an unconverged state is not an eigenvector of the
+    full Hamiltonian (measured 1.6e-5 at the second sweep).  Later the two
+    may settle in different fixed points of
+    the truncated (chi = 16) ansatz (single-node updates from slightly
+    different states descend into different local minima), so the end
+    point is checked for convergence to 1e-8 and for lying within 1e-4 of
+    the FP64 end point, the spread of the fixed points of this ansatz."""
     setup_ctx(ctx, (2, 2, 2), 0, 0, 16, CPL, 10.0, steps=24, cycles=6, tol=1e-12, dtype=lib.FP64)
     ctx.init_state(7)
-    reps = ctx.sweep(16)
-    e64 = reps[-1]["energy"]
-    assert abs(reps[-1]["energy"] - reps[-2]["energy"]) <= 1e-10 * abs(e64)
+    reps64 = ctx.sweep(16)
+    e64 = reps64[-1]["energy"]
+    assert abs(reps64[-1]["energy"] - reps64[-2]["energy"]) <= 1e-10 * abs(e64)
     nn, _ = ctx.tree()
     state = [ctx.get_node(n) for n in range(nn)]
     # the converged state under FP32 sweeps
@@ -329,13 +345,15 @@ def test_fp32_path_matches_fp64(ctx):
         ctx.set_node(n, state[n])
     for r in ctx.sweep(2):
         assert abs(r["energy"] - e64) <= 1e-8 * abs(e64), (r["energy"], e64)
-    # an independent FP32 trajectory from the same start: at this strongly
-    # truncated chi = 16 it may settle in a nearby local minimum of the
-    # truncated ansatz (the chi = 64 benchmark trajectories meet to 3e-11)
+    # an independent FP32 trajectory from the same start
     ctx.init_state(7)
     reps = ctx.sweep(24)
-    assert abs(reps[-1]["energy"] - reps[-2]["energy"]) <= 1e-8 * abs(e64)
-    assert abs(reps[-1]["energy"] - e64) <= 1e-4 * abs(e64), (reps[-1]["energy"], e64)
+    for s in range(2):
+        e_ref = reps64[s]["energy"]
+        assert abs(reps[s]["energy"] - e_ref) <= 1e-4 * abs(e_ref), (s, reps[s]["energy"], e_ref)
+    e32 = reps[-1]["energy"]
+    assert abs(e32 - reps[-2]["energy"]) <= 1e-8 * abs(e32)
+    assert abs(e32 - e64) <= 1e-4 * abs(e64), (e32, e64)
 
 
 def test_lanczos_large_vector_deterministic(ctx):
@@ -457,3 +475,141 @@ def test_chemical_potential_sweep_equals_ed(ctx, L, bc, Q):
     e0 = OriginalED(lat, cpl, Q=Q).spectrum()[0]
     assert abs(reps[-1]["energy"] - e0) < 1e-10 * abs(e0), (reps[-1]["energy"], e0)
     ctx.set_chemical_potential(None)
+
+
+# ----------------------------------------------------------------------
+# the benchmark's own node shape
+# ----------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def bottom_node(ctx):
+    """Bottom node 0 of the 2x2x2 free-flux tree at chi = 64 (legs 267 x 267
+    x 64 from the library's sector allocation: l = {0: 141, 1: 126},
+    r = {-1: 126, 0: 141}, p = {-1: 14, 0: 37, 1: 13}; 1,802,691 entries),
+    with the node's 39-term factor pattern (hopping factors shift the
+    charge) and N(0,1) factor blocks; the oracle's application and the
+    same contraction over absolute values, computed once."""
+    g2e, g2m = lib.physical_line(1.0, 1.0)
+    ctx.set_lattice(2, 2, 2, lib.BC_OPEN_FREE_FLUX)
+    ctx.set_couplings(1.0, 1.0, g2e, g2m)
+    ctx.set_charge_sector(0)
+    ctx.set_bond_dim(64)
+    ctx.set_precision(lib.FP64)
+    ctx.build_hamiltonian()
+    legs = tuple(ctx.leg_sectors(e) for e in ctx.node_links(0))
+    assert [oblocks.leg_dim(g) for g in legs] == [267, 267, 64]
+    metas = synth.bottom_node_pattern((2, 2, 2))
+    assert len(metas) == 39
+    blks = synth.pattern_op_blocks(7, legs, metas)
+    coefs = synth.sym_uniform(7, 99, len(metas)) + 1.5
+    terms, dterms, aterms = [], [], []
+    for c, (hA, dA, hB, dB, hC, dC), ops in zip(coefs, metas, blks):
+        shifts = (dA, dB, dC)
+        terms.append((float(c), tuple(ops), shifts))
+        dense = [None if ops[e] is None else oblocks.op_to_dense(ops[e], legs[e], shifts[e])
+                 for e in range(3)]
+        dterms.append((float(c), *dense))
+        aterms.append((abs(float(c)), *[None if d is None else np.abs(d) for d in dense]))
+    _, offs = oblocks.block_table(*legs)
+    x = synth.normal(7, 3, int(offs[-1]))
+    y_or = oheff.apply_flat(x, legs, dterms)
+    y_abs = oheff.apply_flat(np.abs(x), legs, aterms)
+    return dict(legs=legs, metas=metas, terms=terms, x=x, y_or=y_or, y_abs=y_abs)
+
+
+@pytest.mark.parametrize("plan,pipeline", [("fused", None), ("staged", None), ("staged", "flat"),
+                                           ("staged", "loop")])
+@pytest.mark.parametrize("dtype", [lib.FP64, lib.FP32])
+def test_bench_bottom_node_matvec(ctx, bottom_node, dtype, plan, pipeline, monkeypatch):
+    """H_eff application at the benchmark's bottom-node shape, element by
+    element against the oracle: with the fused stages (terms with a
+    bond-leg factor applied per output tile), and with three mode-product
+    stages, their GEMM pipeline chosen per stage or forced to either
+    pipeline on every stage.  FP64: 1e-13 of max|y|.
+    FP32: 2e-6 of max|y|, and every element within the first-order
+    worst-case bound (4 input roundings, 2 stored intermediates, the three
+    reduction lengths and the term sum) times u = 2^-24 of the same
+    contraction over absolute values."""
+    if pipeline is None:
+        monkeypatch.delenv("QEDTTN_GEMM_PIPELINE", raising=False)
+    else:
+        monkeypatch.setenv("QEDTTN_GEMM_PIPELINE", pipeline)
+    monkeypatch.setenv("QEDTTN_HEFF_FUSED", "1" if plan == "fused" else "0")
+    ctx.set_precision(dtype)
+    B = bottom_node
+    legs = B["legs"]
+    h, keep = make_heff(ctx, legs, B["terms"])
+    assert h.size == B["x"].size == 1802691
+    assert h.flops()[0] == oheff.flops(legs, B["metas"])
+    xd = dev(B["x"])
+    yd = torch.full((h.size,), np.nan, dtype=torch.float64, device="cuda")
+    ctx.set_profiling(True)
+    h.matvec(xd.data_ptr(), yd.data_ptr())
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ctx.set_profiling(False)
+    # the plan that ran: fused launches only where asked for
+    assert (st["fused_launches"] > 0) == (plan == "fused"), st
+    y = yd.cpu().numpy()
+    h.close()
+    y_or = B["y_or"]
+    err = np.abs(y - y_or)
+    if dtype == lib.FP64:
+        assert err.max() <= 1e-13 * np.abs(y_or).max(), err.max() / np.abs(y_or).max()
+    else:
+        assert err.max() <= 2e-6 * np.abs(y_or).max(), err.max() / np.abs(y_or).max()
+        K = sum(max(n for _, n in g) for g in legs)
+        gamma = (4 + 2 + K + len(B["metas"])) * 2.0 ** -24
+        assert np.all(err <= gamma * B["y_abs"]), (err / B["y_abs"]).max()
+    ctx.set_precision(lib.FP64)
+
+
+GOLDEN_SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                            "sweep_2x2x2_free_chi64.json")
+
+
+@pytest.mark.parametrize("plan", ["staged", "fused"])
+@pytest.mark.parametrize("dtype", [lib.FP64, lib.FP32])
+def test_bench_config_sweeps_vs_oracle(ctx, dtype, plan, monkeypatch):
+    """The benchmark's lattice (2x2x2, free-flux boundary, d = 267 at every
+    site, m = t = 1, g^2 = 1 on the physical line, Q = 0, chi = 64) against
+    two sweeps of the oracle's tree tensor network from the same seeded
+    start with the same schedule (nu = 8, 12 Lanczos steps per update).
+    The oracle's values are stored by tests/golden/make_sweep_free_flux.py
+    (a run costs minutes of CPU).  The sector allocation must be identical
+    on every link.  FP64 GEMMs: per-sweep energies within 1e-9 relative,
+    site occupations, link fields and delta_L within 1e-8.  FP32 GEMMs:
+    the Ritz vectors of 12 unconverged steps carry the FP32 matvec error to
+    first order into every later environment (the state is not an
+    eigenvector yet, so the FP64 Rayleigh quotient does not square the
+    error), so the stated bound is 1e-5 relative for the energies and 1e-4
+    for the observables (measured 1.2e-5 on the link fields).  Both H_eff
+    plans: three mode-product stages, and the fused stages for the terms
+    with a bond-leg factor."""
+    monkeypatch.setenv("QEDTTN_HEFF_FUSED", "1" if plan == "fused" else "0")
+    with open(GOLDEN_SWEEP) as f:
+        G = json.load(f)
+    c = G["couplings"]
+    ctx.set_lattice(*G["lattice"], lib.BC_OPEN_FREE_FLUX)
+    ctx.set_couplings(c["t"], c["m"], c["g2e"], c["g2m"])
+    ctx.set_charge_sector(G["Q"])
+    ctx.set_bond_dim(G["chi"])
+    ctx.set_penalty(G["nu"], 0, 0)
+    ctx.set_lanczos(G["lanczos_steps"], 1, 0.0)
+    ctx.set_precision(dtype)
+    ctx.build_hamiltonian()
+    nn, ns = ctx.tree()
+    assert len(G["legs"]) == nn + ns
+    for e in range(nn + ns):
+        assert [list(s) for s in ctx.leg_sectors(e)] == G["legs"][str(e)], e
+    ctx.init_state(G["seed"])
+    reps = ctx.sweep(len(G["energies"]))
+    tol_e, tol_o = (1e-9, 1e-8) if dtype == lib.FP64 else (1e-5, 1e-4)
+    for s, eo in enumerate(G["energies"]):
+        assert abs(reps[s]["energy"] - eo) <= tol_e * abs(eo), (s, reps[s]["energy"], eo)
+    ob = ctx.observables()
+    assert np.abs(ob["occ"] - np.array(G["phi"])).max() < tol_o
+    assert np.abs(ob["efield"] - np.array(G["efield"])).max() < tol_o
+    assert abs(ob["deltaL"] - G["deltaL"]) < tol_o
+    assert abs(ob["Q"]) < 1e-10 and abs(G["Qexp"]) < 1e-10
+    assert abs(ob["rho"] - G["rho"]) < tol_o
+    ctx.set_precision(lib.FP64)

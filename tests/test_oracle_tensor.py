@@ -100,6 +100,42 @@ def test_heff_c1_symmetric_and_flops():
     assert heff.flops(legs, metas[:1]) == 20160
 
 
+def test_heff_flops_charge_shifted_hand_count():
+    """The flop count of charge-shifting terms, counted by hand from the
+    mode-product definition (factor on p first, then r, then l, each
+    dense on the extents the previous step produced; 2 flops per
+    multiply-add; a term whose output block does not exist costs 0).
+    Legs l = {0: 2, 1: 3}, r = {0: 1, 1: 2}, p = {0: 2, 1: 4, 2: 1};
+    allowed blocks (q_l, q_r, q_p): (0,0,0) (0,1,1) (1,0,1) (1,1,2)."""
+    l = [(0, 2), (1, 3)]
+    r = [(0, 1), (1, 2)]
+    p = [(0, 2), (1, 4), (2, 1)]
+    legs = (l, r, p)
+    # T1: A shift +1 on l, C shift +1 on p, no factor on r.
+    #   (0,0,0) -> (1,0,1): C 2*2*1*2*4 = 32, A 2*2*3*1*4 = 48  -> 80
+    #   (0,1,1) -> (1,1,2): C 2*2*2*4*1 = 32, A 2*2*3*2*1 = 24  -> 56
+    #   (1,*,*) -> q_l = 2 does not exist                       ->  0
+    t1 = (True, 1, False, 0, True, 1)
+    assert heff.flops(legs, [t1]) == 136
+    # T2: B shift -1 on r, C shift -1 on p.
+    #   (0,0,0), (1,0,1) -> q_r = -1 does not exist             ->  0
+    #   (0,1,1) -> (0,0,0): C 2*2*2*4*2 = 64, B 2*2*2*1*2 = 16  -> 80
+    #   (1,1,2) -> (1,0,1): C 2*3*2*1*4 = 48, B 2*3*2*1*4 = 48  -> 96
+    t2 = (False, 0, True, -1, True, -1)
+    assert heff.flops(legs, [t2]) == 176
+    # T3: A shift +1, B shift -1, C sector preserving.
+    #   only (0,1,1) -> (1,0,1): C 2*2*2*4*4 = 128, B 2*2*2*1*4 = 32,
+    #   A 2*2*3*1*4 = 48                                         -> 208
+    t3 = (True, 1, True, -1, True, 0)
+    assert heff.flops(legs, [t3]) == 208
+    assert heff.flops(legs, [t1, t2, t3]) == 520
+    # the sector-preserving closed form 2 n_l n_r n_p (n_l + n_r + n_p)
+    # summed over the four blocks
+    t0 = (True, 0, True, 0, True, 0)
+    closed = sum(2 * a * b * c * (a + b + c) for a, b, c in ((2, 1, 2), (2, 2, 4), (3, 1, 4), (3, 2, 1)))
+    assert heff.flops(legs, [t0]) == closed == 2 * (4 * 5 + 16 * 8 + 12 * 8 + 6 * 6)
+
+
 def test_heff_shifted_factors_stay_in_blocks():
     # a charge-shifting pair delta_A = +1, delta_C = +1 keeps y on allowed blocks
     leg = [(-1, 2), (0, 3), (1, 2)]
