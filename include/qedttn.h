@@ -368,6 +368,29 @@ int qed_heff_destroy(qed_heff* h);
 int qed_heff_size(qed_heff* h, int64_t* size);
 int qed_heff_matvec(qed_heff* h, const double* x, double* y);
 
+/* Size of the scratch area of qed_heff_matvec_noalloc, per GPU. */
+#define QED_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = H_eff x as qed_heff_matvec (same plan and kernels, same result),
+ * with the stage intermediates held in a fixed scratch area of
+ * QED_NOALLOC_SCRATCH_BYTES that the library keeps on every GPU it runs
+ * on from load to process exit, instead of the handle's own workspace.
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine (reduced-precision handles use the staging buffers that
+ * qed_heff_create made).  x, y: device FP64, length qed_heff_size,
+ * distinct; work is enqueued on the context's stream.
+ * Errors: QED_ERR_INVALID_ARG, with nothing launched, when the handle's
+ * stage workspace exceeds the scratch size (the message gives both);
+ * QED_ERR_HIP when the scratch address of the device could not be looked
+ * up at qed_create.  Every call on one GPU shares that GPU's scratch, so
+ * calls whose work overlaps on the device (several streams, threads or
+ * contexts) race on it; the scratch keeps the last call's contents, and
+ * no call reads a scratch element before writing it.  No profiling
+ * events are recorded for this call. */
+int qed_heff_matvec_noalloc(qed_heff* h, const double* x, double* y);
+
 /* Lanczos for the lowest eigenpair started from x (device FP64); x is
  * overwritten by the normalised Ritz vector; *eval receives theta and
  * *resid (may be NULL) the residual estimate.  `steps` per cycle, cycles

@@ -5,8 +5,10 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "engine.h"
 
@@ -69,6 +71,49 @@ Leg make_leg(const int* ch, const int* n, int s) {
 }
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// ---- scratch of the allocation-free matvec -----------------------------
+// Device memory with static storage: every GPU the library runs on holds
+// its own copy (at its own address) from module load until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host
+// the name is a stand-in, not a device address): the address of each
+// device's copy is looked up once per device, with that device current,
+// when a context is created on it.
+namespace {
+
+constexpr size_t SCRATCH_BYTES = QED_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+std::mutex scratch_mu;
+std::vector<void*> scratch_ptr;     // per device: address of its copy, or null
+std::vector<int> scratch_rc;        // per device: 0 = not looked up, 1 = ok, < 0 = failed
+
+// with `device` current
+void scratch_lookup(int device) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if ((int)scratch_ptr.size() <= device) {
+        scratch_ptr.resize(device + 1, nullptr);
+        scratch_rc.resize(device + 1, 0);
+    }
+    if (scratch_rc[device] == 1) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) {
+        scratch_ptr[device] = p;
+        scratch_rc[device] = 1;
+    } else {
+        (void)hipGetLastError();
+        scratch_rc[device] = -1;
+    }
+}
+
+void* scratch_for(int device) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (device < 0 || device >= (int)scratch_ptr.size() || scratch_rc[device] != 1) return nullptr;
+    return scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -145,6 +190,7 @@ int qed_create(qed_ctx** out, int hip_device) {
         }
         ctx->c.dev.device = hip_device;
         ctx->c.host_only = false;
+        scratch_lookup(hip_device);
     }
     *out = ctx;
     return QED_OK;
@@ -892,6 +938,26 @@ int qed_heff_matvec(qed_heff* h, const double* x, double* y) {
         if (!x || !y || x == y) fail(QED_ERR_INVALID_ARG, "x and y must be distinct device buffers");
         h->h.matvec(x, y);
         h->h.ctx->dev.check(hipGetLastError(), "matvec");
+        return QED_OK;
+    });
+}
+
+int qed_heff_matvec_noalloc(qed_heff* h, const double* x, double* y) {
+    if (!h) return QED_ERR_INVALID_ARG;
+    qed_ctx* ctx = h->owner;
+    return guard(ctx, [&] {
+        if (!x || !y || x == y) fail(QED_ERR_INVALID_ARG, "x and y must be distinct device buffers");
+        Heff& H = h->h;
+        const size_t need =
+            (size_t)std::max<int64_t>(1, H.plan.ws_elems) * (size_t)dtype_size(H.plan.dtype);
+        if (need > SCRATCH_BYTES)
+            fail(QED_ERR_INVALID_ARG, "this H_eff needs " + std::to_string(need) +
+                                          " bytes of workspace; the allocation-free matvec has " +
+                                          std::to_string(SCRATCH_BYTES));
+        void* w = scratch_for(H.ctx->dev.device);
+        if (!w) fail(QED_ERR_HIP, "the scratch address of this device could not be looked up");
+        H.matvec_ws(x, y, w);
+        H.ctx->dev.check(hipGetLastError(), "matvec (allocation-free)");
         return QED_OK;
     });
 }

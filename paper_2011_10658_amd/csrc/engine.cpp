@@ -1699,9 +1699,19 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double*
 void Heff::matvec(const double* x, double* y) {
     Dev* dev = &ctx->dev;
     plan.prof = &ctx->prof;
+    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(plan.dtype));
+    run_matvec(x, y, w);
+}
+
+void Heff::matvec_ws(const double* x, double* y, void* w) {
+    plan.prof = nullptr;   // no timing events: nothing is created
+    run_matvec(x, y, w);
+}
+
+void Heff::run_matvec(const double* x, double* y, void* w) {
+    Dev* dev = &ctx->dev;
     ctx->mv_flops += plan.flops;
     ctx->mv_count += 1;
-    void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(plan.dtype));
     const int64_t n = tab.size();
     if (plan.dtype == QED_FP64) {
         plan.run(dev, w, (void*)x, (void*)y);

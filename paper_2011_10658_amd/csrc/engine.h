@@ -397,6 +397,10 @@ struct Heff {
     LanczosWS lws;
     Adjoint adj;
     void matvec(const double* x, double* y);
+    // the same application with the stage workspace at w (at least
+    // plan.ws_elems elements of the plan's type); allocates nothing
+    void matvec_ws(const double* x, double* y, void* w);
+    void run_matvec(const double* x, double* y, void* w);
     void build_adjoint();
     void adjoint(const double* x, const double* ybar, double* xbar, double* const* opbar,
                  double* coefbar);

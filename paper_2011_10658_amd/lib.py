@@ -119,6 +119,7 @@ SIGNATURES = {
     "qed_heff_destroy": [_P],
     "qed_heff_size": [_P, _LP],
     "qed_heff_matvec": [_P, _P, _P],
+    "qed_heff_matvec_noalloc": [_P, _P, _P],
     "qed_heff_lanczos": [_P, _P, _I, _DP, _DP],
     "qed_heff_flops": [_P, _DP, _DP],
     "qed_heff_matvec_adjoint": [_P, _P, _P, _P, C.POINTER(_P), _DP],
@@ -430,6 +431,10 @@ class Heff:
 
     def matvec(self, x_ptr, y_ptr):
         self.ctx._c(self.ctx.lib.qed_heff_matvec(self.h, C.c_void_p(x_ptr), C.c_void_p(y_ptr)))
+
+    def matvec_noalloc(self, x_ptr, y_ptr):
+        self.ctx._c(self.ctx.lib.qed_heff_matvec_noalloc(self.h, C.c_void_p(x_ptr),
+                                                         C.c_void_p(y_ptr)))
 
     def lanczos(self, x_ptr, steps=0):
         ev, res = C.c_double(), C.c_double()
