@@ -10,9 +10,11 @@ driven penalty (4 linear + 4 quadratic sweeps up to nu_max = 40).
 A step is one sweep: every tree node gets one update (H_eff from the
 environments, FP64 Lanczos over block-GEMM matvecs, QR move of the
 isometry centre, renormalisation of the environments).  Each GEMM path
-(FP64, FP32, BF16 operands) first runs its own warm-up trajectory from the
-seeded start (per-sweep energies, time to convergence).  The FP64
-trajectory's converged state is checkpointed, and every path times its
+(FP64, FP32, BF16 operands; BF16 with the FP64 residual correction) first
+runs its own untimed trajectory from the seeded start, at least --warmup
+sweeps and on until it converges (|E_s - E_{s-1}| <= 1e-8 |E_s| at the
+final penalty; per-sweep energies, matvecs and time to convergence).  The
+FP64 trajectory's final state is checkpointed, and every path times its
 sweeps resumed from that same state: the headline is the FP32 path, and
 its energy there is compared with the FP64 path's (dE_rel, at the same
 variational state rather than after trajectories that may settle in
@@ -33,7 +35,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H_eff matvec TFLOP/s + TTN sweep s, FP32/BF16-MFMA vs FP64 at ΔE≤1e-8"
-PEAK = {"f32": 157.3, "f64": 78.6}
+PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
+# GEMM refinement per path (qed_set_precision): FP32 keeps its Krylov
+# recurrence in reduced precision with an FP64 Rayleigh quotient for the
+# sweep energy; BF16 adds the FP64 residual correction at every update
+REFINE = {"f64": 1, "f32": 1, "bf16": 2}
+MAX_TRAJECTORY = 30
 L = (2, 2, 2)
 CHI = 64
 SEED = 2011
@@ -73,7 +80,7 @@ def recorded_traffic():
     return rec.get("bytes_per_launch")
 
 
-def make_ctx(lib, dtype):
+def make_ctx(lib, dtype, refine=1):
     ctx = lib.Context(0)
     g2e, g2m = lib.physical_line(1.0, 1.0)
     ctx.set_lattice(*L, lib.BC_OPEN_FREE_FLUX)
@@ -84,47 +91,66 @@ def make_ctx(lib, dtype):
     ctx.set_penalty(nu_max, 4, 4)
     ctx.set_lanczos(24, 4, 1e-10)
     ctx.set_lanczos_schedule(1e-4, 0.1)    # tol_s = max(1e-10, 1e-4 10^-s)
-    ctx.set_precision(dtype, 1)
+    ctx.set_precision(dtype, refine)
     ctx.build_hamiltonian()
     ctx.init_state(SEED)
     return ctx
 
 
-def trajectory(lib, torch, dtype, warmup, save=None):
-    """`warmup` untimed sweeps from the seeded start, one record each
-    (energy, penalty, delta_L, library-timed seconds); the state is saved to
-    `save` at the end when given."""
-    ctx = make_ctx(lib, dtype)
+def trajectory(lib, torch, dtype, refine, warmup, save=None):
+    """Untimed sweeps from the seeded start, one record each (energy,
+    penalty, delta_L, matvecs, library-timed seconds): at least `warmup`,
+    and on until the path has converged (first sweep s at the final penalty
+    with |E_s - E_{s-1}| <= 1e-8 |E_s|) or MAX_TRAJECTORY sweeps.  The final
+    state is saved to `save` when given."""
+    ctx = make_ctx(lib, dtype, refine)
+    ctx.set_profiling(True)
     t0 = time.perf_counter()
-    reps = ctx.sweep(warmup, report=True) if warmup else []
+    reps, conv = [], None
+    while len(reps) < MAX_TRAJECTORY:
+        reps += ctx.sweep(1, report=True)
+        i = len(reps) - 1
+        if conv is None and i and reps[i]["nu"] == reps[i - 1]["nu"] and \
+                abs(reps[i]["energy"] - reps[i - 1]["energy"]) <= 1e-8 * abs(reps[i]["energy"]):
+            conv = i
+        if conv is not None and len(reps) >= warmup:
+            break
     torch.cuda.synchronize()
-    log(f"  trajectory: {warmup} sweeps from the seeded start, {time.perf_counter() - t0:.2f} s")
+    log(f"  trajectory: {len(reps)} sweeps from the seeded start, {time.perf_counter() - t0:.2f} s")
     for i, r in enumerate(reps):
         log(f"    sweep {i}: E={r['energy']:.12f} nu={r['nu']:.3f} dL={r['deltaL']:.3e} "
-            f"{r['seconds'] * 1e3:.1f} ms")
-    # time to convergence: first sweep s at the final penalty with
-    # |E_s - E_{s-1}| <= 1e-8 |E_s|
-    conv, t_conv = None, 0.0
-    for i, r in enumerate(reps):
-        t_conv += r["seconds"]
-        if i and r["nu"] == reps[i - 1]["nu"] and \
-                abs(r["energy"] - reps[i - 1]["energy"]) <= 1e-8 * abs(r["energy"]):
-            conv = i
-            break
+            f"{r['matvecs']} matvecs {r['seconds'] * 1e3:.1f} ms")
+    t_conv = sum(r["seconds"] for r in reps[:conv + 1]) if conv is not None else None
+    st = ctx.stats()
+    ctx.set_profiling(False)
     if save:
         ctx.save_state(save)
-    out = dict(energy=reps[-1]["energy"] if reps else None, converged_sweep=conv,
-               seconds_to_converge=t_conv if conv is not None else None,
+    out = dict(energy=reps[-1]["energy"], sweeps=len(reps), converged_sweep=conv,
+               gemm_tflops=st["gemm_flops"] / (st["gemm_ms"] / 1e3) / 1e12 if st["gemm_ms"] else 0.0,
+               gemm_launches=st["gemm_launches"], gemm_ms=st["gemm_ms"],
+               seconds_to_converge=t_conv,
+               matvecs_to_converge=sum(r["matvecs"] for r in reps[:conv + 1]) if conv is not None else None,
                energies=[r["energy"] for r in reps])
     ctx.close()
     return out
 
 
-def timed_from(lib, torch, dtype, ckpt, steps):
+def fp64_check(lib, ckpt):
+    """Energy of one FP64 sweep resumed from a saved state: at a converged
+    state of another path it tells whether that state is also a fixed point
+    of the FP64 sweep."""
+    ctx = make_ctx(lib, lib.FP64, 1)
+    ctx.load_state(ckpt)
+    e = ctx.sweep(1, report=True)[0]["energy"]
+    ctx.close()
+    return e
+
+
+def timed_from(lib, torch, dtype, refine, ckpt, steps):
     """Resume the saved state, one untimed sweep (environments and plans are
     rebuilt), then `steps` timed sweeps bracketed by device syncs, with the
     H_eff GEMM launches timed by HIP events on the library's stream."""
-    ctx = make_ctx(lib, dtype)
+    ctx = make_ctx(lib, dtype, refine)
     ctx.load_state(ckpt)
     ctx.sweep(1, report=False)
     ctx.set_profiling(True)
@@ -150,6 +176,7 @@ def timed_from(lib, torch, dtype, ckpt, steps):
         deltaL=ob["deltaL"],
         Q=ob["Q"],
     )
+    out["matvecs_per_sweep"] = out["matvecs"] / steps
     out["tflops"] = out["flops"] / wall / 1e12
     out["gemm_tflops"] = out["gemm_flops"] / (out["gemm_ms"] / 1e3) / 1e12 if out["gemm_ms"] else 0.0
     ctx.close()
@@ -176,23 +203,42 @@ def cpu_baseline(legs, budget_s=15.0):
     xd = np.zeros(dims)
     xd[mask] = x
     flops = oh.flops(tuple(legs), metas)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        oh.apply_dense(xd, terms)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
-            break
+
+    def timed(budget):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oh.apply_dense(xd, terms)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget or n >= 50:
+                return n, el
+
+    n, el = timed(budget_s)
+    n1, el1 = None, None
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        with threadpool_limits(limits=1):
+            n1, el1 = timed(budget_s)
     except Exception:
         cores = os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    shape = (f"at the shape of bottom node 0 (legs {dims[0]}x{dims[1]}x{dims[2]}, {len(metas)} terms "
+             f"with the node's factor pattern); algorithmic flops per application {flops:.3e}")
     return dict(value=flops * n / el / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
-                sample=(f"{n} oracle H_eff applications (dense NumPy float64 definition) at the "
-                        f"shape of bottom node 0 (legs {dims[0]}x{dims[1]}x{dims[2]}, "
-                        f"{len(metas)} terms with the node's factor pattern), {el:.1f} s; "
-                        f"algorithmic flops per application {flops:.3e}"))
+                cpu_model=model, host_cpus=os.cpu_count(),
+                sample=f"{n} oracle H_eff applications (dense NumPy float64 definition) {shape}, {el:.1f} s",
+                single_thread=None if n1 is None else dict(
+                    value=flops * n1 / el1 / 1e12, unit="TFLOP/s", cores=1,
+                    sample=f"{n1} applications on one BLAS thread, {el1:.1f} s"))
 
 
 def batched_workload(lib, torch, steps, warmup, cpu_budget, no_cpu):
@@ -599,7 +645,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--workload", choices=("sweep", "batched", "finite_density", "adjoint",
                                            "observables", "expansion"),
                     default="sweep")
@@ -648,19 +694,32 @@ def main():
 
     import tempfile
     tmpd = tempfile.mkdtemp(prefix="qedttn_bench_")
-    ckpt = os.path.join(tmpd, "fp64_converged.ckpt")
+    ckpt = os.path.join(tmpd, "fp64_final.ckpt")
     res, traj = {}, {}
+    own = os.path.join(tmpd, "own_final.ckpt")
     for name, dt in (("f64", lib.FP64), ("f32", lib.FP32), ("bf16", lib.BF16)):
-        log(f"== {name.upper()} GEMM path")
-        traj[name] = trajectory(lib, torch, dt, a.warmup, save=ckpt if name == "f64" else None)
-        res[name] = timed_from(lib, torch, dt, ckpt, a.steps)
+        log(f"== {name.upper()} GEMM path (refine {REFINE[name]})")
+        traj[name] = trajectory(lib, torch, dt, REFINE[name], a.warmup,
+                                save=ckpt if name == "f64" else own)
+        if name != "f64":
+            e64 = fp64_check(lib, own)
+            traj[name]["fp64_sweep_from_end_state"] = e64
+            traj[name]["end_state_dE_rel_vs_fp64_sweep"] = abs(traj[name]["energy"] - e64) / abs(e64)
+            os.remove(own)
+        res[name] = timed_from(lib, torch, dt, REFINE[name], ckpt, a.steps)
         r = res[name]
-        log(f"  from the FP64 state: {r['ms_per_step']:.1f} ms/sweep, {r['tflops']:.3f} TFLOP/s, "
-            f"GEMM {r['gemm_tflops']:.2f} TFLOP/s, E={r['energy']:.12f}")
+        log(f"  from the FP64 state: {r['ms_per_step']:.1f} ms/sweep, {r['matvecs_per_sweep']:.0f} "
+            f"matvecs/sweep, {r['tflops']:.3f} TFLOP/s, GEMM {r['gemm_tflops']:.2f} TFLOP/s, "
+            f"E={r['energy']:.12f}")
     os.remove(ckpt)
     os.rmdir(tmpd)
     r64, r32, r16 = res["f64"], res["f32"], res["bf16"]
+    t64 = traj["f64"]
     dE = abs(r32["energy"] - r64["energy"]) / abs(r64["energy"])
+    dE16 = abs(r16["energy"] - r64["energy"]) / abs(r64["energy"])
+    state = (f"the FP64 trajectory's state after {t64['sweeps']} sweeps from the seeded start "
+             + (f"(converged at sweep {t64['converged_sweep']}: |dE| <= 1e-8 |E| at the final penalty)"
+                if t64["converged_sweep"] is not None else "(not converged)"))
 
     # leg sectors of bottom node 0 for the CPU sample
     ctx = lib.Context(-1)
@@ -675,7 +734,12 @@ def main():
     if not a.no_cpu_baseline:
         log("== oracle CPU baseline (bounded sample)")
         cpu = cpu_baseline(legs, a.cpu_budget)
-        log(f"  {cpu['value']:.5f} TFLOP/s on {cpu['cores']} threads")
+        log(f"  {cpu['value']:.5f} TFLOP/s on {cpu['cores']} threads "
+            f"({cpu['single_thread']['value']:.5f} on 1 thread)")
+
+    def speed(k):
+        t = traj[k]["seconds_to_converge"]
+        return t64["seconds_to_converge"] / t if t and t64["seconds_to_converge"] else None
 
     achieved = r32["gemm_tflops"]
     line = {
@@ -695,32 +759,46 @@ def main():
             "workload": "TTN sweep, 2x2x2 open-lattice compact QED, free-flux boundary "
                         "(d=267 per site), Q=0, m=t=1, g^2=1 (g_e^2=1, g_m^2=8), chi=64",
             "lattice": "2x2x2", "bond_dim": CHI, "charge": 0, "seed": SEED,
-            "lanczos": "24 steps x <=4 cycles, tol max(1e-10, 1e-4 10^-s) in sweep s "
-                       "(FP32 floor 2e-6, BF16 floor 3.9e-3), "
-                       "FP64 Rayleigh quotient for the sweep energy (last update)",
-            "timed": "sweeps resumed from the converged FP64 state (checkpoint after the "
-                     "warm-up trajectory), after one untimed sweep",
+            "lanczos": "24 steps x <=4 cycles, tol max(1e-10, 1e-4 10^-s) in sweep s; "
+                       "FP32: Krylov recurrence in FP32 down to a 2e-6 floor, FP64 Rayleigh "
+                       "quotient for the sweep energy; BF16: FP64 residual correction (first "
+                       "product of every cycle in FP64, floor 1e-6)",
+            "timed": f"{a.steps} sweeps resumed from {state}, after one untimed sweep",
         },
         "sweep_s": r32["ms_per_step"] / 1e3,
         "energy": r32["energy"],
+        "matvecs_per_sweep": r32["matvecs_per_sweep"],
         "dE_rel_vs_fp64": dE,
         "dE_within_1e-8": bool(dE <= 1e-8),
         "fp64_path": {"ms_per_step": r64["ms_per_step"], "tflops": r64["tflops"],
-                      "energy": r64["energy"], "gemm_tflops": r64["gemm_tflops"]},
+                      "energy": r64["energy"], "gemm_tflops": r64["gemm_tflops"],
+                      "matvecs_per_sweep": r64["matvecs_per_sweep"]},
         "speedup_vs_fp64": {"sweep": r64["ms_per_step"] / r32["ms_per_step"],
-                            "to_converge": (traj["f64"]["seconds_to_converge"] /
-                                            traj["f32"]["seconds_to_converge"])
-                            if traj["f64"]["seconds_to_converge"] and traj["f32"]["seconds_to_converge"]
-                            else None},
+                            "to_converge": speed("f32")},
         "bf16_path": {"ms_per_step": r16["ms_per_step"], "tflops": r16["tflops"],
                       "energy": r16["energy"], "gemm_tflops": r16["gemm_tflops"],
-                      "dE_rel_vs_fp64": abs(r16["energy"] - r64["energy"]) / abs(r64["energy"]),
-                      "speedup_vs_fp64": r64["ms_per_step"] / r16["ms_per_step"]},
-        # independent trajectories from the seeded start: each path converges
-        # on its own (time to convergence); the truncated chi = 64 ansatz has
-        # several fixed points, and rounding can lead a trajectory to another
-        "trajectories": {k: {"energy": v["energy"], "converged_sweep": v["converged_sweep"],
-                             "seconds_to_converge": v["seconds_to_converge"]}
+                      "matvecs_per_sweep": r16["matvecs_per_sweep"],
+                      "dE_rel_vs_fp64": dE16, "dE_within_1e-8": bool(dE16 <= 1e-8),
+                      "speedup_vs_fp64": {"sweep": r64["ms_per_step"] / r16["ms_per_step"],
+                                          "to_converge": speed("bf16")},
+                      # at the converged state the FP64 residual check of each
+                      # update finds the vector converged: the BF16 GEMM rate
+                      # is taken over the BF16 trajectory instead
+                      "roofline": {"bound": "mfma", "kernel": "k_brgemm_bf16",
+                                   "over": "the BF16 trajectory from the seeded start",
+                                   "achieved": traj["bf16"]["gemm_tflops"], "peak": PEAK["bf16"],
+                                   "unit": "TFLOP/s",
+                                   "frac": traj["bf16"]["gemm_tflops"] / PEAK["bf16"]}},
+        # independent trajectories from the seeded start, each run until it
+        # converges (untimed; seconds from the library's per-sweep clock);
+        # the truncated chi = 64 ansatz has several fixed points, and rounding
+        # can lead a trajectory to another
+        # (end_state_dE_rel_vs_fp64_sweep: the path's final energy against one
+        # FP64 sweep resumed from its final state)
+        "trajectories": {k: {kk: v.get(kk) for kk in
+                             ("energy", "sweeps", "converged_sweep", "seconds_to_converge",
+                              "matvecs_to_converge", "gemm_tflops", "fp64_sweep_from_end_state",
+                              "end_state_dE_rel_vs_fp64_sweep")}
                          for k, v in traj.items()},
         "deltaL": r32["deltaL"],
         "roofline": {

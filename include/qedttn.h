@@ -184,11 +184,22 @@ int qed_set_lanczos_schedule(qed_ctx* ctx, double tol0, double factor);
  * QED_ERR_INVALID_ARG for alpha < 0 or not finite, delta < 0, chi_max < 0. */
 int qed_set_expansion(qed_ctx* ctx, int on, double alpha, int delta, int chi_max, uint64_t seed);
 
-/* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16).  refine != 0 makes the
- * reduced-precision paths compute the energy of each sweep (that of its
- * last node update, the root) as an FP64 Rayleigh quotient of the Ritz
- * vector, so that it carries an error second order in the eigenvector
- * error; the other updates of a sweep keep their Ritz values. */
+/* GEMM arithmetic (QED_FP64 / QED_FP32 / QED_BF16) of the reduced-
+ * precision paths and their refinement (Methods, "Tensor Networks", step
+ * (ii) run with lower-precision products):
+ *   refine = 0: Lanczos on the reduced-precision operator alone; each
+ *     update's Ritz value is its energy; cycles stop at the precision's
+ *     residual floor (FP32 2e-6, BF16 3.9e-3 relative);
+ *   refine = 1: as 0, and the energy of each sweep (that of its last node
+ *     update, the root) is an FP64 Rayleigh quotient of the Ritz vector,
+ *     with an error second order in the eigenvector error;
+ *   refine >= 2: FP64 residual correction at every update: the first
+ *     product of every Lanczos cycle is taken with the FP64 operator, so
+ *     the exact residual of the current vector enters the Krylov space and
+ *     ends the update once it is below the tolerance (floors FP32 1e-8,
+ *     BF16 1e-6 relative); the other products stay in reduced precision.
+ *     The energy is then an FP64 Rayleigh quotient as well.
+ * QED_ERR_INVALID_ARG for an unknown dtype or refine < 0. */
 int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine);
 
 /* Build the dressed-site bases, local operators, the term list, the tree

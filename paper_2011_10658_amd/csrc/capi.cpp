@@ -370,8 +370,9 @@ int qed_set_precision(qed_ctx* ctx, int gemm_dtype, int refine) {
     return guard(ctx, [&] {
         if (gemm_dtype != QED_FP64 && gemm_dtype != QED_FP32 && gemm_dtype != QED_BF16)
             fail(QED_ERR_INVALID_ARG, "unknown GEMM dtype");
+        if (refine < 0) fail(QED_ERR_INVALID_ARG, "refine must be >= 0");
         C(ctx).prm.dtype = gemm_dtype;
-        C(ctx).prm.refine = refine ? 1 : 0;
+        C(ctx).prm.refine = std::min(refine, 2);
         return QED_OK;
     });
 }

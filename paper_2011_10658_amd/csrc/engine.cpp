@@ -1634,7 +1634,7 @@ void LanczosWS::ensure(Dev* dev, int mm, int64_t nn) {
 }
 
 LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double* x, int64_t n, int m,
-                      int cycles, double tol, float* vc) {
+                      int cycles, double tol, float* vc, double exit_tol) {
     if (n <= 0) fail(QED_ERR_INVALID_ARG, "empty eigenproblem");
     m = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(m, 64), n));
     W.ensure(dev, m, n);
@@ -1674,6 +1674,23 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double*
                 launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
                 launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
             }
+            if (j == 0 && exit_tol > 0.0) {
+                // the exact residual of the current vector decides
+                double ab[2];
+                dev->download(&ab[0], al, sizeof(double));
+                dev->download(&ab[1], be, sizeof(double));
+                if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
+                    fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value");
+                if (ab[1] <= exit_tol * std::max(std::fabs(ab[0]), 1e-300)) {
+                    dev->check(hipMemcpyAsync(x, V, n * sizeof(double), hipMemcpyDeviceToDevice, s),
+                               "copy");
+                    R.theta = ab[0];
+                    R.resid = ab[1];
+                    R.cycles = cyc + 1;
+                    R.exact = true;
+                    return R;
+                }
+            }
             launch_lz_next(V, ld, j, w, be, n, st, s, vc);
         }
         launch_tridiag(al, be, W.sv->as<double>(), st, W.work->as<double>(), s);
@@ -1688,7 +1705,7 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double*
         R.cycles = cyc + 1;
         if (!std::isfinite(hs.theta) || !std::isfinite(hs.norm) || hs.norm == 0.0)
             fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value (zero or invalid start vector?)");
-        if (hs.resid <= tol * std::max(std::fabs(hs.theta), 1e-300)) break;
+        if (exit_tol <= 0.0 && hs.resid <= tol * std::max(std::fabs(hs.theta), 1e-300)) break;
     }
     return R;
 }

@@ -350,6 +350,7 @@ struct LanczosResult {
     double theta = 0.0, resid = 0.0;
     int cycles = 0;
     long long matvecs = 0;
+    bool exact = false;   // theta, resid: from the first step of a cycle (see exit_tol)
 };
 
 // Lowest eigenpair; x (device FP64, length n) is the start vector and
@@ -358,9 +359,15 @@ struct LanczosResult {
 // of v . y in part (the layout of launch_dots, one row) and then returns
 // true.  With vc set, each new basis vector is also written to vc in FP32,
 // and pre = true tells apply that vc already holds v.
+// exit_tol > 0 (for an apply whose first product of a cycle is exact):
+// after the first step of every cycle, alpha_0 = <x, H x> and beta_0 =
+// |H x - alpha_0 x| are those of the current vector itself; the run ends
+// there once beta_0 <= exit_tol |alpha_0| (x is left normalised, theta =
+// alpha_0, resid = beta_0, exact = true), and the estimate from the
+// tridiagonal at the end of a cycle does not end it.
 using LanczosApply = std::function<bool(const double*, double*, double*, bool)>;
 LanczosResult lanczos(Dev* dev, LanczosWS& ws, const LanczosApply& apply, double* x, int64_t n, int m,
-                      int cycles, double tol, float* vc = nullptr);
+                      int cycles, double tol, float* vc = nullptr, double exit_tol = 0.0);
 
 // ---- node-level effective Hamiltonian (C ABI object) ------------------
 struct Ctx;
@@ -449,7 +456,7 @@ struct Engine {
     bool isometric = false;   // every non-root node is an isometry toward the root
     double energy = 0.0;
     bool have_energy = false;
-    Arena ws;
+    Arena ws, ws64;   // plan workspaces (ws64: the FP64 plan of a reduced-precision update)
     LanczosWS lws;
     long long matvecs = 0;
     double flops = 0.0;

@@ -23,6 +23,11 @@ constexpr double LZ_TOL_FLOOR_FP32 = 2e-6;
 // matvec is accurate to a few u relative, and Krylov residuals stall near
 // that level; the floor is 2u
 constexpr double LZ_TOL_FLOOR_BF16 = 3.9e-3;
+// with the FP64 residual correction (refine >= 2) the residual is exact at
+// every restart; the floors are those that carry the energy to well below
+// 1e-8 relative (the energy error is second order in the residual)
+constexpr double LZ_TOL_FLOOR_FIX_FP32 = 1e-8;
+constexpr double LZ_TOL_FLOOR_FIX_BF16 = 1e-6;
 
 namespace {
 
@@ -867,9 +872,27 @@ double Engine::update(int n, double nu, bool refine_here) {
         yc = std::make_shared<DBuf>(dev, n_el * dtype_size(dtype));
     }
     void* w = ws.get(dev, std::max<int64_t>(1, plan.ws_elems) * dtype_size(dtype));
+    // reduced precision with the FP64 residual correction: the FP64 plan
+    // applies the first vector of every Lanczos cycle, so the exact residual
+    // of the current vector enters the Krylov space and ends the run once it
+    // is small enough; the other steps use the reduced-precision plan
+    const bool fix = dtype != QED_FP64 && P.refine >= 2;
+    Plan p64;
+    void* w64 = nullptr;
+    if (fix) {
+        p64 = plan_matvec(T.legs, T.tab, ht, QED_FP64);
+        p64.upload(dev);
+        w64 = ws64.get(dev, std::max<int64_t>(1, p64.ws_elems) * 8);
+    }
+    long long exact_mv = 0;
     auto apply = [&](const double* v, double* y, double* part, bool pre) {
         if (dtype == QED_FP64) {
             plan.run(dev, w, (void*)v, (void*)y);
+            return false;
+        }
+        if (fix && v == lws.V->as<double>()) {
+            p64.run(dev, w64, (void*)v, (void*)y);
+            ++exact_mv;
             return false;
         }
         if (!pre) to_compute(dtype, v, xc->p, n_el, dev->stream);
@@ -888,12 +911,14 @@ double Engine::update(int n, double nu, bool refine_here) {
     // the precision schedule of the sweeps (raised sweep by sweep)
     double tol_s = P.lz_tol;
     if (P.lz_tol0 > 0.0) tol_s = std::max(tol_s, P.lz_tol0 * std::pow(P.lz_factor, (double)sweeps_done));
-    const double tol = dtype == QED_FP64 ? tol_s
-                       : std::max(tol_s, dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32);
+    double tol = tol_s;
+    if (dtype != QED_FP64)
+        tol = std::max(tol_s, fix ? (dtype == QED_BF16 ? LZ_TOL_FLOOR_FIX_BF16 : LZ_TOL_FLOOR_FIX_FP32)
+                                  : (dtype == QED_BF16 ? LZ_TOL_FLOOR_BF16 : LZ_TOL_FLOOR_FP32));
     // the FP32 path takes each new basis vector's FP32 copy from the
     // Lanczos step that writes it
     LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol,
-                              dtype == QED_FP32 ? (float*)xc->p : nullptr);
+                              dtype == QED_FP32 ? (float*)xc->p : nullptr, fix ? tol : 0.0);
     // the Lanczos run ended in a synchronising download: every GEMM event
     // recorded so far has completed, and its pair can be reused
     if (ctx->prof.on) ctx->prof.harvest();
@@ -902,11 +927,13 @@ double Engine::update(int n, double nu, bool refine_here) {
     ctx->mv_count += R.matvecs;
     ctx->mv_flops += R.matvecs * plan.flops;
     double theta = R.theta;
-    if (dtype != QED_FP64 && P.refine && refine_here) {
+    if (dtype != QED_FP64 && P.refine && refine_here && !R.exact) {
         // FP64 Rayleigh quotient of the (normalised) Ritz vector
-        Plan p64 = plan_matvec(T.legs, T.tab, ht, QED_FP64);
-        p64.upload(dev);
-        void* w64 = ws.get(dev, std::max<int64_t>(1, p64.ws_elems) * 8);
+        if (!fix) {
+            p64 = plan_matvec(T.legs, T.tab, ht, QED_FP64);
+            p64.upload(dev);
+            w64 = ws64.get(dev, std::max<int64_t>(1, p64.ws_elems) * 8);
+        }
         DBuf y(dev, n_el * sizeof(double));
         p64.run(dev, w64, T.ptr(), y.p);
         DBuf part(dev, 512 * sizeof(double)), out(dev, sizeof(double));
@@ -922,8 +949,9 @@ double Engine::update(int n, double nu, bool refine_here) {
     have_energy = true;
     last_updated = n;
     if (std::getenv("QEDTTN_TRACE"))
-        std::fprintf(stderr, "[qedttn] update node %d size %lld terms %zu theta %.15g resid %.3g E %.15g\n",
-                     n, (long long)n_el, ht.size(), theta, R.resid, energy);
+        std::fprintf(stderr, "[qedttn] update node %d size %lld terms %zu theta %.15g resid %.3g%s E %.15g "
+                     "(%lld matvecs, %lld FP64)\n", n, (long long)n_el, ht.size(), theta, R.resid,
+                     R.exact ? " (exact)" : "", energy, R.matvecs, exact_mv);
     return energy;
 }
 

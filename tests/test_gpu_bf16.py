@@ -196,3 +196,63 @@ def test_bf16_sweeps_track_fp64(ctx):
         assert r["energy"] >= e64 - 1e-8 * abs(e64)
         assert r["energy"] - e64 <= 4 * U * abs(e64), (r["energy"], e64)
     ctx.set_precision(lib.FP64)
+
+
+def test_bf16_fp64_residual_correction(ctx):
+    """BF16 GEMMs with the FP64 residual correction (refine 2: the first
+    product of every Lanczos cycle with the FP64 operator, the rest in
+    BF16), 2x2x2 zero flux, chi 16.
+    (1) From the converged FP64 state the BF16 sweeps keep the FP64 energy
+    to 1e-8 relative.
+    (2) One sweep from a perturbed state (the converged state with 1e-3 of
+    its norm of noise on every node), where every update has real work to
+    do, lands within 1e-6 relative of the FP64 sweep from the same state:
+    each update stops at a residual of 1e-6 (the refine-2 floor) where the
+    FP64 path goes on to 1e-12, and away from a fixed point that difference
+    enters the energy at first order.
+    (3) An independent BF16 trajectory from the seeded start converges
+    (|dE| <= 1e-8 |E|), and its end state is a fixed point of the FP64
+    sweep: one FP64 sweep resumed from it changes the energy by less than
+    1e-8 relative."""
+    def setup(dtype, refine=1):
+        ctx.set_lattice(2, 2, 2, lib.BC_OPEN_ZERO_FLUX)
+        ctx.set_couplings(CPL_T, CPL_M, CPL_G2E, CPL_G2M)
+        ctx.set_charge_sector(0)
+        ctx.set_bond_dim(16)
+        ctx.set_penalty(10.0, 0, 0)
+        ctx.set_lanczos(24, 6, 1e-12)
+        ctx.set_precision(dtype, refine)
+        ctx.build_hamiltonian()
+
+    setup(lib.FP64)
+    ctx.init_state(7)
+    reps = ctx.sweep(16)
+    e64 = reps[-1]["energy"]
+    nn, _ = ctx.tree()
+    state = [ctx.get_node(n) for n in range(nn)]
+    # (1)
+    setup(lib.BF16, 2)
+    for n in range(nn):
+        ctx.set_node(n, state[n])
+    for r in ctx.sweep(2):
+        assert abs(r["energy"] - e64) <= 1e-8 * abs(e64), (r["energy"], e64)
+    # (2)
+    noisy = [s + 1e-3 * np.linalg.norm(s) / np.sqrt(s.size) * synth.normal(21, n, s.size)
+             for n, s in enumerate(state)]
+    energies = {}
+    for dtype, refine in ((lib.FP64, 1), (lib.BF16, 2)):
+        setup(dtype, refine)
+        for n in range(nn):
+            ctx.set_node(n, noisy[n])
+        energies[dtype] = ctx.sweep(1)[0]["energy"]
+    e_ref = energies[lib.FP64]
+    assert abs(energies[lib.BF16] - e_ref) <= 1e-6 * abs(e_ref), (energies, e_ref)
+    # (3)
+    setup(lib.BF16, 2)
+    ctx.init_state(7)
+    reps = ctx.sweep(24)
+    e16 = reps[-1]["energy"]
+    assert abs(e16 - reps[-2]["energy"]) <= 1e-8 * abs(e16)
+    ctx.set_precision(lib.FP64, 1)
+    e_chk = ctx.sweep(1)[0]["energy"]
+    assert abs(e_chk - e16) <= 1e-8 * abs(e16), (e16, e_chk)
