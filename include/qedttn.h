@@ -141,10 +141,17 @@ int qed_set_chemical_potential(qed_ctx* ctx, const double* mu);
 int qed_physical_line(double g2, double t, double* g2_e, double* g2_m);
 
 /* Link penalty nu sum (1 - delta_{2,L}) (Methods, penalty equation) and
- * its driven schedule: n_linear sweeps growing linearly from nu_max/20
- * to nu_max/4, then n_quadratic sweeps growing quadratically to nu_max,
- * then constant.  n_linear = n_quadratic = 0 keeps nu = nu_max.
- * adaptive must be 0 in this version. */
+ * its driven schedule (Methods, "Numerical Convergence"): n_linear sweeps
+ * growing linearly from nu_max/20 to nu_max/4, then n_quadratic sweeps
+ * growing quadratically to nu_max, then constant.  n_linear = n_quadratic
+ * = 0 keeps nu = nu_max.  adaptive != 0: the linear phase ends early,
+ * after the first linear sweep t >= 1 whose energy exceeds that of sweep
+ * t - 1 by more than 1e-10 |E_t| (the energy "rises slightly"), and the
+ * quadratic phase grows from the nu of that sweep to nu_max over
+ * n_quadratic sweeps.  The energies looked at are those of the sweeps run
+ * by this context since qed_init_state / qed_load_state (a resumed run
+ * starts a new history).  QED_ERR_INVALID_ARG for nu_max < 0 or negative
+ * counts. */
 int qed_set_penalty(qed_ctx* ctx, double nu_max, int n_linear, int n_quadratic, int adaptive);
 
 /* Total charge Q = N - L^3/2 (Results).  Q != 0 needs the free-flux

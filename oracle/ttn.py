@@ -805,6 +805,38 @@ def penalty_schedule(s, nu_max, n_lin=4, n_quad=4):
     return nu_max
 
 
+def adaptive_penalty_schedule(s, energies, nu_max, n_lin=4, n_quad=4, rise=1e-10):
+    """nu for sweep s under the adaptive switch (Methods, "Numerical
+    Convergence": the penalty grows linearly until the energy is seen to
+    rise slightly, then quadratically).  Reading: the linear phase has the
+    slope of `penalty_schedule`; it ends after the first linear sweep t >= 1
+    whose energy exceeds that of sweep t - 1 by more than rise |E_t| (or
+    after n_lin sweeps); the quadratic phase then runs over n_quad sweeps
+    from the nu of that last linear sweep to nu_max, and nu stays at nu_max
+    afterwards.  energies[t] is the energy reported by sweep t; only sweeps
+    before s are looked at."""
+    lo, mid = nu_max / 20.0, nu_max / 4.0
+
+    def linear(t):
+        if n_lin == 1:
+            return mid
+        return lo + (mid - lo) * t / (n_lin - 1)
+
+    switch = n_lin
+    for t in range(1, min(n_lin, len(energies), s)):
+        if energies[t] > energies[t - 1] + rise * abs(energies[t]):
+            switch = t + 1
+            break
+    if s < switch:
+        return linear(s)
+    start = linear(switch - 1) if switch > 0 else mid
+    k = s - switch
+    if k < n_quad:
+        u = (k + 1) / n_quad
+        return start + (nu_max - start) * u * u
+    return nu_max
+
+
 def default_nu_max(cpl):
     """nu_max = 10 max(|t|, |m|, g_e^2/2, g_m^2/2) (a reading of the
     'much larger than the couplings' condition)."""

@@ -61,12 +61,57 @@ def build(jobs=8, verbose=False):
     return OUT
 
 
+# Host-sanitizer build: AddressSanitizer + UndefinedBehaviorSanitizer on the
+# host code only (the device code is compiled as usual, unsanitised); the
+# CPU tests use it for host-only contexts (bases, tree, sector allocation,
+# block tables, argument checks).  Load it with the clang ASan runtime
+# preloaded.
+SAN_OUT = os.path.join(BUILD, "asan", "libqedttn_asan.so")
+SAN_FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined",
+             "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
+
+
+def asan_runtime():
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+def build_sanitized(jobs=8):
+    d = os.path.dirname(SAN_OUT)
+    os.makedirs(d, exist_ok=True)
+
+    def one(src):
+        obj = os.path.join(d, os.path.basename(src) + ".o")
+        cmd = [HIPCC, "-x", "hip"] + SAN_FLAGS + ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, sources()))
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", SAN_OUT + ".tmp"] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(SAN_OUT + ".tmp", SAN_OUT)
+    return SAN_OUT
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--sanitize", action="store_true",
+                    help="build the host-sanitizer library under _build/asan instead")
     a = ap.parse_args()
     try:
-        build(a.jobs, verbose=True)
+        if a.sanitize:
+            print("built", build_sanitized(a.jobs))
+        else:
+            build(a.jobs, verbose=True)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

@@ -303,11 +303,11 @@ int qed_set_penalty(qed_ctx* ctx, double nu_max, int n_linear, int n_quadratic, 
     return guard(ctx, [&] {
         if (!(nu_max >= 0.0) || n_linear < 0 || n_quadratic < 0)
             fail(QED_ERR_INVALID_ARG, "invalid penalty schedule");
-        if (adaptive) fail(QED_ERR_UNSUPPORTED, "the adaptive penalty switch is not implemented");
         Params& P = C(ctx).prm;
         P.nu_max = nu_max;
         P.n_lin = n_linear;
         P.n_quad = n_quadratic;
+        P.pen_adaptive = adaptive ? 1 : 0;
         return QED_OK;
     });
 }
@@ -612,6 +612,7 @@ int qed_load_state(qed_ctx* ctx, const char* path) {
         e.invalidate();
         e.isometric = iso != 0;
         e.sweeps_done = sweeps;
+        e.sweep_energies.assign(sweeps, NAN);
         e.have_energy = have_e != 0;
         e.energy = energy;
         return QED_OK;

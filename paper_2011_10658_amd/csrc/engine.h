@@ -426,6 +426,7 @@ struct Params {
     std::vector<double> mu;   // local chemical potentials, one per site (empty: none)
     double nu_max = 10.0;
     int n_lin = 0, n_quad = 0;
+    int pen_adaptive = 0;   // adaptive switch from linear to quadratic growth
     int Q = 0, chi = 16;
     int lz_steps = 30, lz_cycles = 1;
     double lz_tol = 0.0;
@@ -453,6 +454,7 @@ struct Engine {
     std::vector<std::vector<int>> tsites;    // per term: its sites
     int centre = -1;
     int sweeps_done = 0;
+    std::vector<double> sweep_energies;   // energy of every sweep of this run
     bool isometric = false;   // every non-root node is an isometry toward the root
     double energy = 0.0;
     bool have_energy = false;

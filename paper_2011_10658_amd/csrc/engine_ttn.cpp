@@ -95,6 +95,7 @@ void Engine::build(Ctx* c) {
     dn.assign(tree.nlinks(), EnvD());
     centre = -1;
     sweeps_done = 0;
+    sweep_energies.clear();
     have_energy = false;
 }
 
@@ -118,19 +119,38 @@ void Engine::init_nodes(uint64_t seed) {
         T.d = std::make_shared<DBuf>(dev, sz * sizeof(double));
         dev->upload(T.d->p, h.data(), sz * sizeof(double));
     }
+    sweep_energies.assign(sweeps_done, NAN);
     invalidate();
 }
 
+// Driven penalty (Methods, "Numerical Convergence"): linear growth from
+// nu_max/20 to nu_max/4 over n_lin sweeps, quadratic growth to nu_max over
+// n_quad sweeps, then constant.  With the adaptive switch the linear phase
+// ends early, after the first linear sweep t >= 1 whose energy rose above
+// that of sweep t - 1 (by more than 1e-10 |E_t|), and the quadratic phase
+// starts from the nu of that sweep.
 double Engine::nu_for(int s) const {
     const Params& P = ctx->prm;
     const double numax = P.nu_max, lo = numax / 20.0, mid = numax / 4.0;
-    if (s < P.n_lin) {
+    auto linear = [&](int t) {
         if (P.n_lin == 1) return mid;
-        return lo + (mid - lo) * s / (P.n_lin - 1);
+        return lo + (mid - lo) * t / (P.n_lin - 1);
+    };
+    int sw = P.n_lin;
+    if (P.pen_adaptive) {
+        const int nh = std::min<int>({P.n_lin, (int)sweep_energies.size(), s});
+        for (int t = 1; t < nh; ++t)
+            if (sweep_energies[t] > sweep_energies[t - 1] + 1e-10 * std::fabs(sweep_energies[t])) {
+                sw = t + 1;
+                break;
+            }
     }
-    if (s < P.n_lin + P.n_quad) {
-        double u = (double)(s - P.n_lin + 1) / P.n_quad;
-        return mid + (numax - mid) * u * u;
+    if (s < sw) return linear(s);
+    const double start = sw > 0 ? linear(sw - 1) : mid;
+    const int k = s - sw;
+    if (k < P.n_quad) {
+        const double u = (double)(k + 1) / P.n_quad;
+        return start + (numax - start) * u * u;
     }
     return numax;
 }
@@ -987,6 +1007,10 @@ void Engine::sweep(int s_index, qed_sweep_report* rep) {
     dev->sync();
     auto t1 = std::chrono::steady_clock::now();
     ++sweeps_done;
+    // energy history by sweep index (entries of sweeps run before a state
+    // was set are NaN: they never count as a rise)
+    if ((int)sweep_energies.size() < sweeps_done) sweep_energies.resize(sweeps_done, NAN);
+    sweep_energies[sweeps_done - 1] = energy;
     if (rep) {
         std::vector<double> e7;
         observables(e7);

@@ -13,7 +13,9 @@ import weakref
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libqedttn.so")
+# QEDTTN_LIBRARY names another build of the same library (the host-sanitizer
+# build used by the CPU tests); the in-tree build otherwise
+LIBPATH = os.environ.get("QEDTTN_LIBRARY") or os.path.join(HERE, "libqedttn.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR = {-1: "INVALID_ARG", -2: "BAD_STATE", -3: "OOM", -4: "HIP", -6: "NONFINITE",

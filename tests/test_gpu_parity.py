@@ -613,3 +613,36 @@ def test_bench_config_sweeps_vs_oracle(ctx, dtype, plan, monkeypatch):
     assert abs(ob["Q"]) < 1e-10 and abs(G["Qexp"]) < 1e-10
     assert abs(ob["rho"] - G["rho"]) < tol_o
     ctx.set_precision(lib.FP64)
+
+
+@pytest.mark.parametrize("adaptive", [0, 1])
+def test_penalty_schedule_adaptive_switch(ctx, adaptive):
+    """The library's driven penalty follows the oracle's schedule: fixed, or
+    with the adaptive switch decided on the library's own sweep energies.
+    The lattice is the benchmark's (2x2x2 free flux, g^2 = 1) at chi 8 with a
+    weak penalty (nu_max = 2 over 12 linear + 3 quadratic sweeps): the
+    truncated state keeps link defects (delta_L ~ 1e-2), so raising nu lifts
+    its energy within the linear phase and the adaptive run switches to the
+    quadratic growth early."""
+    from oracle.ttn import adaptive_penalty_schedule, penalty_schedule
+    nu_max, n_lin, n_quad, nsw = 2.0, 12, 3, 16
+    g2e, g2m = lib.physical_line(1.0, 1.0)
+    ctx.set_lattice(2, 2, 2, lib.BC_OPEN_FREE_FLUX)
+    ctx.set_couplings(1.0, 1.0, g2e, g2m)
+    ctx.set_charge_sector(0)
+    ctx.set_bond_dim(8)
+    ctx.set_penalty(nu_max, n_lin, n_quad, adaptive)
+    ctx.set_lanczos(20, 3, 1e-12)
+    ctx.set_precision(lib.FP64)
+    ctx.build_hamiltonian()
+    ctx.init_state(3)
+    reps = ctx.sweep(nsw)
+    E = [r["energy"] for r in reps]
+    for s, r in enumerate(reps):
+        want = adaptive_penalty_schedule(s, E[:s], nu_max, n_lin, n_quad) if adaptive \
+            else penalty_schedule(s, nu_max, n_lin, n_quad)
+        assert abs(r["nu"] - want) <= 1e-12 * nu_max, (s, r["nu"], want)
+    fixed = [penalty_schedule(s, nu_max, n_lin, n_quad) for s in range(nsw)]
+    switched = any(abs(r["nu"] - f) > 1e-9 for r, f in zip(reps, fixed))
+    assert switched == bool(adaptive), (E, [r["nu"] for r in reps])
+    ctx.set_penalty(8.0, 0, 0)

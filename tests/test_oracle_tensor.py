@@ -521,3 +521,28 @@ def test_expansion_respects_chi_max_and_bound():
             if e >= lat.nsites:
                 assert sum(n for _, n in leg) <= 3
     assert E >= e0 - 1e-10
+
+
+def test_adaptive_penalty_schedule_hand_values():
+    """The adaptive switch of the driven penalty (Methods, "Numerical
+    Convergence"), by hand: nu_max = 40, 4 linear + 4 quadratic sweeps, so
+    the linear phase runs 2, 14/3, 22/3, 10 (slope 8/3).  Sweep 2's energy
+    rises above sweep 1's: the quadratic phase starts at sweep 3 from 22/3
+    and reaches 40 in four sweeps: 22/3 + (40 - 22/3) u^2, u = 1/4 .. 1."""
+    from oracle.ttn import adaptive_penalty_schedule
+    E = [-10.0, -12.0, -11.5, -11.0, -10.0, -9.0, -8.0, -7.0]
+    nu = [adaptive_penalty_schedule(s, E[:s], 40.0, 4, 4) for s in range(9)]
+    start = 22.0 / 3.0
+    want = [2.0, 2.0 + 8.0 / 3.0, start] + [start + (40.0 - start) * (k / 4.0) ** 2 for k in (1, 2, 3, 4)] \
+        + [40.0, 40.0]
+    assert np.allclose(nu, want, rtol=0, atol=1e-12), (nu, want)
+    assert abs(nu[3] - 9.375) < 1e-12 and abs(nu[4] - 15.5) < 1e-12
+    # no rise (or one below 1e-10 |E|): the fixed schedule
+    E2 = [-10.0, -12.0, -12.0 + 1e-12, -13.0, -14.0, -15.0, -16.0, -17.0]
+    for s in range(10):
+        assert adaptive_penalty_schedule(s, E2[:s], 40.0, 4, 4) == penalty_schedule(s, 40.0, 4, 4)
+    # a rise at the first comparison: quadratic from sweep 2, from nu(1)
+    E3 = [-10.0, -9.0]
+    assert adaptive_penalty_schedule(1, E3[:1], 40.0, 4, 4) == 2.0 + 8.0 / 3.0
+    s1 = 2.0 + 8.0 / 3.0
+    assert abs(adaptive_penalty_schedule(2, E3, 40.0, 4, 4) - (s1 + (40.0 - s1) / 16.0)) < 1e-12
