@@ -1496,6 +1496,165 @@ void split_for_occupancy(Plan& P, int s, int64_t target_tiles) {
     }
 }
 
+// Shifted CholeskyQR3 of every task's column-major matrix (Methods,
+// "Tensor Networks", step (iii): the isometrisation of a node is a QR per
+// sector; the method is that of Fukaya, Kannan, Nakatsukasa, Yamamoto and
+// Yanagisawa, SIAM J. Sci. Comput. 42 (2020)).  Pass p: G = A^T A (block
+// GEMM, split-K over the long rows), G + s_p I = R_p^T R_p and R_p^-1 (one
+// workgroup per sector), A := A R_p^-1 (block GEMM).  The first pass is
+// shifted by s_0 = 11 (m n + n (n + 1)) u |A|_F^2, which keeps it positive
+// definite for condition numbers up to ~1/u (the downward moves of a sweep
+// meet Schmidt spectra that decay to zero); it leaves a condition number of
+// at most ~1e8, and two plain passes then give columns orthonormal to
+// rounding.  R = R_2 R_1 R_0 has a positive diagonal, so for full-rank
+// sectors Q and R equal those of the Householder route.  Returns false,
+// with the matrices unchanged, when a sector is wider than CHOL_MAX_COLS or
+// a pivot still fails (the caller then takes the Householder route).
+bool cholqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
+    if (tasks.empty()) return true;
+    int maxn = 0;
+    int64_t tot = 0, gtot = 0;
+    for (const QRTask& t : tasks) {
+        if (t.n > CHOL_MAX_COLS || t.m < t.n) return false;
+        maxn = std::max(maxn, t.n);
+        tot += t.m * t.n;
+        gtot += (int64_t)t.n * t.n;
+    }
+    const int nt = (int)tasks.size();
+    DBuf w1(dev, tot * sizeof(double)), w2(dev, tot * sizeof(double));
+    DBuf gram(dev, gtot * sizeof(double));
+    DBuf rinv(dev, gtot * sizeof(double));
+    DBuf ra(dev, gtot * sizeof(double)), rb(dev, gtot * sizeof(double));
+    DBuf status(dev, 3 * nt * sizeof(int));
+    std::vector<int64_t> goff(nt), woff(nt);
+    {
+        int64_t g = 0, w = 0;
+        for (int i = 0; i < nt; ++i) {
+            goff[i] = g;
+            woff[i] = w;
+            g += (int64_t)tasks[i].n * tasks[i].n;
+            w += tasks[i].m * tasks[i].n;
+        }
+    }
+    auto absref = [](const void* p) { return GRef{p, 0, TAG_ABS, 0}; };
+    using In = std::function<const double*(int)>;
+    using Out = std::function<double*(int)>;
+    // G_i = A_i^T A_i for the matrices at a(i)
+    auto gram_pass = [&](const In& a) {
+        Plan P;
+        P.dtype = QED_FP64;
+        P.jobs.emplace_back();
+        P.prods.emplace_back();
+        P.stage_flops.push_back(0.0);
+        for (int i = 0; i < nt; ++i) {
+            const QRTask& t = tasks[i];
+            GProd q{};
+            q.A = absref(a(i));
+            q.lda = (int)t.m;
+            q.tA = 0;
+            q.B = absref(a(i));
+            q.ldb = (int)t.m;
+            q.tB = 1;
+            q.K = (int)t.m;
+            q.alpha = 1.0;
+            q.nred = 1;
+            GJob j{};
+            j.C = absref(gram.as<double>() + goff[i]);
+            j.M = t.n;
+            j.N = t.n;
+            j.ldc = t.n;
+            j.batch = 1;
+            j.p0 = (int)P.prods[0].size();
+            P.prods[0].push_back(q);
+            j.p1 = j.p0 + 1;
+            P.jobs[0].push_back(j);
+        }
+        split_long_reductions(P, 0);
+        P.upload(dev);
+        DBuf ws(dev, std::max<int64_t>(1, P.ws_elems) * sizeof(double));
+        P.run(dev, ws.p, nullptr, nullptr);
+    };
+    // out_i = in_i R_i^-1 (column-major m x n, as (R^-T)(A^T) row-major)
+    auto apply_pass = [&](const In& in, const Out& out) {
+        Plan P;
+        P.dtype = QED_FP64;
+        P.jobs.emplace_back();
+        P.prods.emplace_back();
+        P.stage_flops.push_back(0.0);
+        for (int i = 0; i < nt; ++i) {
+            const QRTask& t = tasks[i];
+            GProd q{};
+            q.A = absref(rinv.as<double>() + goff[i]);
+            q.lda = t.n;
+            q.tA = 1;
+            q.B = absref(in(i));
+            q.ldb = (int)t.m;
+            q.tB = 0;
+            q.K = t.n;
+            q.alpha = 1.0;
+            q.nred = 1;
+            GJob j{};
+            j.C = absref(out(i));
+            j.M = t.n;
+            j.N = (int)t.m;
+            j.ldc = (int)t.m;
+            j.batch = 1;
+            j.p0 = (int)P.prods[0].size();
+            P.prods[0].push_back(q);
+            j.p1 = j.p0 + 1;
+            P.jobs[0].push_back(j);
+        }
+        P.upload(dev);
+        P.run(dev, nullptr, nullptr, nullptr);
+    };
+    // Cholesky of pass p; the running R goes ra (pass 0) -> rb (pass 1) ->
+    // the caller's R (pass 2)
+    auto chol_pass = [&](int pass) {
+        std::vector<CholMat> cm(nt);
+        for (int i = 0; i < nt; ++i) {
+            const QRTask& t = tasks[i];
+            CholMat& c = cm[i];
+            c.g = gram.as<double>() + goff[i];
+            c.rinv = rinv.as<double>() + goff[i];
+            c.n = t.n;
+            c.status = status.as<int>() + pass * nt + i;
+            c.shift = pass == 0 ? 11.0 * ((double)t.m * t.n + (double)t.n * (t.n + 1)) * 0x1p-53 : 0.0;
+            c.rprev = pass == 0 ? nullptr : (pass == 1 ? ra : rb).as<double>() + goff[i];
+            if (pass < 2) {
+                c.rout = (pass == 0 ? ra : rb).as<double>() + goff[i];
+                c.rrs = t.n;
+                c.rcs = 1;
+            } else {
+                c.rout = t.R;
+                c.rrs = t.rrs;
+                c.rcs = t.rcs;
+            }
+        }
+        DBuf d(dev, nt * sizeof(CholMat));
+        dev->upload(d.p, cm.data(), nt * sizeof(CholMat));
+        launch_chol_inv(d.as<CholMat>(), nt, maxn, dev->stream);
+        dev->check(hipGetLastError(), "cholesky launch");
+    };
+    const In a0 = [&](int i) { return (const double*)tasks[i].M; };
+    const In in1 = [&](int i) { return (const double*)(w1.as<double>() + woff[i]); };
+    const In in2 = [&](int i) { return (const double*)(w2.as<double>() + woff[i]); };
+    gram_pass(a0);
+    chol_pass(0);
+    apply_pass(a0, [&](int i) { return w1.as<double>() + woff[i]; });
+    gram_pass(in1);
+    chol_pass(1);
+    apply_pass(in1, [&](int i) { return w2.as<double>() + woff[i]; });
+    gram_pass(in2);
+    chol_pass(2);
+    // the caller's matrices are written only once every pivot test passed
+    std::vector<int> st(3 * nt);
+    dev->download(st.data(), status.p, 3 * nt * sizeof(int));
+    for (int v : st)
+        if (v) return false;
+    apply_pass(in2, [&](int i) { return tasks[i].M; });
+    return true;
+}
+
 void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     if (tasks.empty()) return;
     // level 1: every direct matrix and every row chunk of every tall one

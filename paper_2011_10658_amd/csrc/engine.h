@@ -77,6 +77,8 @@ void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
 void launch_jacobi_svd(const SvdMat*, int nmats, hipStream_t);
+// Cholesky of every sector's Gram matrix, R^-1 and the running R
+void launch_chol_inv(const CholMat*, int nmats, int maxn, hipStream_t);
 void launch_axpy(double* y, const double* x, double f, int64_t n, hipStream_t);
 
 void seg_dots(const double*, int64_t, int, const double*, const SegChunk*, int, const int*, int,
@@ -336,6 +338,9 @@ struct QRTask {
     int64_t rrs, rcs;
 };
 void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks);
+// CholeskyQR2 of the same tasks: false (matrices untouched) when a sector
+// is too wide or rank deficient, to be done by tsqr_multi instead
+bool cholqr_multi(Dev* dev, const std::vector<QRTask>& tasks);
 void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t rcs);
 
 // ---- Lanczos -----------------------------------------------------------

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #include "engine.h"
 
@@ -158,6 +159,18 @@ double Engine::nu_for(int s) const {
 // ---------------------------------------------------------------------
 // QR of node n toward leg `which`; returns R (sector-preserving op)
 // ---------------------------------------------------------------------
+// QEDTTN_QR=cholesky takes the shifted CholeskyQR3 route for the centre
+// moves, where it applies; by default every move takes the Householder
+// route.  On the benchmark lattice the sector matrices of the bottom nodes
+// toward their parent become numerically rank deficient as the state
+// converges (Schmidt weights far below 1e-8), where the Cholesky route has
+// to hand over to Householder after its passes: measured 103 against
+// 99 ms per FP32 sweep, so it is not the default.
+static bool use_cholqr() {
+    const char* v = std::getenv("QEDTTN_QR");
+    return v && !std::strcmp(v, "cholesky");
+}
+
 OpP Engine::qr_toward(int n, int which) {
     Dev* dev = &ctx->dev;
     TensorD& T = nodes[n];
@@ -198,12 +211,18 @@ OpP Engine::qr_toward(int n, int which) {
     dev->upload(dpb.p, pb.data(), pb.size() * sizeof(PackBlk));
     DBuf packed(dev, tot * sizeof(double));
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 0, dev->stream);
-    // every sector of the leg in one batched (level-synchronous) QR
+    // every sector of the leg at once: CholeskyQR2 on the block GEMM, or,
+    // for sectors it cannot take (too wide, rank deficient), the batched
+    // level-synchronous Householder QR
     std::vector<QRTask> tasks;
     for (int s = 0; s < ns; ++s)
         tasks.push_back(QRTask{packed.as<double>() + mat[s], rows[s], L.n[s],
                                (double*)R->d64->p + R->lay.off[s], L.n[s], 1});
-    tsqr_multi(dev, tasks);
+    if (!use_cholqr() || !cholqr_multi(dev, tasks)) {
+        if (use_cholqr() && std::getenv("QEDTTN_TRACE"))
+            std::fprintf(stderr, "[qedttn] QR of node %d toward leg %d: Householder route\n", n, which);
+        tsqr_multi(dev, tasks);
+    }
     launch_pack(dpb.as<PackBlk>(), (int)pb.size(), maxsize, T.ptr(), packed.as<double>(), 1, dev->stream);
     dev->check(hipGetLastError(), "qr launch");
     return R;

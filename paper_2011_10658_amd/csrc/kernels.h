@@ -158,6 +158,26 @@ struct QRMat {
     int rows, cols;
 };
 
+// One sector of a CholeskyQR pass: G (n x n, row-major) = A^T A of the
+// sector matrix; the kernel factors G + shift trace(G) I = R^T R (R upper,
+// positive diagonal), writes R^-1 (row-major n x n) to rinv and, when
+// rprev is set, the product R rprev (row-major n x n) to rout at
+// rout[i * rrs + j * rcs]; otherwise R itself.  status = 1 when a pivot
+// fell below 1e-12 of the largest diagonal entry (not positive definite to
+// working precision), else 0.
+struct CholMat {
+    const double* g;
+    double* rinv;
+    const double* rprev;
+    double* rout;
+    int* status;
+    int64_t rrs, rcs;
+    double shift;
+    int n;
+    int pad;
+};
+constexpr int CHOL_MAX_COLS = 96;
+
 // A chunk of a segmented vector (never straddles a segment boundary).
 struct SegChunk {
     int seg;

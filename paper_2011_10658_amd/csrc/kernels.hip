@@ -1559,6 +1559,98 @@ __global__ __launch_bounds__(256) void k_householder_qr_wide(const QRMat* __rest
     }
 }
 
+// ---------------------------------------------------------------------
+// CholeskyQR: factor of the Gram matrix, its inverse, the running R
+// ---------------------------------------------------------------------
+// One workgroup per sector.  G (+ the shift) is copied to LDS and factored
+// in place column by column (right-looking: row j of R is formed from its
+// pivot, the trailing upper triangle takes one rank-1 update); the pivot
+// test uses the largest diagonal entry.  R^-1 is formed in LDS by back
+// substitution, one column per thread (each column's triangular solve is
+// independent), and written out once complete.
+__global__ __launch_bounds__(256) void k_chol_inv(const CholMat* __restrict__ mats) {
+    extern __shared__ double sh[];
+    const CholMat M = mats[blockIdx.x];
+    const int n = M.n, ld = n + 1;
+    double* G = sh;                    // n x ld: G, then R in its upper triangle
+    double* X = sh + n * ld;           // n x ld: R^-1
+    __shared__ double gmax, sft;
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n * n; i += blockDim.x) G[(i / n) * ld + i % n] = M.g[i];
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0, tr = 0.0;
+        for (int i = 0; i < n; ++i) {
+            m = fmax(m, G[i * ld + i]);
+            tr += G[i * ld + i];
+        }
+        sft = M.shift * tr;
+        gmax = m + sft;
+        bad = 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) G[i * ld + i] += sft;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double d = G[j * ld + j];
+        if (!(d > 1e-12 * gmax)) {
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const double r = sqrt(d);
+        __syncthreads();
+        for (int k = j + tid; k < n; k += blockDim.x) G[j * ld + k] = (k == j) ? r : G[j * ld + k] / r;
+        __syncthreads();
+        const int t = n - j - 1;
+        for (int e = tid; e < t * t; e += blockDim.x) {
+            const int i = j + 1 + e / t, k = j + 1 + e % t;
+            if (k >= i) G[i * ld + k] -= G[j * ld + i] * G[j * ld + k];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) *M.status = 1;
+        return;
+    }
+    if (tid == 0) *M.status = 0;
+    // R^-1: column c solves R x = e_c (x[i] = 0 for i > c)
+    for (int c = tid; c < n; c += blockDim.x) {
+        for (int i = n - 1; i > c; --i) X[i * ld + c] = 0.0;
+        X[c * ld + c] = 1.0 / G[c * ld + c];
+        for (int i = c - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (int k = i + 1; k <= c; ++k) acc += G[i * ld + k] * X[k * ld + c];
+            X[i * ld + c] = -acc / G[i * ld + i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) M.rinv[e] = X[(e / n) * ld + e % n];
+    // the running R: R rprev (both upper triangular), or R itself
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        double v = 0.0;
+        if (j >= i) {
+            if (M.rprev) {
+                for (int k = i; k <= j; ++k) v += G[i * ld + k] * M.rprev[(int64_t)k * n + j];
+            } else {
+                v = G[i * ld + j];
+            }
+        }
+        M.rout[i * M.rrs + j * M.rcs] = v;
+    }
+}
+
+void launch_chol_inv(const CholMat* mats, int nmats, int maxn, hipStream_t s) {
+    if (nmats <= 0) return;
+    const size_t lds = (size_t)2 * maxn * (maxn + 1) * sizeof(double);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL(k_chol_inv, dim3(nmats), dim3(256), lds, s, mats);
+}
+
 void launch_qr(const QRMat* mats, int nmats, int64_t maxrows, int maxcols, hipStream_t s) {
     if (nmats <= 0) return;
     if (maxrows <= QR_ROWS && maxcols <= QR_COLS) {

@@ -646,3 +646,44 @@ def test_penalty_schedule_adaptive_switch(ctx, adaptive):
     switched = any(abs(r["nu"] - f) > 1e-9 for r, f in zip(reps, fixed))
     assert switched == bool(adaptive), (E, [r["nu"] for r in reps])
     ctx.set_penalty(8.0, 0, 0)
+
+
+def _parent_isometry_error(ctx, n):
+    l, r, p = [ctx.leg_sectors(e) for e in ctx.node_links(n)]
+    triples, offs = oblocks.block_table(l, r, p)
+    x = ctx.get_node(n)
+    gram = {ip: np.zeros((p[ip][1], p[ip][1])) for ip in range(len(p))}
+    for b, (il, ir, ip) in enumerate(triples):
+        B = x[offs[b]:offs[b + 1]].reshape(l[il][1] * r[ir][1], p[ip][1])
+        gram[ip] += B.T @ B
+    return max(np.abs(G - np.eye(G.shape[0])).max() for G in gram.values())
+
+
+@pytest.mark.parametrize("qr", ["cholesky", "householder"])
+def test_qr_rank_deficient_sector(ctx, qr, monkeypatch):
+    """A node whose sector matrices toward the parent leg are rank deficient
+    (in every block, column 1 of each parent sector copied from column 0):
+    isometrising the tree (the first centre move) must still leave
+    orthonormal columns.  The Cholesky route (QEDTTN_QR=cholesky) detects
+    the failed pivot and hands those sectors to the Householder QR;
+    full-rank nodes take the Cholesky route and come out orthonormal to
+    1e-12 as well."""
+    monkeypatch.setenv("QEDTTN_QR", qr)
+    setup_ctx(ctx, (2, 2, 2), 0, 0, 16, CPL, 10.0, steps=8)
+    ctx.init_state(5)
+    l, r, p = [ctx.leg_sectors(e) for e in ctx.node_links(0)]
+    triples, offs = oblocks.block_table(l, r, p)
+    x = ctx.get_node(0)
+    touched = 0
+    for b, (il, ir, ip) in enumerate(triples):
+        if p[ip][1] < 2:
+            continue
+        B = x[offs[b]:offs[b + 1]].reshape(l[il][1] * r[ir][1], p[ip][1])
+        B[:, 1] = B[:, 0]
+        touched += 1
+    assert touched > 0
+    ctx.set_node(0, x)
+    ctx.observables()            # isometrises every node toward the root
+    nn, _ = ctx.tree()
+    for n in range(nn - 1):
+        assert _parent_isometry_error(ctx, n) < 1e-12, n
