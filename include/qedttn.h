@@ -485,8 +485,10 @@ int qed_heff_batch_lanczos(qed_heff_batch* b, double* x_inout, int steps, double
 /* Algorithmic flops and bytes of one batched matvec. */
 int qed_heff_batch_flops(qed_heff_batch* b, double* flops, double* bytes);
 
-/* Autotuner: from now on, node-level and batched H_eff objects time the
- * three workgroup tile shapes of every GEMM stage and keep the fastest.
+/* Autotuner: from now on, node-level and batched H_eff objects time every
+ * (workgroup tile shape, operand pipeline) pair each GEMM stage allows -
+ * three tile shapes; the register-staged loop, the flat product pipeline
+ * and, for FP32, the LDS-DMA ring - and keep the fastest.
  * Decisions are cached per stage signature and, if cache_path is not
  * NULL, loaded from and saved to that text file.  cache_path = "" turns
  * tuning off. */

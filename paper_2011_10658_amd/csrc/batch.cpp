@@ -1,9 +1,9 @@
 // Batched node updates: many independent tree nodes of uneven shape share
 // one grouped block-GEMM launch per contraction stage and one segmented
 // FP64 Lanczos (one recurrence per node).  A whole Lanczos cycle is
-// captured once into a HIP graph and replayed.  The GEMM tile shape of
-// every stage can be chosen by timing (autotuner) instead of the padding
-// heuristic.
+// captured once into a HIP graph and replayed.  The GEMM tile shape and
+// operand pipeline of every stage can be chosen by timing (autotuner)
+// instead of the padding and reduction-length heuristics.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -90,7 +90,8 @@ void SegLanczos::cycle(const std::function<void(const double*, double*)>& apply,
 // autotuner
 // ---------------------------------------------------------------------
 static std::string stage_key(const Plan& P, size_t s) {
-    // shape signature: dtype, job count and the sums of padded extents
+    // shape signature: dtype, job count and the sums of extents (the
+    // leading "p" marks entries that store tile shape + 4 pipeline)
     std::ostringstream o;
     int64_t jm = 0, jn = 0, jk = 0, jb = 0;
     for (const GJob& J : P.jobs[s]) {
@@ -99,7 +100,7 @@ static std::string stage_key(const Plan& P, size_t s) {
         jb += J.batch;
         for (int p = J.p0; p < J.p1; ++p) jk += (int64_t)P.prods[s][p].K * P.prods[s][p].nred;
     }
-    o << P.dtype << ":" << P.jobs[s].size() << ":" << jm << ":" << jn << ":" << jk << ":" << jb;
+    o << "p" << P.dtype << ":" << P.jobs[s].size() << ":" << jm << ":" << jn << ":" << jk << ":" << jb;
     return o.str();
 }
 
@@ -125,31 +126,41 @@ void Tuner::tune(Dev* dev, Plan& P, void* ws, void* x, void* y) {
         const std::string key = stage_key(P, s);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            P.set_shape(dev, (int)s, it->second);
-            continue;
-        }
-        int best = P.shape[s];
-        float best_ms = -1.0f;
-        for (int sh = 0; sh < GEMM_NSHAPES; ++sh) {
-            P.set_shape(dev, (int)s, sh);
-            hipEvent_t a, b;
-            dev->check(hipEventCreate(&a), "event");
-            dev->check(hipEventCreate(&b), "event");
-            P.run_stage(dev, (int)s, ws, x, y);   // warm-up
-            dev->check(hipEventRecord(a, dev->stream), "event");
-            for (int r = 0; r < 3; ++r) P.run_stage(dev, (int)s, ws, x, y);
-            dev->check(hipEventRecord(b, dev->stream), "event");
-            dev->sync();
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, a, b);
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            if (best_ms < 0 || ms < best_ms) {
-                best_ms = ms;
-                best = sh;
+            const int sh = it->second % 4, pp = it->second / 4;
+            if (sh < GEMM_NSHAPES && P.pipe_valid(s, pp, sh)) {
+                P.set_shape(dev, (int)s, sh);
+                P.pipe[s] = (char)pp;
+                continue;
             }
         }
-        P.set_shape(dev, (int)s, best);
+        // every (tile shape, pipeline) pair the stage allows; BF16 stages
+        // have one pipeline
+        int best = P.shape[s] + 4 * P.pipe[s];
+        float best_ms = -1.0f;
+        for (int sh = 0; sh < GEMM_NSHAPES; ++sh)
+            for (int pp = 0; pp < (P.dtype == QED_BF16 ? 1 : GEMM_NPIPES); ++pp) {
+                if (!P.pipe_valid(s, pp, sh)) continue;
+                P.set_shape(dev, (int)s, sh);
+                P.pipe[s] = (char)pp;
+                hipEvent_t a, b;
+                dev->check(hipEventCreate(&a), "event");
+                dev->check(hipEventCreate(&b), "event");
+                P.run_stage(dev, (int)s, ws, x, y);   // warm-up
+                dev->check(hipEventRecord(a, dev->stream), "event");
+                for (int r = 0; r < 3; ++r) P.run_stage(dev, (int)s, ws, x, y);
+                dev->check(hipEventRecord(b, dev->stream), "event");
+                dev->sync();
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                if (best_ms < 0 || ms < best_ms) {
+                    best_ms = ms;
+                    best = sh + 4 * pp;
+                }
+            }
+        P.set_shape(dev, (int)s, best % 4);
+        P.pipe[s] = (char)(best / 4);
         cache[key] = best;
         changed = true;
     }

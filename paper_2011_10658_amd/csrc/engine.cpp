@@ -445,15 +445,44 @@ static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
     return tiles;
 }
 
-// QEDTTN_GEMM_PIPELINE=flat or =loop forces one GEMM pipeline on every
-// stage of the plans built afterwards; anything else (or unset) chooses per
-// stage by the mean reduction length.
+// QEDTTN_GEMM_PIPELINE=flat, =loop or =dma forces one GEMM pipeline on
+// every stage of the plans built afterwards (dma where a stage allows it,
+// loop elsewhere); =nodma chooses as by default with loop in place of dma;
+// anything else (or unset) chooses per stage: flat for short mean
+// reductions, else dma where allowed, else loop.
 static int forced_pipeline() {
     const char* v = std::getenv("QEDTTN_GEMM_PIPELINE");
     if (!v) return -1;
-    if (!std::strcmp(v, "flat")) return 1;
-    if (!std::strcmp(v, "loop")) return 0;
+    if (!std::strcmp(v, "nodma")) return -2;
+    if (!std::strcmp(v, "flat")) return GEMM_PIPE_FLAT;
+    if (!std::strcmp(v, "loop")) return GEMM_PIPE_LOOP;
+    if (!std::strcmp(v, "dma")) return GEMM_PIPE_DMA;
     return -1;
+}
+
+// The LDS-DMA pipeline reads FP32 operands with tA = tB = 0 through 32-bit
+// byte offsets: every offset a tile forms (rows and reduction chunks padded
+// to the tile) must stay below 2^31 bytes.
+static bool dma_operands_ok(const std::vector<GJob>& jobs, const std::vector<GProd>& prods) {
+    const int64_t LIM = (int64_t)1 << 29;
+    bool any = false;
+    for (const GJob& J : jobs)
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd& P = prods[p];
+            if (P.ident) continue;
+            if (P.tA || P.tB) return false;
+            any = true;
+            const int64_t nlast = (int64_t)J.N + 128;
+            const int64_t co = P.nsb ? (nlast / P.nsb) * P.nob + P.nsb : nlast;
+            if ((int64_t)(J.M + 128) * P.lda + P.K + 16 >= LIM) return false;
+            if ((int64_t)(P.K + 16) * P.ldb + co >= LIM) return false;
+        }
+    return any;
+}
+
+bool Plan::pipe_valid(size_t s, int pp, int sh) const {
+    if (pp != GEMM_PIPE_DMA) return pp == GEMM_PIPE_LOOP || pp == GEMM_PIPE_FLAT;
+    return dtype == QED_FP32 && dma_ok[s] && brgemm_dma_shape(sh);
 }
 
 // QEDTTN_HEFF_FUSED=1 plans the terms with a bond-leg factor of every FP32
@@ -476,7 +505,8 @@ void Plan::upload(Dev* dev) {
     ntiles.clear();
     shape.clear();
     sumk.clear();
-    flat.clear();
+    pipe.clear();
+    dma_ok.clear();
     for (size_t s = 0; s < jobs.size(); ++s) {
         bool only_ident = !jobs[s].empty();
         double ksum = 0.0, kn = 0.0;
@@ -487,11 +517,7 @@ void Plan::upload(Dev* dev) {
                 kn += 1.0;
             }
         sumk.push_back(only_ident ? 1 : 0);
-        // short reductions per product: pipeline across products (the
-        // environment may force either pipeline, to compare the two on one
-        // plan)
-        const int forced = forced_pipeline();
-        flat.push_back(forced >= 0 ? forced : (kn > 0.0 && ksum / kn < 64.0 ? 1 : 0));
+        dma_ok.push_back(dtype == QED_FP32 && !only_ident && dma_operands_ok(jobs[s], prods[s]) ? 1 : 0);
         // the tile shape that pads the stage's jobs least
         int best = GEMM_SHAPE_SQUARE;
         double best_area = -1.0;
@@ -508,6 +534,15 @@ void Plan::upload(Dev* dev) {
         tiles.push_back(only_ident ? make_sum_tiles(jobs[s]) : make_tiles(jobs[s], prods[s], best));
         ntiles.push_back((int)tiles.back().size());
         shape.push_back(best);
+        // short reductions per product: pipeline across products; long
+        // ones through the LDS ring where the stage allows it (the
+        // environment may force one pipeline, to compare them on one plan)
+        const int forced = forced_pipeline();
+        int pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT : GEMM_PIPE_DMA;
+        if (forced >= 0) pp = forced;
+        if (forced == -2 && pp == GEMM_PIPE_DMA) pp = GEMM_PIPE_LOOP;
+        if (!pipe_valid(s, pp, best)) pp = GEMM_PIPE_LOOP;
+        pipe.push_back((char)pp);
     }
     // fused jobs of each stage
     const size_t S = jobs.size();
@@ -611,9 +646,12 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
         launch_sum_stage(dtype, J, Pp, T, ntiles[s], b, st);
         return;
     }
-    if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], flat[s] != 0, st);
+    const bool fl = pipe[s] == GEMM_PIPE_FLAT;
+    if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
     else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
-    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], flat[s] != 0, st);
+    else if (pipe[s] == GEMM_PIPE_DMA && pipe_valid(s, GEMM_PIPE_DMA, shape[s]))
+        launch_brgemm_dma(J, Pp, T, ntiles[s], b, shape[s], st);
+    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
 }
 
 void Prof::record_begin(hipStream_t s, hipEvent_t& a) {
@@ -650,12 +688,15 @@ void Prof::harvest() {
 
 void Prof::report() const {
     static const char* shapes[] = {"64x64", "128x32", "32x128"};
+    static const char* pipes[] = {"loop", "flat", "dma"};
     for (const auto& kv : by_key) {
-        const int st = kv.first / 16, sh = kv.first % 16;
+        const int st = kv.first / 16, k = kv.first % 16;
+        const int sh = k % 4, pp = k / 4;
         const auto& v = kv.second;
-        std::fprintf(stderr, "[qedttn] gemm stage %d tile %s: %.0f launches, %.3f ms, %.3e flops, %.2f TFLOP/s\n",
-                     st, sh < 3 ? shapes[sh] : (sh == FUSED_KEY ? "fused" : "?"), v[0], v[1], v[2],
-                     v[1] > 0 ? v[2] / v[1] / 1e9 : 0.0);
+        std::fprintf(stderr,
+                     "[qedttn] gemm stage %d tile %s %s: %.0f launches, %.3f ms, %.3e flops, %.2f TFLOP/s\n", st,
+                     k == FUSED_KEY ? "fused" : (sh < 3 ? shapes[sh] : "?"), k == FUSED_KEY ? "" : pipes[pp % 3],
+                     v[0], v[1], v[2], v[1] > 0 ? v[2] / v[1] / 1e9 : 0.0);
     }
 }
 
@@ -694,7 +735,7 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
                 prof->record_begin(dev->stream, e1);
                 prof->ev.push_back({e0, e1});
                 prof->ev_flops.push_back(s < stage_flops.size() ? stage_flops[s] : 0.0);
-                prof->ev_key.push_back((int)s * 16 + shape[s]);
+                prof->ev_key.push_back((int)s * 16 + shape[s] + 4 * pipe[s]);
                 prof->launches += 1;
             }
         }

@@ -98,6 +98,10 @@ void seg_ritz(double*, const double*, int64_t, const double*, int, const SegChun
 void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const double*, int,
                         double*, int64_t*, double*, hipStream_t);
 
+// FP32 block GEMM whose operands travel straight into an LDS ring
+// (GEMM_PIPE_DMA; SQUARE and WIDE tiles only)
+bool brgemm_dma_shape(int shape);
+void launch_brgemm_dma(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape, hipStream_t);
 void launch_brgemm_bf16(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape,
                         hipStream_t);
 void launch_f64_to_bf16(const double*, void*, int64_t, hipStream_t);
@@ -210,7 +214,7 @@ struct Prof {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<hipEvent_t> pool;        // harvested events, reused
     std::vector<double> ev_flops;
-    std::vector<int> ev_key;             // stage index * 16 + tile shape (FUSED_KEY: fused)
+    std::vector<int> ev_key;             // stage index * 16 + tile shape + 4 pipeline (FUSED_KEY: fused)
     long long launches = 0;
     double ms = 0.0, flops = 0.0;
     long long f_launches = 0;            // the fused kernel's share of the above
@@ -243,7 +247,11 @@ struct Plan {
     std::vector<int> ntiles;
     std::vector<int> shape;   // workgroup tile shape per stage
     std::vector<char> sumk;   // stage of identity products only: elementwise sum kernel
-    std::vector<char> flat;   // stage with short reductions: flat product pipeline
+    // GEMM pipeline per stage (GEMM_PIPE_*): the flat product pipeline for
+    // short reductions, the LDS-DMA ring for long FP32 reductions whose
+    // operands it can read (dma_ok), the register-staged loop otherwise
+    std::vector<char> pipe;
+    std::vector<char> dma_ok;
     // fused H_eff jobs (k_heff_fused) of each stage, launched after the
     // stage's GEMM jobs; stages without them have empty lists (the lists
     // may be shorter than `jobs`)
@@ -261,6 +269,7 @@ struct Plan {
     void launch_stage(size_t s, const Bases& b, hipStream_t st) const;
     void launch_fused(size_t s, const Bases& b, hipStream_t st) const;
     void set_shape(Dev* dev, int s, int sh);   // re-tile one stage
+    bool pipe_valid(size_t s, int pipe, int sh) const;
 };
 
 struct HTerm {
@@ -508,7 +517,7 @@ struct SegLanczos {
     void cycle(const std::function<void(const double*, double*)>& apply, double* x, hipStream_t s);
 };
 
-// ---- autotuner of the GEMM tile shape per plan stage --------------------
+// ---- autotuner of the GEMM tile shape and pipeline per plan stage --------
 struct Tuner {
     bool on = false;
     std::string path;

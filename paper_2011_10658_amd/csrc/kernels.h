@@ -128,6 +128,12 @@ inline int gemm_tn(int s) {
 }
 constexpr int GEMM_THREADS = 256;
 
+// Operand pipelines of the block GEMM: register-staged double buffer
+// (loop), one chunk per product across the products of a job (flat), and
+// the LDS ring filled by buffer-to-LDS loads (dma: FP32, tA = tB = 0,
+// SQUARE and WIDE tiles, operands under 2^29 elements).
+enum { GEMM_PIPE_LOOP = 0, GEMM_PIPE_FLAT = 1, GEMM_PIPE_DMA = 2, GEMM_NPIPES = 3 };
+
 // Per-block description for packing a node tensor into the column-major
 // matrices of its sectors along one leg (QR), and back.
 struct PackBlk {

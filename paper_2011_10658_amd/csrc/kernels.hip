@@ -409,6 +409,225 @@ void launch_sum_stage(int dtype, const GJob* jobs, const GProd* prods, const GTi
         launch_sum_stage_bf16(jobs, prods, tiles, ntiles, bases, st);
 }
 
+// ---------------------------------------------------------------------
+// FP32 grouped batch-reduce GEMM with direct global -> LDS loads
+// ---------------------------------------------------------------------
+// The same job/product/tile contract as k_brgemm, for stages whose
+// products read A row-major along K (tA = 0) and B row-major along N
+// (tB = 0): the mode products on the two child legs, with reductions of a
+// full child sector (K up to 141).  Operands travel from global memory
+// straight into LDS (buffer loads with the LDS destination: each
+// instruction fills 64 consecutive LDS words, lane by lane), NS chunks of
+// KC = 16 live in an LDS ring, and a chunk is requested NS - 1 chunks
+// before it is multiplied, so no registers stage the operands and more of
+// the load latency is covered.
+// Elements outside the operands (M, N and K tails) are given an offset
+// beyond the buffer resource's range, which reads as zero, so every lane
+// issues every load and the per-wave count of loads in flight is exact (the
+// waits are counted).  The product's coefficient
+// multiplies the A operand as it is read from LDS.
+// LDS layouts (conflict-free MFMA operand reads):
+//   A: element (m, k) at (m / 4) 66 + (m % 4) 16 + (k ^ (8 [m % 4 >= 2]));
+//      one load instruction fills 4 rows of 16 k;
+//   B: element (k, n) at k (TN + 16) + n; one instruction fills 64 n of a row.
+// word 3 of a raw (untyped, stride 0) buffer resource on gfx9-family
+// parts, and a byte offset beyond every resource's range
+constexpr int DMA_RSRC_W3 = 0x00020000;
+constexpr uint32_t DMA_OOB = 0x80000000u;
+
+template <int N> struct VmWait {
+    // s_waitcnt with vmcnt(N) only (expcnt and lgkmcnt left unconstrained)
+    static constexpr int imm = (N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+};
+
+#define QED_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+template <int WM, int WN, int BM, int BN, int NS>
+__global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ jobs,
+                                                     const GProd* __restrict__ prods,
+                                                     const GTile* __restrict__ tiles, Bases bases) {
+    typedef Mfma<float>::v4 v4;
+    constexpr int KC = 16;
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
+    static_assert(TN % 64 == 0 && TM % 16 == 0, "tile shape");
+    constexpr int A_SLOT = (TM / 4) * 66;
+    constexpr int LDB = TN + 16;
+    constexpr int B_SLOT = KC * LDB;
+    constexpr int SLOT = A_SLOT + B_SLOT;
+    constexpr int IA = TM / 16;          // A load instructions per wave and chunk
+    constexpr int IB = TN / 16;          // B load instructions per wave and chunk
+    constexpr int V = IA + IB;
+    constexpr int D = NS - 1;            // chunks requested ahead
+    __shared__ float lds[NS * SLOT];
+    const GTile tl = tiles[blockIdx.x];
+    if (tl.job < 0) return;
+    const GJob J = jobs[tl.job];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave / WN) * 16 * BM;
+    const int wn0 = (wave % WN) * 16 * BN;
+    const int m0 = tl.tm * TM;
+    const int n0 = tl.tn * TN;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4 acc[BM][BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    // this lane's element of each of its load instructions: A instruction
+    // j covers rows 4 q .. 4 q + 3 (q = wave IA + j); B instruction j is row
+    // t / (TN / 64), segment t % (TN / 64) (t = wave IB + j)
+    const int ar = lane >> 4;
+    const int ak = (lane & 15) ^ ((ar & 2) << 2);
+    // MFMA operand words: A row (wm0 + i 16 + lr), B column (wn0 + j 16 + lr)
+    int aw[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const int m = wm0 + i * 16 + lr;
+        aw[i] = (m >> 2) * 66 + (m & 3) * 16;
+    }
+    const int sw = ((lr & 2) << 2);       // the A swizzle of row m (m % 4 = lr % 4)
+    for (int p = J.p0; p < J.p1; ++p) {
+        const GProd P = prods[p];
+        const float* Bb = resolve<float>(P.B, bases) + (int64_t)tl.b * P.bsB;
+        if (P.ident) {
+            const float alpha = (float)P.alpha;
+#pragma unroll
+            for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < BN; ++bj) {
+                    const int col = n0 + wn0 + bj * 16 + lr;
+                    const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = m0 + wm0 + bi * 16 + Mfma<float>::row(lane, i);
+                        if (row < J.M && col < J.N) acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + co];
+                    }
+                }
+            continue;
+        }
+        const float* Ab = resolve<float>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        const float alpha = (float)P.alpha;
+        const int nchunk = (P.K + KC - 1) / KC;
+        // B instruction j of this wave: row wave IB / HS + j / HS of the
+        // chunk, 64-column segment j % HS (IB is a multiple of HS).  Byte
+        // offsets relative to the chunk's first row (B) or column (A) are
+        // fixed for the product; a chunk adds its k0 to them.
+        constexpr int HS = TN / 64;
+        const int brow0 = wave * (IB / HS);
+        uint32_t boff[IB];
+        bool bok[IB];
+#pragma unroll
+        for (int j = 0; j < IB; ++j) {
+            const int n = n0 + (j % HS) * 64 + lane;
+            const int row = brow0 + j / HS;
+            bok[j] = n < J.N;
+            const int co = P.nsb ? (n / P.nsb) * (int)P.nob + n % P.nsb : n;
+            boff[j] = 4u * (uint32_t)(row * P.ldb + co);
+        }
+        // A instruction j of this wave: row am + 4 j (this lane's row)
+        const int am = m0 + 4 * wave * IA + ar;
+        uint32_t aoff[IA];
+        bool aok[IA];
+#pragma unroll
+        for (int j = 0; j < IA; ++j) {
+            aok[j] = am + 4 * j < J.M;
+            aoff[j] = 4u * (uint32_t)((am + 4 * j) * P.lda + ak);
+        }
+        for (int r = 0; r < P.nred; ++r) {
+            // raw buffer resources over the operands; an offset of 2^31 is
+            // outside every operand (the host routes no product whose
+            // operand spans 2^31 bytes here) and reads as zero
+            const __amdgpu_buffer_rsrc_t ra =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(Ab + (int64_t)r * P.rsA), (short)0, 0x7fffffff, DMA_RSRC_W3);
+            const __amdgpu_buffer_rsrc_t rb =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(Bb + (int64_t)r * P.rsB), (short)0, 0x7fffffff, DMA_RSRC_W3);
+            // request chunk c into ring slot c % NS
+            auto issue = [&](int c) {
+                float* slot = lds + (c % NS) * SLOT;
+                const int k0 = c * KC;
+                const bool kin = k0 + ak < P.K;
+#pragma unroll
+                for (int j = 0; j < IA; ++j) {
+                    const uint32_t o = (aok[j] && kin) ? aoff[j] + 4u * (uint32_t)k0 : DMA_OOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, QED_LDS_PTR(slot + (wave * IA + j) * 66), 4, o, 0, 0,
+                                                             0);
+                }
+                const uint32_t kb = 4u * (uint32_t)(k0 * P.ldb);
+#pragma unroll
+                for (int j = 0; j < IB; ++j) {
+                    const int row = brow0 + j / HS, h = j % HS;
+                    const uint32_t o = (bok[j] && k0 + row < P.K) ? boff[j] + kb : DMA_OOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, QED_LDS_PTR(slot + A_SLOT + row * LDB + h * 64), 4, o,
+                                                             0, 0, 0);
+                }
+            };
+            // the previous product's last chunks may still be read from the
+            // ring by other waves
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                if (c < nchunk) issue(c);
+            for (int c = 0; c < nchunk; ++c) {
+                // chunk c complete for this wave: the loads requested after
+                // it (at most D - 1 chunks) may still be in flight
+                const int after = nchunk - 1 - c < D - 1 ? nchunk - 1 - c : D - 1;
+                if (after >= 2) __builtin_amdgcn_s_waitcnt(VmWait<2 * V>::imm);
+                else if (after == 1) __builtin_amdgcn_s_waitcnt(VmWait<V>::imm);
+                else __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
+                __builtin_amdgcn_s_barrier();
+                // every wave is past chunk c - 1: its slot takes chunk c + D
+                if (c + D < nchunk) issue(c + D);
+                const float* As = lds + (c % NS) * SLOT;
+                const float* Bs = As + A_SLOT;
+#pragma unroll
+                for (int kk = 0; kk < KC; kk += 4) {
+                    float a[BM], bb[BN];
+                    const int k = kk + lk;
+#pragma unroll
+                    for (int i = 0; i < BM; ++i) a[i] = As[aw[i] + (k ^ sw)] * alpha;
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) bb[j] = Bs[k * LDB + wn0 + j * 16 + lr];
+#pragma unroll
+                    for (int i = 0; i < BM; ++i)
+#pragma unroll
+                        for (int j = 0; j < BN; ++j) acc[i][j] = Mfma<float>::step(a[i], bb[j], acc[i][j]);
+                }
+            }
+        }
+    }
+    float* C = resolve<float>(J.C, bases) + (int64_t)tl.b * J.bsC;
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BN; ++bj) {
+            const int col = n0 + wn0 + bj * 16 + lr;
+            const int64_t co = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + wm0 + bi * 16 + Mfma<float>::row(lane, i);
+                if (row < J.M && col < J.N) {
+                    float* c = C + (int64_t)row * J.ldc + co;
+                    *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
+                }
+            }
+        }
+}
+
+bool brgemm_dma_shape(int shape) { return shape == GEMM_SHAPE_SQUARE || shape == GEMM_SHAPE_WIDE; }
+
+void launch_brgemm_dma(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
+                       const Bases& bases, int shape, hipStream_t st) {
+    if (ntiles <= 0) return;
+    if (shape == GEMM_SHAPE_WIDE)
+        hipLaunchKernelGGL((k_brgemm_dma<1, 4, 2, 2, 3>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles,
+                           bases);
+    else
+        hipLaunchKernelGGL((k_brgemm_dma<2, 2, 2, 2, 3>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles,
+                           bases);
+}
+
 template <typename T>
 void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
                    const Bases& bases, int shape, bool flat, hipStream_t st) {
