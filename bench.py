@@ -649,6 +649,10 @@ def main():
     ap.add_argument("--workload", choices=("sweep", "batched", "finite_density", "adjoint",
                                            "observables", "expansion"),
                     default="sweep")
+    ap.add_argument("--only", choices=("f64", "f32", "bf16"),
+                    help="profiling aid: run one path alone (its trajectory from the seeded "
+                         "start, then --steps timed sweeps from its own final state) and print "
+                         "that path's record instead of the benchmark line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one elementwise pass of known size (256 MiB read, 256 MiB "
                          "written) to calibrate hardware byte counters")
@@ -694,6 +698,19 @@ def main():
 
     import tempfile
     tmpd = tempfile.mkdtemp(prefix="qedttn_bench_")
+    if a.only:
+        dt = {"f64": lib.FP64, "f32": lib.FP32, "bf16": lib.BF16}[a.only]
+        ckpt = os.path.join(tmpd, "own_final.ckpt")
+        log(f"== {a.only.upper()} GEMM path alone (refine {REFINE[a.only]})")
+        t = trajectory(lib, torch, dt, REFINE[a.only], a.warmup, save=ckpt)
+        r = timed_from(lib, torch, dt, REFINE[a.only], ckpt, a.steps)
+        os.remove(ckpt)
+        os.rmdir(tmpd)
+        t.pop("energies", None)
+        log(f"  from its own final state: {r['ms_per_step']:.1f} ms/sweep, "
+            f"{r['matvecs_per_sweep']:.0f} matvecs/sweep, GEMM {r['gemm_tflops']:.2f} TFLOP/s")
+        print(json.dumps({"only": a.only, "trajectory": t, "timed": r}), flush=True)
+        return
     ckpt = os.path.join(tmpd, "fp64_final.ckpt")
     res, traj = {}, {}
     own = os.path.join(tmpd, "own_final.ckpt")

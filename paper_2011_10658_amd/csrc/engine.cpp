@@ -1696,21 +1696,41 @@ bool cholqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     return true;
 }
 
+// Rows per chunk of the LDS-resident QR: its time per column step grows
+// with the rows, so tall sectors are cut into chunks of at most 256 rows
+// (QEDTTN_QR_CHUNK sets another target; never fewer than 3n rows).
+static int64_t qr_lds_chunk(int n) {
+    static const int64_t target = [] {
+        const char* v = std::getenv("QEDTTN_QR_CHUNK");
+        const long t = v ? std::atol(v) : 0;
+        return (int64_t)(t > 0 ? t : 256);
+    }();
+    return std::max<int64_t>(target, 3 * (int64_t)n);
+}
+
 void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     if (tasks.empty()) return;
-    // level 1: every direct matrix and every row chunk of every tall one
-    std::vector<QRMat> blocked, wide;
-    int64_t rows_b = 0, rows_w = 0;
-    int cols_b = 0, cols_w = 0;
+    // level 1: every direct matrix and every row chunk of every tall one.
+    // Matrices of at most QRL_MAXC columns take the LDS-resident kernel;
+    // wider ones up to QR_COLS columns the blocked kernel (up to QR_ROWS
+    // rows), wider still the unblocked one
+    std::vector<QRMat> lds, blocked, wide;
+    int64_t rows_b = 0, rows_w = 0, rows_l = 0;
+    int cols_b = 0, cols_w = 0, cols_l = 0;
     std::vector<BufP> keep;
     struct Tall {
         QRTask t;
-        int64_t b;
-        int P;
+        std::vector<int64_t> cut;   // first row of every chunk, then m
         BufP S, T;
     };
     std::vector<Tall> tall;
     auto add = [&](const QRMat& q) {
+        if (qr_lds_fits(q.rows, q.cols)) {
+            lds.push_back(q);
+            rows_l = std::max<int64_t>(rows_l, q.rows);
+            cols_l = std::max(cols_l, q.cols);
+            return;
+        }
         const bool bl = q.rows <= QR_ROWS && q.cols <= QR_COLS;
         (bl ? blocked : wide).push_back(q);
         if (bl) {
@@ -1725,32 +1745,47 @@ void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
         if (t.m < t.n) fail(QED_ERR_BAD_STATE, "QR of a wide matrix");
         if (t.n > 8192) fail(QED_ERR_UNSUPPORTED, "QR of a sector wider than 8192 columns");
         if (t.n == 0) continue;
-        // sectors up to QR_COLS wide take the blocked kernel (at most QR_ROWS
-        // rows per workgroup); wider ones the unblocked kernel
+        const bool in_lds = t.n <= QRL_MAXC;
         const bool bl = t.n <= QR_COLS;
-        const int64_t direct_max = bl ? QR_ROWS : std::max<int64_t>(4096, 16 * (int64_t)t.n);
+        const int64_t direct_max = in_lds ? std::min<int64_t>(qr_lds_chunk(t.n), QRL_CAP / t.n - 1)
+                                          : (bl ? QR_ROWS : std::max<int64_t>(4096, 16 * (int64_t)t.n));
         if (t.m <= direct_max) {
             auto q = std::make_shared<DBuf>(dev, (size_t)t.m * t.n * sizeof(double));
             keep.push_back(q);
             add(QRMat{t.M, q->as<double>(), t.R, t.m, t.rrs, t.rcs, (int)t.m, t.n});
             continue;
         }
-        // chunks of b rows (the last one takes the remainder, < 2b, which is
-        // at most QR_ROWS on the blocked path)
         Tall T;
         T.t = t;
-        T.b = bl ? std::max<int64_t>(512, 4 * (int64_t)t.n) : std::max<int64_t>(2048, 4 * (int64_t)t.n);
-        T.P = (int)(t.m / T.b);
-        const int64_t ls = (int64_t)T.P * t.n;   // rows of the stacked R factors
+        if (in_lds) {
+            // P near-equal chunks of at most direct_max rows (each at least
+            // direct_max / 2 >= n rows)
+            const int64_t P = (t.m + direct_max - 1) / direct_max;
+            for (int64_t i = 0; i <= P; ++i) T.cut.push_back(t.m * i / P);
+        } else {
+            // chunks of b rows, the last one takes the remainder (< 2b,
+            // which is at most QR_ROWS on the blocked path)
+            const int64_t b = bl ? std::max<int64_t>(512, 4 * (int64_t)t.n) : std::max<int64_t>(2048, 4 * (int64_t)t.n);
+            const int64_t P = t.m / b;
+            for (int64_t i = 0; i < P; ++i) T.cut.push_back(i * b);
+            T.cut.push_back(t.m);
+        }
+        const int P = (int)T.cut.size() - 1;
+        const int64_t ls = (int64_t)P * t.n;   // rows of the stacked R factors
         T.S = std::make_shared<DBuf>(dev, (size_t)ls * t.n * sizeof(double));
         T.T = std::make_shared<DBuf>(dev, (size_t)t.m * t.n * sizeof(double));
-        for (int i = 0; i < T.P; ++i) {
-            const int64_t r0 = (int64_t)i * T.b;
-            const int64_t rows = i == T.P - 1 ? t.m - r0 : T.b;
+        for (int i = 0; i < P; ++i) {
+            const int64_t r0 = T.cut[i];
             add(QRMat{t.M + r0, T.T->as<double>() + r0, T.S->as<double>() + (int64_t)i * t.n, t.m, 1, ls,
-                      (int)rows, t.n});
+                      (int)(T.cut[i + 1] - r0), t.n});
         }
         tall.push_back(T);
+    }
+    if (!lds.empty()) {
+        DBuf dq(dev, lds.size() * sizeof(QRMat));
+        dev->upload(dq.p, lds.data(), lds.size() * sizeof(QRMat));
+        launch_qr_lds(dq.as<QRMat>(), (int)lds.size(), rows_l, cols_l, dev->stream);
+        dev->check(hipGetLastError(), "qr launch");
     }
     for (int kind = 0; kind < 2; ++kind) {
         const auto& list = kind == 0 ? blocked : wide;
@@ -1765,7 +1800,8 @@ void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     // the stacked R factors of every tall matrix, one level further up
     std::vector<QRTask> up;
     for (const Tall& T : tall)
-        up.push_back(QRTask{T.S->as<double>(), (int64_t)T.P * T.t.n, T.t.n, T.t.R, T.t.rrs, T.t.rcs});
+        up.push_back(QRTask{T.S->as<double>(), (int64_t)(T.cut.size() - 1) * T.t.n, T.t.n, T.t.R, T.t.rrs,
+                            T.t.rcs});
     tsqr_multi(dev, up);
     // Q = blockdiag(Q1_i) * Q2: chunk i of Q is Q1_i Q2[i n .. (i+1) n), all
     // matrices in one GEMM launch
@@ -1776,10 +1812,11 @@ void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     pl.stage_flops.push_back(0.0);
     for (const Tall& T : tall) {
         const int n = T.t.n;
-        const int64_t m = T.t.m, ls = (int64_t)T.P * n;
-        for (int i = 0; i < T.P; ++i) {
-            const int64_t r0 = (int64_t)i * T.b;
-            const int rows = (int)(i == T.P - 1 ? m - r0 : T.b);
+        const int P = (int)T.cut.size() - 1;
+        const int64_t m = T.t.m, ls = (int64_t)P * n;
+        for (int i = 0; i < P; ++i) {
+            const int64_t r0 = T.cut[i];
+            const int rows = (int)(T.cut[i + 1] - r0);
             GProd pr{};
             pr.A = GRef{T.S->as<double>() + (int64_t)i * n, 0, TAG_ABS, 0};
             pr.lda = (int)ls;

@@ -74,6 +74,7 @@ void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_
 // blocked kernel when every matrix has rows <= QR_ROWS and cols <= QR_COLS,
 // else the unblocked one
 void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_t);
+void launch_qr_lds(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
 void launch_jacobi_svd(const SvdMat*, int nmats, hipStream_t);

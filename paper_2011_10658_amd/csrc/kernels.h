@@ -154,6 +154,18 @@ constexpr int SUM_TILE = 256;
 // Sizes one QR workgroup handles (the panel and the T factors live in LDS).
 constexpr int QR_ROWS = 2048;
 constexpr int QR_COLS = 256;
+// LDS-resident QR (k_qr_lds): matrices of at most QRL_MAXC columns, QR_ROWS
+// rows and (rows + 1) x cols <= QRL_CAP
+constexpr int QRL_MAXC = 96;
+constexpr int QRL_CAP = 19456;
+inline bool qr_lds_fits(int64_t rows, int cols) {
+    return cols <= QRL_MAXC && rows <= QR_ROWS && (rows + 1) * cols <= QRL_CAP;
+}
+// LDS of a k_qr_lds launch whose matrices have at most maxrows rows and
+// maxcols columns
+inline size_t qr_lds_bytes(int64_t maxrows, int maxcols) {
+    return (size_t)(((maxrows | 1) * maxcols) + 3 * maxcols + 4 + 512) * sizeof(double);
+}
 
 struct QRMat {
     double* a;          // the matrix (column-major, leading dimension ld); Q on exit

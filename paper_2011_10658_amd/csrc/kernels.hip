@@ -1861,6 +1861,219 @@ __global__ __launch_bounds__(256) void k_chol_inv(const CholMat* __restrict__ ma
     }
 }
 
+// Householder QR of one column-major rows x cols chunk per workgroup with
+// the whole chunk resident in LDS (qr_lds_fits); the same contract as
+// k_householder_qr (explicit Q written over the input, R through (rout,
+// rrs, rcs), diag(R) >= 0, tau = 0 and R_jj = 0 for a zero column).
+// Lane l of every wave owns column k = i + 1 + l (and k + 64) of the
+// trailing matrix, and the rows below the diagonal are split into four
+// ranges, one per wave: the products v^T a_k are per-lane sums over the
+// wave's rows (eight rows' loads issued together), combined across the
+// waves through LDS in a fixed order (one barrier), so no cross-lane
+// reduction is on the path.  The norm of the next column is gathered while
+// its update is written.  Q is then formed in place from the reflectors,
+// last to first (column i becomes H_i e_i once the columns right of it
+// hold H_i+1 ... [I; 0]), with the same column-per-lane products.  The
+// leading dimension in LDS is odd, so the lanes of a wave read different
+// banks.
+__device__ __forceinline__ void qrl_rows(int r0, int m, int wave, int& rb, int& re) {
+    const int nr = m - r0;
+    rb = r0 + (nr * wave) / 4;
+    re = r0 + (nr * (wave + 1)) / 4;
+}
+
+// sum over rows [rb, re) of v[r] c[r]
+__device__ __forceinline__ double qrl_dot(const double* v, const double* c, int rb, int re) {
+    double p = 0.0;
+    int r = rb;
+    for (; r + 8 <= re; r += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = v[r + u];
+            b[u] = c[r + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p += a[u] * b[u];
+    }
+    for (; r < re; ++r) p += v[r] * c[r];
+    return p;
+}
+
+// c[r] -= w v[r] over rows [rb, re); returns the sum of the new c[r]^2 over
+// rows r > skip
+__device__ __forceinline__ double qrl_axpy(double* c, const double* v, double w, int rb, int re, int skip) {
+    double s = 0.0;
+    int r = rb;
+    for (; r + 8 <= re; r += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = v[r + u];
+            b[u] = c[r + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            b[u] -= w * a[u];
+            if (r + u > skip) s += b[u] * b[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) c[r + u] = b[u];
+    }
+    for (; r < re; ++r) {
+        const double u = c[r] - w * v[r];
+        c[r] = u;
+        if (r > skip) s += u * u;
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_qr_lds(const QRMat* __restrict__ mats) {
+    extern __shared__ double qs[];
+    const QRMat Mt = mats[blockIdx.x];
+    const int m = Mt.rows, n = Mt.cols;
+    const int64_t ldg = Mt.ld;
+    const int ld = m | 1;
+    double* As = qs;                          // column k at As + k ld
+    double* tau = As + (int64_t)ld * n;
+    double* vd = tau + n;                     // v on the diagonal
+    double* dg = vd + n;                      // R_ii before the sign fix
+    double* red = dg + n;                     // [4]
+    double* part = red + 4;                   // [4][128]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
+        const int c = (int)(e / m), r = (int)(e % m);
+        As[(int64_t)c * ld + r] = Mt.a[(int64_t)c * ldg + r];
+    }
+    __syncthreads();
+    {
+        double s0 = 0.0;
+        for (int r = 1 + tid; r < m; r += 256) s0 += As[r] * As[r];
+        s0 = wave_allsum(s0);
+        if (lane == 0) red[wave] = s0;
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+        const double* ci = As + (int64_t)i * ld;
+        const double sb = ((red[0] + red[1]) + red[2]) + red[3];
+        const double x0 = ci[i];
+        const double nrm = sqrt(x0 * x0 + sb);
+        double ti = 0.0, v0 = 0.0, al = 0.0;
+        if (nrm != 0.0) {
+            al = x0 >= 0.0 ? -nrm : nrm;
+            v0 = x0 - al;
+            const double vtv = v0 * v0 + sb;
+            ti = vtv > 0.0 ? 2.0 / vtv : 0.0;
+        }
+        int rb, re;
+        qrl_rows(i + 1, m, wave, rb, re);
+        const int k0 = i + 1 + lane, k1 = k0 + 64;
+        const bool a0 = k0 < n, a1 = k1 < n;
+        double* c0 = As + (int64_t)(a0 ? k0 : i) * ld;
+        double* c1 = As + (int64_t)(a1 ? k1 : i) * ld;
+        if (ti != 0.0) {
+            double p0 = 0.0, p1 = 0.0;
+            if (wave == 0) {
+                p0 = v0 * c0[i];
+                p1 = v0 * c1[i];
+            }
+            p0 += qrl_dot(ci, c0, rb, re);
+            if (i + 65 < n) p1 += qrl_dot(ci, c1, rb, re);
+            part[wave * 128 + lane] = p0;
+            part[wave * 128 + 64 + lane] = p1;
+        }
+        if (tid == 0) {
+            tau[i] = ti;
+            vd[i] = v0;
+            dg[i] = al;
+        }
+        __syncthreads();
+        // updates, and the next column's squares below its diagonal
+        double nx = 0.0;
+        if (ti != 0.0) {
+            const double w0 = ti * (((part[lane] + part[128 + lane]) + part[256 + lane]) + part[384 + lane]);
+            const double w1 =
+                ti * (((part[64 + lane] + part[192 + lane]) + part[320 + lane]) + part[448 + lane]);
+            if (a0) {
+                nx = qrl_axpy(c0, ci, w0, rb, re, i + 1);
+                if (wave == 0) c0[i] -= w0 * v0;
+            }
+            if (a1) {
+                (void)qrl_axpy(c1, ci, w1, rb, re, m);
+                if (wave == 0) c1[i] -= w1 * v0;
+            }
+        } else if (a0) {
+            for (int r = rb; r < re; ++r)
+                if (r > i + 1) nx += c0[r] * c0[r];
+        }
+        if (lane == 0) red[wave] = nx;   // lane 0 holds column i + 1
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += 256) {
+        const int r = e / n, c = e % n;
+        const double v = c > r ? As[(int64_t)c * ld + r] : (c == r ? dg[r] : 0.0);
+        Mt.r[r * Mt.rrs + c * Mt.rcs] = dg[r] < 0.0 ? -v : v;
+    }
+    __syncthreads();
+    // Q in place: step i turns columns k > i (rows > i hold H_i+1 ... e_k,
+    // row i still R) into H_i applied to them, then column i into H_i e_i
+    for (int i = n - 1; i >= 0; --i) {
+        double* ci = As + (int64_t)i * ld;
+        const double ti = tau[i], v0 = vd[i];
+        int rb, re;
+        qrl_rows(i + 1, m, wave, rb, re);
+        const int k0 = i + 1 + lane, k1 = k0 + 64;
+        const bool a0 = k0 < n, a1 = k1 < n;
+        double* c0 = As + (int64_t)(a0 ? k0 : i) * ld;
+        double* c1 = As + (int64_t)(a1 ? k1 : i) * ld;
+        if (ti != 0.0) {
+            const double p0 = qrl_dot(ci, c0, rb, re);
+            const double p1 = i + 65 < n ? qrl_dot(ci, c1, rb, re) : 0.0;
+            part[wave * 128 + lane] = p0;
+            part[wave * 128 + 64 + lane] = p1;
+        }
+        __syncthreads();
+        if (ti != 0.0) {
+            const double w0 = ti * (((part[lane] + part[128 + lane]) + part[256 + lane]) + part[384 + lane]);
+            const double w1 =
+                ti * (((part[64 + lane] + part[192 + lane]) + part[320 + lane]) + part[448 + lane]);
+            if (a0) {
+                (void)qrl_axpy(c0, ci, w0, rb, re, m);
+                if (wave == 0) c0[i] = -w0 * v0;
+            }
+            if (a1) {
+                (void)qrl_axpy(c1, ci, w1, rb, re, m);
+                if (wave == 0) c1[i] = -w1 * v0;
+            }
+        } else if (wave == 0) {
+            if (a0) c0[i] = 0.0;
+            if (a1) c1[i] = 0.0;
+        }
+        __syncthreads();
+        // column i: H_i e_i (every row of it is read above, by every wave)
+        for (int r = tid; r < m; r += 256) {
+            double q;
+            if (r < i) q = 0.0;
+            else if (r == i) q = 1.0 - ti * v0 * v0;
+            else q = -ti * v0 * ci[r];
+            ci[r] = q;
+        }
+        __syncthreads();
+    }
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
+        const int c = (int)(e / m), r = (int)(e % m);
+        const double q = As[(int64_t)c * ld + r];
+        Mt.a[(int64_t)c * ldg + r] = dg[c] < 0.0 ? -q : q;
+    }
+}
+
+void launch_qr_lds(const QRMat* mats, int nmats, int64_t maxrows, int maxcols, hipStream_t s) {
+    if (nmats <= 0) return;
+    const size_t lds = qr_lds_bytes(maxrows, maxcols);
+    (void)hipFuncSetAttribute((const void*)k_qr_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_qr_lds, dim3(nmats), dim3(256), lds, s, mats);
+}
+
 void launch_chol_inv(const CholMat* mats, int nmats, int maxn, hipStream_t s) {
     if (nmats <= 0) return;
     const size_t lds = (size_t)2 * maxn * (maxn + 1) * sizeof(double);
