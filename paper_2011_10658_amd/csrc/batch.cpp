@@ -140,6 +140,7 @@ void Tuner::tune(Dev* dev, Plan& P, void* ws, void* x, void* y) {
         for (int sh = 0; sh < GEMM_NSHAPES; ++sh)
             for (int pp = 0; pp < (P.dtype == QED_BF16 ? 1 : GEMM_NPIPES); ++pp) {
                 if (!P.pipe_valid(s, pp, sh)) continue;
+                if (pp == GEMM_PIPE_SKINNY && sh != 0) continue;   // the tile shape does not apply
                 P.set_shape(dev, (int)s, sh);
                 P.pipe[s] = (char)pp;
                 hipEvent_t a, b;

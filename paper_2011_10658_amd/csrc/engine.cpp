@@ -412,6 +412,36 @@ static std::vector<GTile> make_tiles(const std::vector<GJob>& jobs, const std::v
     return tiles;
 }
 
+// Strip tiles of a skinny stage: jobs grouped by their first product's A
+// panel; strip a of every job of a group goes to one XCD, so the group's
+// panel strip is fetched once into that XCD's L2.
+static std::vector<GTile> make_skinny_tiles(const std::vector<GJob>& jobs, const std::vector<GProd>& prods,
+                                            int RS) {
+    std::vector<std::vector<GTile>> per(NXCD);
+    std::map<std::tuple<const void*, int64_t, int>, std::vector<int>> by_a;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const GProd& f = prods[jobs[j].p0];
+        by_a[std::make_tuple(f.A.abs, f.A.off, f.A.tag)].push_back((int)j);
+    }
+    for (const auto& g : by_a) {
+        int tmax = 0;
+        for (int j : g.second) tmax = std::max(tmax, (jobs[j].M + RS - 1) / RS);
+        for (int a = 0; a < tmax; ++a) {
+            int x = 0;
+            for (int y = 1; y < NXCD; ++y)
+                if (per[y].size() < per[x].size()) x = y;
+            for (int j : g.second)
+                if (a < (jobs[j].M + RS - 1) / RS) per[x].push_back(GTile{j, 0, a, 0});
+        }
+    }
+    size_t slots = 0;
+    for (const auto& v : per) slots = std::max(slots, v.size());
+    std::vector<GTile> tiles(slots * NXCD, GTile{-1, 0, 0, 0});
+    for (int x = 0; x < NXCD; ++x)
+        for (size_t k = 0; k < per[x].size(); ++k) tiles[k * NXCD + x] = per[x][k];
+    return tiles;
+}
+
 // Tiles of fused jobs: per job, its group tiles in order, each with all
 // of its row tiles one after another on the least-loaded XCD (the row
 // tiles of a group tile read the same input columns).
@@ -445,15 +475,19 @@ static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
     return tiles;
 }
 
-// QEDTTN_GEMM_PIPELINE=flat, =loop or =dma forces one GEMM pipeline on
-// every stage of the plans built afterwards (dma where a stage allows it,
-// loop elsewhere); =nodma chooses as by default with loop in place of dma;
-// anything else (or unset) chooses per stage: flat for short mean
-// reductions, else dma where allowed, else loop.
+// QEDTTN_GEMM_PIPELINE=flat, =loop, =dma or =skinny forces one GEMM
+// pipeline on every stage of the plans built afterwards (dma or skinny
+// where a stage allows it, loop elsewhere); =nodma chooses as by default
+// without the dma pipeline; anything else (or unset) chooses per stage:
+// flat for short mean reductions, else dma where allowed, else loop.  The
+// skinny pipeline is not chosen by default: on the d = 267 bottom nodes
+// its stage (180 MB of per-term intermediates written per product) runs
+// at the flat pipeline's rate or below; the autotuner may still pick it.
 static int forced_pipeline() {
     const char* v = std::getenv("QEDTTN_GEMM_PIPELINE");
     if (!v) return -1;
     if (!std::strcmp(v, "nodma")) return -2;
+    if (!std::strcmp(v, "skinny")) return GEMM_PIPE_SKINNY;
     if (!std::strcmp(v, "flat")) return GEMM_PIPE_FLAT;
     if (!std::strcmp(v, "loop")) return GEMM_PIPE_LOOP;
     if (!std::strcmp(v, "dma")) return GEMM_PIPE_DMA;
@@ -480,7 +514,28 @@ static bool dma_operands_ok(const std::vector<GJob>& jobs, const std::vector<GPr
     return any;
 }
 
+// The skinny kernel takes stages whose every product is A B^T on a
+// contiguous panel (lda = K, ldb = K, K <= SK_KMAX, one reduction term)
+// into contiguous overwritten outputs of at most SK_NMAX columns (FP32 and
+// FP64).
+static bool skinny_operands_ok(int dtype, const std::vector<GJob>& jobs, const std::vector<GProd>& prods) {
+    if (dtype != QED_FP32 && dtype != QED_FP64) return false;
+    if (jobs.empty()) return false;
+    for (const GJob& J : jobs) {
+        if (J.batch != 1 || J.nsc || J.acc || J.ldc != J.N || J.N > SK_NMAX || J.N < 1 || J.p1 <= J.p0)
+            return false;
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd& P = prods[p];
+            if (P.ident || P.tA || !P.tB || P.nred != 1 || P.lda != P.K || P.ldb != P.K || P.K > SK_KMAX ||
+                P.K < 1 || P.nsb)
+                return false;
+        }
+    }
+    return true;
+}
+
 bool Plan::pipe_valid(size_t s, int pp, int sh) const {
+    if (pp == GEMM_PIPE_SKINNY) return skinny_ok[s] != 0;
     if (pp != GEMM_PIPE_DMA) return pp == GEMM_PIPE_LOOP || pp == GEMM_PIPE_FLAT;
     return dtype == QED_FP32 && dma_ok[s] && brgemm_dma_shape(sh);
 }
@@ -507,6 +562,8 @@ void Plan::upload(Dev* dev) {
     sumk.clear();
     pipe.clear();
     dma_ok.clear();
+    skinny_ok.clear();
+    std::vector<std::vector<GTile>> stiles;
     for (size_t s = 0; s < jobs.size(); ++s) {
         bool only_ident = !jobs[s].empty();
         double ksum = 0.0, kn = 0.0;
@@ -518,6 +575,9 @@ void Plan::upload(Dev* dev) {
             }
         sumk.push_back(only_ident ? 1 : 0);
         dma_ok.push_back(dtype == QED_FP32 && !only_ident && dma_operands_ok(jobs[s], prods[s]) ? 1 : 0);
+        skinny_ok.push_back(!only_ident && skinny_operands_ok(dtype, jobs[s], prods[s]) ? 1 : 0);
+        stiles.push_back(skinny_ok.back() ? make_skinny_tiles(jobs[s], prods[s], skinny_rows(dtype))
+                                          : std::vector<GTile>());
         // the tile shape that pads the stage's jobs least
         int best = GEMM_SHAPE_SQUARE;
         double best_area = -1.0;
@@ -540,9 +600,33 @@ void Plan::upload(Dev* dev) {
         const int forced = forced_pipeline();
         int pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT : GEMM_PIPE_DMA;
         if (forced >= 0) pp = forced;
-        if (forced == -2 && pp == GEMM_PIPE_DMA) pp = GEMM_PIPE_LOOP;
+        if (forced == -2 && pp == GEMM_PIPE_DMA) pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT : GEMM_PIPE_LOOP;
         if (!pipe_valid(s, pp, best)) pp = GEMM_PIPE_LOOP;
         pipe.push_back((char)pp);
+    }
+    if (std::getenv("QEDTTN_TRACE")) {
+        static const char* pn[] = {"loop", "flat", "dma", "skinny"};
+        for (size_t s = 0; s < jobs.size(); ++s) {
+            size_t maxp = 0, single = 0;
+            double out = 0.0, ain = 0.0, kk = 0.0, nn = 0.0;
+            for (const GJob& J : jobs[s]) {
+                const size_t np = (size_t)(J.p1 - J.p0);
+                maxp = std::max(maxp, np);
+                single += np == 1;
+                out += (double)J.M * J.N * J.batch;
+                nn += J.N;
+                for (int p = J.p0; p < J.p1; ++p) {
+                    ain += (double)J.M * prods[s][p].K * prods[s][p].nred * J.batch;
+                    kk += prods[s][p].K;
+                }
+            }
+            std::fprintf(stderr,
+                         "[qedttn] plan stage %zu: %zu jobs (%zu of one product, at most %zu), %zu products, "
+                         "output %.3e, A read %.3e elements, mean N %.1f, mean K %.1f, pipeline %s\n",
+                         s, jobs[s].size(), single, maxp, prods[s].size(), out, ain,
+                         jobs[s].empty() ? 0.0 : nn / jobs[s].size(), prods[s].empty() ? 0.0 : kk / prods[s].size(),
+                         sumk[s] ? "sum" : pn[pipe[s] % 4]);
+        }
     }
     // fused jobs of each stage
     const size_t S = jobs.size();
@@ -553,6 +637,8 @@ void Plan::upload(Dev* dev) {
     dfj.clear();
     dfp.clear();
     dft.clear();
+    dts.clear();
+    nts.clear();
     nftiles.clear();
     fcs_rows.assign(S, 0);
     fcs_cols.assign(S, 0);
@@ -568,7 +654,7 @@ void Plan::upload(Dev* dev) {
     }
     // one device buffer and one copy for the whole plan; arrays at 256-byte
     // aligned offsets
-    std::vector<size_t> oj(S), op(S), ot(S), ofj(S), ofp(S), oft(S);
+    std::vector<size_t> oj(S), op(S), ot(S), ofj(S), ofp(S), oft(S), ost(S);
     size_t total = 0;
     auto place = [&](size_t bytes) {
         const size_t at = total;
@@ -582,6 +668,7 @@ void Plan::upload(Dev* dev) {
         ofj[s] = place(fjobs[s].size() * sizeof(FJob));
         ofp[s] = place(fprods[s].size() * sizeof(FProd));
         oft[s] = place(ftiles[s].size() * sizeof(GTile));
+        ost[s] = place(stiles[s].size() * sizeof(GTile));
     }
     std::vector<unsigned char> host(total);
     auto put = [&](size_t at, const void* src, size_t bytes) {
@@ -594,6 +681,7 @@ void Plan::upload(Dev* dev) {
         put(ofj[s], fjobs[s].data(), fjobs[s].size() * sizeof(FJob));
         put(ofp[s], fprods[s].data(), fprods[s].size() * sizeof(FProd));
         put(oft[s], ftiles[s].data(), ftiles[s].size() * sizeof(GTile));
+        put(ost[s], stiles[s].data(), stiles[s].size() * sizeof(GTile));
     }
     auto buf = std::make_shared<DBuf>(dev, total);
     dev->upload(buf->p, host.data(), total);   // staged (asynchronous) or synchronous
@@ -605,6 +693,8 @@ void Plan::upload(Dev* dev) {
         dfj.push_back((const FJob*)(base + ofj[s]));
         dfp.push_back((const FProd*)(base + ofp[s]));
         dft.push_back((const GTile*)(base + oft[s]));
+        dts.push_back((const GTile*)(base + ost[s]));
+        nts.push_back((int)stiles[s].size());
     }
     hold.push_back(buf);
 }
@@ -647,6 +737,11 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
         return;
     }
     const bool fl = pipe[s] == GEMM_PIPE_FLAT;
+    if (pipe[s] == GEMM_PIPE_SKINNY && skinny_ok[s]) {
+        if (dtype == QED_FP64) launch_skinny<double>(J, Pp, dts[s], nts[s], b, st);
+        else launch_skinny<float>(J, Pp, dts[s], nts[s], b, st);
+        return;
+    }
     if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
     else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
     else if (pipe[s] == GEMM_PIPE_DMA && pipe_valid(s, GEMM_PIPE_DMA, shape[s]))
@@ -688,14 +783,14 @@ void Prof::harvest() {
 
 void Prof::report() const {
     static const char* shapes[] = {"64x64", "128x32", "32x128"};
-    static const char* pipes[] = {"loop", "flat", "dma"};
+    static const char* pipes[] = {"loop", "flat", "dma", "skinny"};
     for (const auto& kv : by_key) {
         const int st = kv.first / 16, k = kv.first % 16;
         const int sh = k % 4, pp = k / 4;
         const auto& v = kv.second;
         std::fprintf(stderr,
                      "[qedttn] gemm stage %d tile %s %s: %.0f launches, %.3f ms, %.3e flops, %.2f TFLOP/s\n", st,
-                     k == FUSED_KEY ? "fused" : (sh < 3 ? shapes[sh] : "?"), k == FUSED_KEY ? "" : pipes[pp % 3],
+                     k == FUSED_KEY ? "fused" : (sh < 3 ? shapes[sh] : "?"), k == FUSED_KEY ? "" : pipes[pp % 4],
                      v[0], v[1], v[2], v[1] > 0 ? v[2] / v[1] / 1e9 : 0.0);
     }
 }
@@ -1715,8 +1810,9 @@ void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     // wider ones up to QR_COLS columns the blocked kernel (up to QR_ROWS
     // rows), wider still the unblocked one
     std::vector<QRMat> lds, blocked, wide;
-    int64_t rows_b = 0, rows_w = 0, rows_l = 0;
-    int cols_b = 0, cols_w = 0, cols_l = 0;
+    int64_t rows_b = 0, rows_w = 0;
+    int cols_b = 0, cols_w = 0;
+    size_t lds_bytes = 0;   // the largest single matrix's need, not max rows x max cols
     std::vector<BufP> keep;
     struct Tall {
         QRTask t;
@@ -1727,8 +1823,7 @@ void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     auto add = [&](const QRMat& q) {
         if (qr_lds_fits(q.rows, q.cols)) {
             lds.push_back(q);
-            rows_l = std::max<int64_t>(rows_l, q.rows);
-            cols_l = std::max(cols_l, q.cols);
+            lds_bytes = std::max(lds_bytes, qr_lds_bytes(q.rows, q.cols));
             return;
         }
         const bool bl = q.rows <= QR_ROWS && q.cols <= QR_COLS;
@@ -1784,7 +1879,7 @@ void tsqr_multi(Dev* dev, const std::vector<QRTask>& tasks) {
     if (!lds.empty()) {
         DBuf dq(dev, lds.size() * sizeof(QRMat));
         dev->upload(dq.p, lds.data(), lds.size() * sizeof(QRMat));
-        launch_qr_lds(dq.as<QRMat>(), (int)lds.size(), rows_l, cols_l, dev->stream);
+        launch_qr_lds(dq.as<QRMat>(), (int)lds.size(), lds_bytes, dev->stream);
         dev->check(hipGetLastError(), "qr launch");
     }
     for (int kind = 0; kind < 2; ++kind) {

@@ -74,7 +74,7 @@ void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_
 // blocked kernel when every matrix has rows <= QR_ROWS and cols <= QR_COLS,
 // else the unblocked one
 void launch_qr(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_t);
-void launch_qr_lds(const QRMat*, int nmats, int64_t maxrows, int maxcols, hipStream_t);
+void launch_qr_lds(const QRMat*, int nmats, size_t lds_bytes, hipStream_t);
 void launch_site_expect(const double*, const int64_t*, const signed char*, int, double*,
                         hipStream_t);
 void launch_jacobi_svd(const SvdMat*, int nmats, hipStream_t);
@@ -99,6 +99,10 @@ void seg_ritz(double*, const double*, int64_t, const double*, int, const SegChun
 void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const double*, int,
                         double*, int64_t*, double*, hipStream_t);
 
+// skinny stages (GEMM_PIPE_SKINNY): rows per workgroup strip, and launch
+int skinny_rows(int dtype);
+template <typename T>
+void launch_skinny(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
 // FP32 block GEMM whose operands travel straight into an LDS ring
 // (GEMM_PIPE_DMA; SQUARE and WIDE tiles only)
 bool brgemm_dma_shape(int shape);
@@ -253,6 +257,9 @@ struct Plan {
     // operands it can read (dma_ok), the register-staged loop otherwise
     std::vector<char> pipe;
     std::vector<char> dma_ok;
+    std::vector<char> skinny_ok;                 // stage the skinny kernel can run
+    std::vector<const GTile*> dts;               // its strip tiles
+    std::vector<int> nts;
     // fused H_eff jobs (k_heff_fused) of each stage, launched after the
     // stage's GEMM jobs; stages without them have empty lists (the lists
     // may be shorter than `jobs`)

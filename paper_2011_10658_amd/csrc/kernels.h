@@ -132,7 +132,11 @@ constexpr int GEMM_THREADS = 256;
 // (loop), one chunk per product across the products of a job (flat), and
 // the LDS ring filled by buffer-to-LDS loads (dma: FP32, tA = tB = 0,
 // SQUARE and WIDE tiles, operands under 2^29 elements).
-enum { GEMM_PIPE_LOOP = 0, GEMM_PIPE_FLAT = 1, GEMM_PIPE_DMA = 2, GEMM_NPIPES = 3 };
+// skinny: the whole stage is A B^T products with K, N <= 64 into contiguous
+// outputs (one workgroup per row strip and the full output width).
+enum { GEMM_PIPE_LOOP = 0, GEMM_PIPE_FLAT = 1, GEMM_PIPE_DMA = 2, GEMM_PIPE_SKINNY = 3, GEMM_NPIPES = 4 };
+constexpr int SK_KMAX = 64;
+constexpr int SK_NMAX = 64;
 
 // Per-block description for packing a node tensor into the column-major
 // matrices of its sectors along one leg (QR), and back.
@@ -161,10 +165,10 @@ constexpr int QRL_CAP = 19456;
 inline bool qr_lds_fits(int64_t rows, int cols) {
     return cols <= QRL_MAXC && rows <= QR_ROWS && (rows + 1) * cols <= QRL_CAP;
 }
-// LDS of a k_qr_lds launch whose matrices have at most maxrows rows and
-// maxcols columns
-inline size_t qr_lds_bytes(int64_t maxrows, int maxcols) {
-    return (size_t)(((maxrows | 1) * maxcols) + 3 * maxcols + 4 + 512) * sizeof(double);
+// LDS that k_qr_lds needs for one rows x cols matrix (a launch takes the
+// largest over its matrices; at most 160 KiB whenever qr_lds_fits)
+inline size_t qr_lds_bytes(int64_t rows, int cols) {
+    return (size_t)(((rows | 1) * cols) + 3 * cols + 4 + 512) * sizeof(double);
 }
 
 struct QRMat {

@@ -615,6 +615,203 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ 
         }
 }
 
+// Skinny products: every product of the stage is A B^T with A the
+// contiguous M x K panel of a block (lda = K, tA = 0), B an N x K operator
+// block (ldb = K, tB = 1), K <= 64 and N <= 64, summed into a contiguous
+// M x N output (ldc = N, overwritten).  This is the mode product on the
+// parent leg: long M, short K and N, so the output written dominates.  A
+// strip of SK_RS(T) rows and the whole output width is one unit of work:
+// its output is one contiguous range of memory, staged through LDS and
+// stored fully coalesced, once.  The kernel is persistent: workgroup w
+// walks strips w, w + G, w + 2G, ... (G a multiple of 8, so a workgroup
+// stays on the XCD the strip order assigns), and the operands of its next
+// product, of this strip or the next, are fetched into registers while the
+// current one is multiplied and its output stored, so the load latency of
+// one strip hides behind the work of the previous one.  The MFMA column
+// blocks are a compile-time count per job.  The order of the sums (k
+// ascending in steps of 4, products in order) is the block GEMM's.
+template <typename T> struct SkinnyRows;
+template <> struct SkinnyRows<float> { static constexpr int BMR = 2; };
+template <> struct SkinnyRows<double> { static constexpr int BMR = 1; };
+
+template <typename T>
+struct SkinnyRegs {
+    static constexpr int RS = 64 * SkinnyRows<T>::BMR;
+    static constexpr int UA = RS * SK_KMAX / 256, UB = SK_NMAX * SK_KMAX / 256;
+    T ra[UA], rb[UB];
+};
+
+// operands of product p of job J for the strip at row m0 into registers;
+// element e of the padded strip is (r, k) = (e / Kp, e % Kp), r = e / Kp
+// exact in float for e < 2^13 (e + 1/2 is at least 1/(2 Kp) away from a
+// multiple of Kp)
+template <typename T>
+__device__ __forceinline__ void skinny_fetch(SkinnyRegs<T>& R, const GJob& J, const GProd& P, int m0,
+                                             const Bases& bases) {
+    constexpr int RS = SkinnyRegs<T>::RS;
+    const int tid = threadIdx.x;
+    const int K = P.K, Kp = (K + 3) & ~3;
+    const int rows = min(RS, J.M - m0);
+    const float inv = 1.0f / (float)Kp;
+    const T* A = resolve<T>(P.A, bases) + (int64_t)m0 * K;
+    const T* B = resolve<T>(P.B, bases);
+#pragma unroll
+    for (int u = 0; u < SkinnyRegs<T>::UA; ++u) {
+        const int e = tid + 256 * u;
+        const int r = (int)(((float)e + 0.5f) * inv), k = e - r * Kp;
+        R.ra[u] = (e < RS * Kp && r < rows && k < K) ? A[r * K + k] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < SkinnyRegs<T>::UB; ++u) {
+        const int e = tid + 256 * u;
+        const int n = (int)(((float)e + 0.5f) * inv), k = e - n * Kp;
+        R.rb[u] = (e < SK_NMAX * Kp && n < J.N && k < K) ? B[n * K + k] : (T)0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void skinny_stash(const SkinnyRegs<T>& R, int K, T* As, T* Bs) {
+    constexpr int RS = SkinnyRegs<T>::RS, LDA = SK_KMAX + 1;
+    const int tid = threadIdx.x;
+    const int Kp = (K + 3) & ~3;
+    const float inv = 1.0f / (float)Kp;
+#pragma unroll
+    for (int u = 0; u < SkinnyRegs<T>::UA; ++u) {
+        const int e = tid + 256 * u;
+        const int r = (int)(((float)e + 0.5f) * inv), k = e - r * Kp;
+        if (e < RS * Kp) As[r * LDA + k] = R.ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < SkinnyRegs<T>::UB; ++u) {
+        const int e = tid + 256 * u;
+        const int n = (int)(((float)e + 0.5f) * inv), k = e - n * Kp;
+        if (e < SK_NMAX * Kp) Bs[n * LDA + k] = R.rb[u];
+    }
+}
+
+// one strip of job J; on return the registers hold the operands of the
+// next strip's first product (job Jn at row mn), if there is one
+template <typename T, int NB>
+__device__ __forceinline__ void skinny_strip(const GJob& J, int m0, const GProd* __restrict__ prods,
+                                             const Bases& bases, SkinnyRegs<T>& R, bool has_next,
+                                             const GJob& Jn, int mn, T* As, T* Bs) {
+    typedef typename Mfma<T>::v4 v4;
+    constexpr int BMR = SkinnyRows<T>::BMR;
+    constexpr int LDA = SK_KMAX + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4 acc[BMR][NB];
+#pragma unroll
+    for (int i = 0; i < BMR; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    for (int p = J.p0; p < J.p1; ++p) {
+        const GProd P = prods[p];
+        __syncthreads();   // the LDS stage is no longer read (previous product or output strip)
+        skinny_stash<T>(R, P.K, As, Bs);
+        __syncthreads();
+        if (p + 1 < J.p1) skinny_fetch<T>(R, J, prods[p + 1], m0, bases);
+        else if (has_next) skinny_fetch<T>(R, Jn, prods[Jn.p0], mn, bases);
+        const int Kp = (P.K + 3) & ~3;
+        const T alpha = (T)P.alpha;
+        for (int kk = 0; kk < Kp; kk += 4) {
+            const int k = kk + lk;
+            T a[BMR], b[NB];
+#pragma unroll
+            for (int i = 0; i < BMR; ++i) a[i] = As[(wave * 16 * BMR + i * 16 + lr) * LDA + k] * alpha;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) b[j] = Bs[(j * 16 + lr) * LDA + k];
+#pragma unroll
+            for (int i = 0; i < BMR; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::step(a[i], b[j], acc[i][j]);
+        }
+    }
+    // the output strip through LDS (it fits in the A stage), then stored as
+    // one contiguous range
+    __syncthreads();
+    T* Cs = As;
+    const int N = J.N;
+#pragma unroll
+    for (int i = 0; i < BMR; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int col = j * 16 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = wave * 16 * BMR + i * 16 + Mfma<T>::row(lane, e);
+                if (col < N) Cs[row * N + col] = acc[i][j][e];
+            }
+        }
+    __syncthreads();
+    const int rows = min(64 * BMR, J.M - m0);
+    T* C = resolve<T>(J.C, bases) + (int64_t)m0 * N;
+    const int tot = rows * N;
+#pragma unroll 8
+    for (int e = tid; e < tot; e += 256) C[e] = Cs[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_skinny(const GJob* __restrict__ jobs, const GProd* __restrict__ prods,
+                                                const GTile* __restrict__ tiles, int ntiles, Bases bases) {
+    constexpr int RS = SkinnyRegs<T>::RS, LDA = SK_KMAX + 1;
+    __shared__ T As[RS * LDA];
+    __shared__ T Bs[SK_NMAX * LDA];
+    const int G = gridDim.x;
+    auto next_real = [&](int i) {
+        while (i < ntiles && tiles[i].job < 0) i += G;
+        return i;
+    };
+    int i = next_real(blockIdx.x);
+    if (i >= ntiles) return;
+    SkinnyRegs<T> R;
+    {
+        const GJob J0 = jobs[tiles[i].job];
+        skinny_fetch<T>(R, J0, prods[J0.p0], tiles[i].tm * RS, bases);
+    }
+    while (i < ntiles) {
+        const GTile tl = tiles[i];
+        const GJob J = jobs[tl.job];
+        const int in = next_real(i + G);
+        const bool has_next = in < ntiles;
+        const GJob Jn = jobs[has_next ? tiles[in].job : tl.job];
+        const int mn = has_next ? tiles[in].tm * RS : 0;
+        const int m0 = tl.tm * RS;
+        switch ((J.N + 15) >> 4) {
+            case 1: skinny_strip<T, 1>(J, m0, prods, bases, R, has_next, Jn, mn, As, Bs); break;
+            case 2: skinny_strip<T, 2>(J, m0, prods, bases, R, has_next, Jn, mn, As, Bs); break;
+            case 3: skinny_strip<T, 3>(J, m0, prods, bases, R, has_next, Jn, mn, As, Bs); break;
+            default: skinny_strip<T, 4>(J, m0, prods, bases, R, has_next, Jn, mn, As, Bs); break;
+        }
+        i = in;
+    }
+}
+
+int skinny_rows(int dtype) { return dtype == QED_FP64 ? 64 * SkinnyRows<double>::BMR : 64 * SkinnyRows<float>::BMR; }
+
+// workgroups of a persistent skinny launch: as many as are resident at once
+// (the occupancy of the kernel on this device, queried once), a multiple
+// of 8, so that no workgroup starts after another has finished its list
+template <typename T>
+void launch_skinny(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles, const Bases& bases,
+                   hipStream_t st) {
+    if (ntiles <= 0) return;
+    static const int resident = [] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_skinny<T>, 256, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+            cus = 8;
+        return per_cu * cus;
+    }();
+    int g = std::min(ntiles, resident);
+    g = std::max(8, g & ~7);
+    hipLaunchKernelGGL(k_skinny<T>, dim3(g), dim3(256), 0, st, jobs, prods, tiles, ntiles, bases);
+}
+template void launch_skinny<float>(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
+template void launch_skinny<double>(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
+
 bool brgemm_dma_shape(int shape) { return shape == GEMM_SHAPE_SQUARE || shape == GEMM_SHAPE_WIDE; }
 
 void launch_brgemm_dma(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
@@ -2067,9 +2264,8 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QRMat* __restrict__ mats) 
     }
 }
 
-void launch_qr_lds(const QRMat* mats, int nmats, int64_t maxrows, int maxcols, hipStream_t s) {
+void launch_qr_lds(const QRMat* mats, int nmats, size_t lds, hipStream_t s) {
     if (nmats <= 0) return;
-    const size_t lds = qr_lds_bytes(maxrows, maxcols);
     (void)hipFuncSetAttribute((const void*)k_qr_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_qr_lds, dim3(nmats), dim3(256), lds, s, mats);
 }

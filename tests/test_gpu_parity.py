@@ -517,14 +517,16 @@ def bottom_node(ctx):
 
 
 @pytest.mark.parametrize("plan,pipeline", [("fused", None), ("staged", None), ("staged", "flat"),
-                                           ("staged", "loop")])
+                                           ("staged", "loop"), ("staged", "dma"), ("staged", "skinny")])
 @pytest.mark.parametrize("dtype", [lib.FP64, lib.FP32])
 def test_bench_bottom_node_matvec(ctx, bottom_node, dtype, plan, pipeline, monkeypatch):
     """H_eff application at the benchmark's bottom-node shape, element by
     element against the oracle: with the fused stages (terms with a
     bond-leg factor applied per output tile), and with three mode-product
-    stages, their GEMM pipeline chosen per stage or forced to either
-    pipeline on every stage.  FP64: 1e-13 of max|y|.
+    stages, their GEMM pipeline chosen per stage or forced to one pipeline
+    on every stage that allows it (register-staged loop, flat, LDS-DMA ring
+    for FP32, skinny strips for the parent-leg stage).  FP64: 1e-13 of
+    max|y|.
     FP32: 2e-6 of max|y|, and every element within the first-order
     worst-case bound (4 input roundings, 2 stored intermediates, the three
     reduction lengths and the term sum) times u = 2^-24 of the same
@@ -657,6 +659,28 @@ def _parent_isometry_error(ctx, n):
         B = x[offs[b]:offs[b + 1]].reshape(l[il][1] * r[ir][1], p[ip][1])
         gram[ip] += B.T @ B
     return max(np.abs(G - np.eye(G.shape[0])).max() for G in gram.values())
+
+
+def test_qr_every_node_of_finite_density_tree(ctx):
+    """Isometrising the 4x4x4 free-flux tree at chi = 256 with Q = +8 (the
+    finite-density set-up; every node moved toward the root once).  Its
+    legs mix sectors of 1 to ~100 columns with 10^2 to 10^5 rows, so one QR
+    launch holds tall narrow row chunks beside short wide sectors (the LDS
+    each needs differs by an order of magnitude).  Every node must come out
+    an isometry toward its parent to 1e-12."""
+    g2e, g2m = lib.physical_line(1.0, 1.0)
+    ctx.set_lattice(4, 4, 4, lib.BC_OPEN_FREE_FLUX)
+    ctx.set_couplings(1.0, 1.0, g2e, g2m)
+    ctx.set_charge_sector(8)
+    ctx.set_bond_dim(256)
+    ctx.set_penalty(40.0, 0, 0)
+    ctx.set_precision(lib.FP64)
+    ctx.build_hamiltonian()
+    ctx.init_state(2011)
+    ctx.observables()            # isometrises every node toward the root
+    nn, _ = ctx.tree()
+    worst = max(_parent_isometry_error(ctx, n) for n in range(nn - 1))
+    assert worst < 1e-12, worst
 
 
 @pytest.mark.parametrize("qr", ["cholesky", "householder"])
