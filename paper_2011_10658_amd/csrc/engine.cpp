@@ -479,7 +479,8 @@ static std::vector<GTile> make_sum_tiles(const std::vector<GJob>& jobs) {
 // pipeline on every stage of the plans built afterwards (dma or skinny
 // where a stage allows it, loop elsewhere); =nodma chooses as by default
 // without the dma pipeline; anything else (or unset) chooses per stage:
-// flat for short mean reductions, else dma where allowed, else loop.  The
+// flat for short mean reductions, else dma where an FP32 stage allows it,
+// else loop.  The
 // skinny pipeline is not chosen by default: on the d = 267 bottom nodes
 // its stage (180 MB of per-term intermediates written per product) runs
 // at the flat pipeline's rate or below; the autotuner may still pick it.
@@ -494,11 +495,11 @@ static int forced_pipeline() {
     return -1;
 }
 
-// The LDS-DMA pipeline reads FP32 operands with tA = tB = 0 through 32-bit
-// byte offsets: every offset a tile forms (rows and reduction chunks padded
-// to the tile) must stay below 2^31 bytes.
-static bool dma_operands_ok(const std::vector<GJob>& jobs, const std::vector<GProd>& prods) {
-    const int64_t LIM = (int64_t)1 << 29;
+// The LDS-DMA pipeline reads FP32 or FP64 operands with tA = tB = 0 through
+// 32-bit byte offsets: every offset a tile forms (rows and reduction chunks
+// padded to the tile) must stay below 2^31 bytes.
+static bool dma_operands_ok(int esize, const std::vector<GJob>& jobs, const std::vector<GProd>& prods) {
+    const int64_t LIM = ((int64_t)1 << 31) / esize;
     bool any = false;
     for (const GJob& J : jobs)
         for (int p = J.p0; p < J.p1; ++p) {
@@ -537,7 +538,7 @@ static bool skinny_operands_ok(int dtype, const std::vector<GJob>& jobs, const s
 bool Plan::pipe_valid(size_t s, int pp, int sh) const {
     if (pp == GEMM_PIPE_SKINNY) return skinny_ok[s] != 0;
     if (pp != GEMM_PIPE_DMA) return pp == GEMM_PIPE_LOOP || pp == GEMM_PIPE_FLAT;
-    return dtype == QED_FP32 && dma_ok[s] && brgemm_dma_shape(sh);
+    return (dtype == QED_FP32 || dtype == QED_FP64) && dma_ok[s] && brgemm_dma_shape(sh);
 }
 
 // QEDTTN_HEFF_FUSED=1 plans the terms with a bond-leg factor of every FP32
@@ -574,7 +575,10 @@ void Plan::upload(Dev* dev) {
                 kn += 1.0;
             }
         sumk.push_back(only_ident ? 1 : 0);
-        dma_ok.push_back(dtype == QED_FP32 && !only_ident && dma_operands_ok(jobs[s], prods[s]) ? 1 : 0);
+        dma_ok.push_back((dtype == QED_FP32 || dtype == QED_FP64) && !only_ident &&
+                                 dma_operands_ok(dtype_size(dtype), jobs[s], prods[s])
+                             ? 1
+                             : 0);
         skinny_ok.push_back(!only_ident && skinny_operands_ok(dtype, jobs[s], prods[s]) ? 1 : 0);
         stiles.push_back(skinny_ok.back() ? make_skinny_tiles(jobs[s], prods[s], skinny_rows(dtype))
                                           : std::vector<GTile>());
@@ -598,7 +602,11 @@ void Plan::upload(Dev* dev) {
         // ones through the LDS ring where the stage allows it (the
         // environment may force one pipeline, to compare them on one plan)
         const int forced = forced_pipeline();
-        int pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT : GEMM_PIPE_DMA;
+        // (the FP64 ring is no faster than the register-staged loop on the
+        // benchmark's node: two 4-byte loads per element, half the
+        // occupancy; it stays a forced or tuned choice)
+        int pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT
+                                              : (dtype == QED_FP32 ? GEMM_PIPE_DMA : GEMM_PIPE_LOOP);
         if (forced >= 0) pp = forced;
         if (forced == -2 && pp == GEMM_PIPE_DMA) pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT : GEMM_PIPE_LOOP;
         if (!pipe_valid(s, pp, best)) pp = GEMM_PIPE_LOOP;
@@ -742,8 +750,12 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
         else launch_skinny<float>(J, Pp, dts[s], nts[s], b, st);
         return;
     }
-    if (dtype == QED_FP64) launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
-    else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
+    if (dtype == QED_FP64) {
+        if (pipe[s] == GEMM_PIPE_DMA && pipe_valid(s, GEMM_PIPE_DMA, shape[s]))
+            launch_brgemm_dma64(J, Pp, T, ntiles[s], b, shape[s], st);
+        else
+            launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
+    } else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
     else if (pipe[s] == GEMM_PIPE_DMA && pipe_valid(s, GEMM_PIPE_DMA, shape[s]))
         launch_brgemm_dma(J, Pp, T, ntiles[s], b, shape[s], st);
     else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], fl, st);

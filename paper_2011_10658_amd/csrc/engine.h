@@ -103,10 +103,11 @@ void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const do
 int skinny_rows(int dtype);
 template <typename T>
 void launch_skinny(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
-// FP32 block GEMM whose operands travel straight into an LDS ring
-// (GEMM_PIPE_DMA; SQUARE and WIDE tiles only)
+// FP32 and FP64 block GEMMs whose operands travel straight into an LDS
+// ring (GEMM_PIPE_DMA; SQUARE and WIDE tiles only)
 bool brgemm_dma_shape(int shape);
 void launch_brgemm_dma(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape, hipStream_t);
+void launch_brgemm_dma64(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape, hipStream_t);
 void launch_brgemm_bf16(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape,
                         hipStream_t);
 void launch_f64_to_bf16(const double*, void*, int64_t, hipStream_t);

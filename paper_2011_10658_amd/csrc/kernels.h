@@ -130,8 +130,8 @@ constexpr int GEMM_THREADS = 256;
 
 // Operand pipelines of the block GEMM: register-staged double buffer
 // (loop), one chunk per product across the products of a job (flat), and
-// the LDS ring filled by buffer-to-LDS loads (dma: FP32, tA = tB = 0,
-// SQUARE and WIDE tiles, operands under 2^29 elements).
+// the LDS ring filled by buffer-to-LDS loads (dma: FP32 and FP64, tA = tB =
+// 0, SQUARE and WIDE tiles, operands under 2^31 bytes).
 // skinny: the whole stage is A B^T products with K, N <= 64 into contiguous
 // outputs (one workgroup per row strip and the full output width).
 enum { GEMM_PIPE_LOOP = 0, GEMM_PIPE_FLAT = 1, GEMM_PIPE_DMA = 2, GEMM_PIPE_SKINNY = 3, GEMM_NPIPES = 4 };

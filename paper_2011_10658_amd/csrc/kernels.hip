@@ -812,7 +812,185 @@ void launch_skinny(const GJob* jobs, const GProd* prods, const GTile* tiles, int
 template void launch_skinny<float>(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
 template void launch_skinny<double>(const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
 
+// FP64 instance of the LDS-DMA ring (same contract and pipeline as
+// k_brgemm_dma): every double travels as two 4-byte buffer-to-LDS loads,
+// so each lane addresses exactly one half of one element (the middle-leg
+// products split their columns at odd strides, so two adjacent doubles
+// need not be adjacent in memory).  LDS layouts, in doubles:
+//   A: element (m, k) at (m / 2) 34 + (m % 2) 16 + k; one instruction fills
+//      two rows of 16 k (64 words) and the pad of 2 doubles per row pair
+//      spreads the 16 rows an MFMA operand read touches over the banks;
+//   B: element (k, n) at k (TN + 16) + n; one instruction fills 32 n of a
+//      row.
+template <int WM, int WN, int BM, int BN, int NS>
+__global__ __launch_bounds__(256, 2) void k_brgemm_dma64(const GJob* __restrict__ jobs,
+                                                       const GProd* __restrict__ prods,
+                                                       const GTile* __restrict__ tiles, Bases bases) {
+    typedef Mfma<double>::v4 v4;
+    constexpr int KC = 16;
+    constexpr int TM = 16 * WM * BM, TN = 16 * WN * BN;
+    static_assert(TN % 32 == 0 && TM % 8 == 0, "tile shape");
+    constexpr int A_SLOT = (TM / 2) * 34;
+    constexpr int LDB = TN + 16;
+    constexpr int B_SLOT = KC * LDB;
+    constexpr int SLOT = A_SLOT + B_SLOT;
+    constexpr int IA = TM / 8;            // A load instructions per wave and chunk
+    constexpr int HS = TN / 32;           // B instructions per row
+    constexpr int IB = KC * HS / 4;       // B load instructions per wave and chunk
+    constexpr int V = IA + IB;
+    constexpr int D = NS - 1;
+    __shared__ double lds[NS * SLOT];
+    const GTile tl = tiles[blockIdx.x];
+    if (tl.job < 0) return;
+    const GJob J = jobs[tl.job];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave / WN) * 16 * BM;
+    const int wn0 = (wave % WN) * 16 * BN;
+    const int m0 = tl.tm * TM;
+    const int n0 = tl.tn * TN;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4 acc[BM][BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) acc[i][j] = v4{0, 0, 0, 0};
+    // this lane's word of an A instruction: row pair half (lane / 32), the
+    // double lane % 32 / 2 of that row, half lane % 2
+    const int ah = lane >> 5, ak = (lane & 31) >> 1, aw = lane & 1;
+    int arow[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const int m = wm0 + i * 16 + lr;
+        arow[i] = (m >> 1) * 34 + (m & 1) * 16;
+    }
+    for (int p = J.p0; p < J.p1; ++p) {
+        const GProd P = prods[p];
+        const double* Bb = resolve<double>(P.B, bases) + (int64_t)tl.b * P.bsB;
+        if (P.ident) {
+            const double alpha = P.alpha;
+#pragma unroll
+            for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < BN; ++bj) {
+                    const int col = n0 + wn0 + bj * 16 + lr;
+                    const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = m0 + wm0 + bi * 16 + Mfma<double>::row(lane, i);
+                        if (row < J.M && col < J.N) acc[bi][bj][i] += alpha * Bb[(int64_t)row * P.ldb + co];
+                    }
+                }
+            continue;
+        }
+        const double* Ab = resolve<double>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        const double alpha = P.alpha;
+        const int nchunk = (P.K + KC - 1) / KC;
+        // byte offsets of this lane's words relative to the chunk's first
+        // row (B) or column (A), fixed for the product
+        uint32_t boff[IB];
+        bool bok[IB];
+        const int brow0 = wave * (KC / 4);
+#pragma unroll
+        for (int j = 0; j < IB; ++j) {
+            const int n = n0 + (j % HS) * 32 + (lane >> 1);
+            const int row = brow0 + j / HS;
+            bok[j] = n < J.N;
+            const int co = P.nsb ? (n / P.nsb) * (int)P.nob + n % P.nsb : n;
+            boff[j] = 8u * (uint32_t)(row * P.ldb + co) + 4u * (uint32_t)(lane & 1);
+        }
+        uint32_t aoff[IA];
+        bool aok[IA];
+#pragma unroll
+        for (int j = 0; j < IA; ++j) {
+            const int m = m0 + 2 * (wave * IA + j) + ah;
+            aok[j] = m < J.M;
+            aoff[j] = 8u * (uint32_t)(m * P.lda + ak) + 4u * (uint32_t)aw;
+        }
+        for (int r = 0; r < P.nred; ++r) {
+            const __amdgpu_buffer_rsrc_t ra =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(Ab + (int64_t)r * P.rsA), (short)0, 0x7fffffff, DMA_RSRC_W3);
+            const __amdgpu_buffer_rsrc_t rb =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(Bb + (int64_t)r * P.rsB), (short)0, 0x7fffffff, DMA_RSRC_W3);
+            auto issue = [&](int c) {
+                double* slot = lds + (c % NS) * SLOT;
+                const int k0 = c * KC;
+                const bool kin = k0 + ak < P.K;
+#pragma unroll
+                for (int j = 0; j < IA; ++j) {
+                    const uint32_t o = (aok[j] && kin) ? aoff[j] + 8u * (uint32_t)k0 : DMA_OOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, QED_LDS_PTR(slot + (wave * IA + j) * 34), 4, o, 0, 0,
+                                                             0);
+                }
+                const uint32_t kb = 8u * (uint32_t)(k0 * P.ldb);
+#pragma unroll
+                for (int j = 0; j < IB; ++j) {
+                    const int row = brow0 + j / HS, h = j % HS;
+                    const uint32_t o = (bok[j] && k0 + row < P.K) ? boff[j] + kb : DMA_OOB;
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, QED_LDS_PTR(slot + A_SLOT + row * LDB + h * 32), 4, o,
+                                                             0, 0, 0);
+                }
+            };
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                if (c < nchunk) issue(c);
+            for (int c = 0; c < nchunk; ++c) {
+                const int after = nchunk - 1 - c < D - 1 ? nchunk - 1 - c : D - 1;
+                if (after >= 2) __builtin_amdgcn_s_waitcnt(VmWait<2 * V>::imm);
+                else if (after == 1) __builtin_amdgcn_s_waitcnt(VmWait<V>::imm);
+                else __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
+                __builtin_amdgcn_s_barrier();
+                if (c + D < nchunk) issue(c + D);
+                const double* As = lds + (c % NS) * SLOT;
+                const double* Bs = As + A_SLOT;
+#pragma unroll
+                for (int kk = 0; kk < KC; kk += 4) {
+                    double a[BM], bb[BN];
+                    const int k = kk + lk;
+#pragma unroll
+                    for (int i = 0; i < BM; ++i) a[i] = As[arow[i] + k] * alpha;
+#pragma unroll
+                    for (int j = 0; j < BN; ++j) bb[j] = Bs[k * LDB + wn0 + j * 16 + lr];
+#pragma unroll
+                    for (int i = 0; i < BM; ++i)
+#pragma unroll
+                        for (int j = 0; j < BN; ++j) acc[i][j] = Mfma<double>::step(a[i], bb[j], acc[i][j]);
+                }
+            }
+        }
+    }
+    double* C = resolve<double>(J.C, bases) + (int64_t)tl.b * J.bsC;
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BN; ++bj) {
+            const int col = n0 + wn0 + bj * 16 + lr;
+            const int64_t co = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + wm0 + bi * 16 + Mfma<double>::row(lane, i);
+                if (row < J.M && col < J.N) {
+                    double* c = C + (int64_t)row * J.ldc + co;
+                    *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
+                }
+            }
+        }
+}
+
 bool brgemm_dma_shape(int shape) { return shape == GEMM_SHAPE_SQUARE || shape == GEMM_SHAPE_WIDE; }
+
+void launch_brgemm_dma64(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
+                         const Bases& bases, int shape, hipStream_t st) {
+    if (ntiles <= 0) return;
+    if (shape == GEMM_SHAPE_WIDE)
+        hipLaunchKernelGGL((k_brgemm_dma64<1, 4, 2, 2, 3>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles,
+                           bases);
+    else
+        hipLaunchKernelGGL((k_brgemm_dma64<2, 2, 2, 2, 3>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles,
+                           bases);
+}
 
 void launch_brgemm_dma(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
                        const Bases& bases, int shape, hipStream_t st) {
