@@ -41,6 +41,7 @@ void SegLanczos::setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t NN
     alpha = std::make_shared<DBuf>(dev, ps);
     beta = std::make_shared<DBuf>(dev, ps);
     coef = std::make_shared<DBuf>(dev, ps);
+    coef2 = std::make_shared<DBuf>(dev, ps);
     sv = std::make_shared<DBuf>(dev, ps);
     work = std::make_shared<DBuf>(dev, (size_t)nseg * 256 * sizeof(double));
     st = std::make_shared<DBuf>(dev, (size_t)nseg * sizeof(LState));
@@ -60,6 +61,7 @@ void SegLanczos::cycle(const std::function<void(const double*, double*)>& apply,
     double* al = alpha->as<double>();
     double* be = beta->as<double>();
     double* co = coef->as<double>();
+    double* co2 = coef2->as<double>();
     double* part = partial->as<double>();
     double* nr = nrm->as<double>();
     LState* sp = st->as<LState>();
@@ -70,12 +72,21 @@ void SegLanczos::cycle(const std::function<void(const double*, double*)>& apply,
         double* vj = Vp + (int64_t)j * N;
         apply(vj, wp);
         seg_dots(vj, N, 1, wp, ch, nch, c0, nseg, part, al + j, LDS, 0, sp, 1, s);
-        seg_three_term(wp, Vp, N, j, al, be, LDS, ch, nch, sp, s);
-        for (int pass = 0; pass < 2; ++pass) {
-            seg_dots(Vp, N, j + 1, wp, ch, nch, c0, nseg, part, co, LDS, 0, sp, 1, s);
-            seg_subtract(wp, Vp, N, j + 1, co, LDS, ch, nch, sp, s);
+        // three-term recurrence, classical Gram-Schmidt against V with a
+        // second pass where a segment's first one removed more than half
+        // of |w|^2, norm: three fused passes over the basis
+        if (seg_fused(0, wp, Vp, N, 0, j, al, be, LDS, nullptr, nullptr, ch, nch, c0, nseg, part, co, LDS, sp,
+                      s)) {
+            seg_fused(1, wp, Vp, N, j + 1, j, al, be, LDS, co, co, ch, nch, c0, nseg, part, co2, LDS, sp, s);
+            seg_fused(2, wp, Vp, N, j + 1, j, al, be, LDS, co2, co, ch, nch, c0, nseg, part, nr + 1, LDN, sp, s);
+        } else {
+            seg_three_term(wp, Vp, N, j, al, be, LDS, ch, nch, sp, s);
+            for (int pass = 0; pass < 2; ++pass) {
+                seg_dots(Vp, N, j + 1, wp, ch, nch, c0, nseg, part, co, LDS, 0, sp, 1, s);
+                seg_subtract(wp, Vp, N, j + 1, co, LDS, ch, nch, sp, s);
+            }
+            seg_dots(wp, N, 1, wp, ch, nch, c0, nseg, part, nr + 1, LDN, 0, sp, 1, s);
         }
-        seg_dots(wp, N, 1, wp, ch, nch, c0, nseg, part, nr + 1, LDN, 0, sp, 1, s);
         seg_beta(nr + 1, LDN, al, be, LDS, j, sp, nseg, 1e-14, s);
         seg_next(Vp, N, j, wp, be, LDS, ch, nch, sp, s);
     }

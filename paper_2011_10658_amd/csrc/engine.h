@@ -86,6 +86,13 @@ void seg_dots(const double*, int64_t, int, const double*, const SegChunk*, int, 
               double*, double*, int, int, const LState*, int, hipStream_t);
 void seg_init(LState*, int, int, const double*, int, hipStream_t);
 void seg_start(double*, const double*, const double*, int, const SegChunk*, int, hipStream_t);
+// one fused pass of a Lanczos step per segment (mode 0, 1, 2 as in
+// launch_lz_fused), with its final sums into out[seg * ldo + r]; false
+// (nothing launched) when the pass would need more than 32 rows
+bool seg_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j, const double* al,
+               const double* be, int lds, const double* c, const double* cf, const SegChunk* ch, int nch,
+               const int* seg_c0, int nseg, double* partial, double* out, int ldo, const LState* st,
+               hipStream_t s);
 void seg_three_term(double*, const double*, int64_t, int, const double*, const double*, int,
                     const SegChunk*, int, const LState*, hipStream_t);
 void seg_subtract(double*, const double*, int64_t, int, const double*, int, const SegChunk*, int,
@@ -520,7 +527,7 @@ struct SegLanczos {
     static constexpr int LDN = 8;    // per-segment norm slots
     int nseg = 0, nch = 0, m = 0;
     int64_t N = 0;
-    BufP chunks, seg_c0, V, w, alpha, beta, coef, sv, work, st, partial, pv, pi, nrm, fac;
+    BufP chunks, seg_c0, V, w, alpha, beta, coef, coef2, sv, work, st, partial, pv, pi, nrm, fac;
     void setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t N, int m);
     // enqueue one cycle on `s` (no host synchronisation: capturable)
     void cycle(const std::function<void(const double*, double*)>& apply, double* x, hipStream_t s);

@@ -149,6 +149,101 @@ __global__ void k_s_next(double* __restrict__ V, int64_t ldv, int j, const doubl
     for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) v[i] = w[i] * inv;
 }
 
+// Fused vector update + dot products of one Lanczos step, segment by
+// segment, one pass over the basis (each chunk's basis entries stay in
+// registers between the update and the dots; rows <= MAXR):
+//   mode 0: w -= alpha_j v_j + beta_{j-1} v_{j-1}, then partials of V[r].w,
+//           r <= j, and of w.w (row j + 1)
+//   mode 1: w -= sum_{r < nrows} c[r] V[r], then, where the segment needs a
+//           second Gram-Schmidt pass, partials of V[r].w, r < nrows;
+//           otherwise the partial of w.w in row 0
+//   mode 2: where the second pass is needed, w -= sum_r c[r] V[r] and the
+//           partial of w.w; otherwise the segment's first chunk forwards
+//           c[0] (the norm from mode 1) and the others write 0
+// The second pass follows the criterion of Daniel, Gragg, Kaufman and
+// Stewart (Math. Comp. 30, 1976): with a = |w|^2 before the projection and
+// p = sum_r c_r^2 the squared length it removed, the projection is
+// repeated only when 2 p > a; every chunk of a segment evaluates it from
+// the segment's mode-0 coefficients `cf` (a in entry nrows) with the same
+// arithmetic, so a segment takes one decision.  Partials go to
+// partial[r * nch + chunk], the layout k_sdot_final sums.
+__device__ __forceinline__ bool s_second_pass(const double* cf, int nrows) {
+    double p = 0.0;
+    for (int r = 0; r < nrows; ++r) p += cf[r] * cf[r];
+    return 2.0 * p > cf[nrows];
+}
+
+template <int MAXR>
+__global__ __launch_bounds__(256) void k_s_fused(double* __restrict__ w, const double* __restrict__ V,
+                                                 int64_t ldv, int mode, int nrows, int j,
+                                                 const double* __restrict__ alpha,
+                                                 const double* __restrict__ beta, int lds,
+                                                 const double* __restrict__ c,
+                                                 const double* __restrict__ cf,
+                                                 const SegChunk* __restrict__ ch, int nch,
+                                                 const int* __restrict__ seg_c0,
+                                                 double* __restrict__ partial, const LState* st) {
+    const SegChunk C = ch[blockIdx.x];
+    if (st[C.seg].broken) return;
+    __shared__ double sh[MAXR][4];
+    const double* cs = mode == 0 ? nullptr : c + (int64_t)C.seg * lds;
+    const double* cfs = mode == 0 ? nullptr : cf + (int64_t)C.seg * lds;
+    const bool second = mode == 0 || s_second_pass(cfs, nrows);
+    if (mode == 2 && !second) {
+        if (threadIdx.x == 0) partial[blockIdx.x] = (int)blockIdx.x == seg_c0[C.seg] ? cs[0] : 0.0;
+        return;
+    }
+    const int nr = mode == 0 ? j + 1 : nrows;                // rows in the update / dots
+    const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;   // partial rows written
+    const bool norm_only = mode == 2 || !second;
+    const double a = mode == 0 ? alpha[(int64_t)C.seg * lds + j] : 0.0;
+    const double b = (mode == 0 && j > 0) ? beta[(int64_t)C.seg * lds + j - 1] : 0.0;
+    double s[MAXR];
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) s[q] = 0.0;
+    for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) {
+        double v[MAXR];
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) v[r] = r < nr ? V[(int64_t)r * ldv + i] : 0.0;
+        double wi = w[i];
+        if (mode == 0) {
+            double t = a * V[(int64_t)j * ldv + i];
+            if (j > 0) t += b * V[(int64_t)(j - 1) * ldv + i];
+            wi -= t;
+        } else {
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r < nr) t += cs[r] * v[r];
+            wi -= t;
+        }
+        w[i] = wi;
+        if (norm_only) {
+            s[0] += wi * wi;
+        } else {
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+                if (r < nr) s[r] += v[r] * wi;
+            if (mode == 0) {
+#pragma unroll
+                for (int r = 0; r < MAXR; ++r)
+                    if (r == nr) s[r] += wi * wi;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) {
+        if (q < nd) {
+            const double t = seg_wave_sum(s[q]);
+            if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = t;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nd)
+        partial[(int64_t)threadIdx.x * nch + blockIdx.x] =
+            ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
+}
+
 // lowest eigenpair of each segment's tridiagonal; one thread per segment
 __global__ void k_s_tridiag(const double* alpha, const double* beta, int lds, double* sv,
                             LState* st, double* work, int nseg) {
@@ -317,6 +412,23 @@ void seg_dots(const double* V, int64_t ldv, int nrows, const double* w, const Se
                        partial, st, skip);
     hipLaunchKernelGGL(k_sdot_final, dim3(nseg * nrows), dim3(256), 0, s, partial, nch, seg_c0,
                        nrows, out, ldo, mode, st, skip);
+}
+bool seg_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j, const double* al,
+               const double* be, int lds, const double* c, const double* cf, const SegChunk* ch, int nch,
+               const int* seg_c0, int nseg, double* partial, double* out, int ldo, const LState* st,
+               hipStream_t s) {
+    const int nr = mode == 0 ? j + 1 : nrows;
+    if (nr + 1 > 32) return false;   // mode 0 also needs the row of w.w
+    if (nr + 1 <= 16)
+        hipLaunchKernelGGL(k_s_fused<16>, dim3(nch), dim3(256), 0, s, w, V, ldv, mode, nrows, j, al, be, lds, c,
+                           cf, ch, nch, seg_c0, partial, st);
+    else
+        hipLaunchKernelGGL(k_s_fused<32>, dim3(nch), dim3(256), 0, s, w, V, ldv, mode, nrows, j, al, be, lds, c,
+                           cf, ch, nch, seg_c0, partial, st);
+    const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;
+    hipLaunchKernelGGL(k_sdot_final, dim3(nseg * nd), dim3(256), 0, s, partial, nch, seg_c0, nd, out, ldo, 0,
+                       st, 1);
+    return true;
 }
 void seg_init(LState* st, int nseg, int m, const double* nrm, int ldn, hipStream_t s) {
     hipLaunchKernelGGL(k_s_init, dim3((nseg + 63) / 64), dim3(64), 0, s, st, nseg, m, nrm, ldn);
