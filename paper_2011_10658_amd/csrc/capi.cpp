@@ -974,7 +974,7 @@ int qed_heff_lanczos(qed_heff* h, double* x, int steps, double* eval, double* re
         const int m = steps > 0 ? steps : P.lz_steps;
         if (m > 64) fail(QED_ERR_INVALID_ARG, "at most 64 Lanczos steps");
         LanczosResult R = lanczos(&H.ctx->dev, H.lws,
-                                  [&](const double* v, double* w, double*, bool) {
+                                  [&](const double* v, const float*, double* w, double*) {
                                       H.matvec(v, w);
                                       return false;
                                   },

@@ -15,6 +15,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <chrono>
@@ -1958,32 +1959,39 @@ void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t
 // ---------------------------------------------------------------------
 // Lanczos (Methods, step (ii)), FP64 on the device
 // ---------------------------------------------------------------------
-void LanczosWS::ensure(Dev* dev, int mm, int64_t nn) {
-    if (V && m >= mm && n >= nn) return;
-    m = std::max(mm, m);
-    n = std::max(nn, n);
-    const int G = dot_grid(n);
-    V = std::make_shared<DBuf>(dev, (size_t)(m + 1) * n * sizeof(double));
-    w = std::make_shared<DBuf>(dev, n * sizeof(double));
-    alpha = std::make_shared<DBuf>(dev, 72 * sizeof(double));
-    beta = std::make_shared<DBuf>(dev, 72 * sizeof(double));
-    coef = std::make_shared<DBuf>(dev, 144 * sizeof(double));   // two passes of coefficients
-    partial = std::make_shared<DBuf>(dev, (size_t)72 * G * sizeof(double));
-    sv = std::make_shared<DBuf>(dev, 72 * sizeof(double));
-    work = std::make_shared<DBuf>(dev, 256 * sizeof(double));
-    st = std::make_shared<DBuf>(dev, sizeof(LState));
-    pv = std::make_shared<DBuf>(dev, 512 * sizeof(double));
-    pi = std::make_shared<DBuf>(dev, 512 * sizeof(int64_t));
-    scal = std::make_shared<DBuf>(dev, 8 * sizeof(double));
+void LanczosWS::ensure(Dev* dev, int mm, int64_t nn, bool b32) {
+    if (!w || m < mm || n < nn) {
+        m = std::max(mm, m);
+        n = std::max(nn, n);
+        const int G = dot_grid(n);
+        w = std::make_shared<DBuf>(dev, n * sizeof(double));
+        alpha = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+        beta = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+        coef = std::make_shared<DBuf>(dev, 144 * sizeof(double));   // two passes of coefficients
+        partial = std::make_shared<DBuf>(dev, (size_t)72 * G * sizeof(double));
+        sv = std::make_shared<DBuf>(dev, 72 * sizeof(double));
+        work = std::make_shared<DBuf>(dev, 256 * sizeof(double));
+        st = std::make_shared<DBuf>(dev, sizeof(LState));
+        pv = std::make_shared<DBuf>(dev, 512 * sizeof(double));
+        pi = std::make_shared<DBuf>(dev, 512 * sizeof(int64_t));
+        scal = std::make_shared<DBuf>(dev, 8 * sizeof(double));
+        V.reset();
+        V32.reset();
+    }
+    // the basis in the type the run asks for (the other one is not needed)
+    if (b32 && !V32) V32 = std::make_shared<DBuf>(dev, (size_t)(m + 1) * n * sizeof(float));
+    if (!b32 && !V) V = std::make_shared<DBuf>(dev, (size_t)(m + 1) * n * sizeof(double));
 }
 
 LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double* x, int64_t n, int m,
-                      int cycles, double tol, float* vc, double exit_tol) {
+                      int cycles, double tol, float* vc, double exit_tol, bool basis32) {
     if (n <= 0) fail(QED_ERR_INVALID_ARG, "empty eigenproblem");
     m = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(m, 64), n));
-    W.ensure(dev, m, n);
+    // an FP32 basis needs every pass to fit the fused kernels' 32 rows and no
+    // exact first product (the correction's exit copies an FP64 basis row)
+    const bool b32 = basis32 && m + 1 <= 32 && exit_tol <= 0.0;
+    W.ensure(dev, m, n, b32);
     hipStream_t s = dev->stream;
-    double* V = W.V->as<double>();
     double* w = W.w->as<double>();
     double* al = W.alpha->as<double>();
     double* be = W.beta->as<double>();
@@ -1994,63 +2002,83 @@ LanczosResult lanczos(Dev* dev, LanczosWS& W, const LanczosApply& apply, double*
     LState* st = W.st->as<LState>();
     LanczosResult R;
     const int64_t ld = n;
-    for (int cyc = 0; cyc < std::max(1, cycles); ++cyc) {
-        launch_dots(x, n, 1, x, n, part, sc + 0, 1, nullptr, 0, s);
-        launch_lz_start(V, x, sc + 0, n, st, m, s);
-        for (int j = 0; j < m; ++j) {
-            double* vj = V + (int64_t)j * ld;
-            if (apply(vj, w, part, vc && j > 0)) launch_dot_final(part, n, 1, al + j, 0, st, 1, s);
-            else launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
-            ++R.matvecs;
-            // three-term recurrence, classical Gram-Schmidt against V, a
-            // second pass where the first removed more than half of |w|^2
-            // (decided on the device), norm: fused so that each pass reads
-            // the basis once
-            if (launch_lz_fused(0, w, V, ld, 0, j, al, be, nullptr, nullptr, n, part, co, st, s)) {
-                launch_lz_fused(1, w, V, ld, j + 1, j, al, be, co, co, n, part, co2, st, s);
-                launch_lz_norm_beta(w, V, ld, j + 1, j, al, be, co2, co, n, part, sc + 1, st, 1e-14, s);
-            } else {
-                launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
-                for (int pass = 0; pass < 2; ++pass) {
-                    launch_dots(V, ld, j + 1, w, n, part, co, 0, st, 1, s);
-                    launch_lz_subtract(w, V, ld, j + 1, co, n, st, s);
+    auto run = [&](auto* V) {
+        using TV = typename std::remove_pointer<decltype(V)>::type;
+        constexpr bool F64 = std::is_same<TV, double>::value;
+        for (int cyc = 0; cyc < std::max(1, cycles); ++cyc) {
+            launch_dots(x, n, 1, x, n, part, sc + 0, 1, nullptr, 0, s);
+            launch_lz_start<TV>(V, x, sc + 0, n, st, m, s);
+            for (int j = 0; j < m; ++j) {
+                TV* vj = V + (int64_t)j * ld;
+                bool fused_alpha;
+                if constexpr (F64) fused_alpha = apply(vj, vc && j > 0 ? vc : nullptr, w, part);
+                else fused_alpha = apply(nullptr, vj, w, part);
+                if (fused_alpha) {
+                    launch_dot_final(part, n, 1, al + j, 0, st, 1, s);
+                } else {
+                    if constexpr (F64) launch_dots(vj, ld, 1, w, n, part, al + j, 0, st, 1, s);
+                    else fail(QED_ERR_BAD_STATE, "an FP32 Lanczos basis needs the fused alpha dot");
                 }
-                launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
-                launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
-            }
-            if (j == 0 && exit_tol > 0.0) {
-                // the exact residual of the current vector decides
-                double ab[2];
-                dev->download(&ab[0], al, sizeof(double));
-                dev->download(&ab[1], be, sizeof(double));
-                if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
-                    fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value");
-                if (ab[1] <= exit_tol * std::max(std::fabs(ab[0]), 1e-300)) {
-                    dev->check(hipMemcpyAsync(x, V, n * sizeof(double), hipMemcpyDeviceToDevice, s),
-                               "copy");
-                    R.theta = ab[0];
-                    R.resid = ab[1];
-                    R.cycles = cyc + 1;
-                    R.exact = true;
-                    return R;
+                ++R.matvecs;
+                // three-term recurrence, classical Gram-Schmidt against V, a
+                // second pass where the first removed more than half of |w|^2
+                // (decided on the device), norm: fused so that each pass reads
+                // the basis once
+                if (launch_lz_fused<TV>(0, w, V, ld, 0, j, al, be, nullptr, nullptr, n, part, co, st, s)) {
+                    launch_lz_fused<TV>(1, w, V, ld, j + 1, j, al, be, co, co, n, part, co2, st, s);
+                    launch_lz_norm_beta<TV>(w, V, ld, j + 1, j, al, be, co2, co, n, part, sc + 1, st, 1e-14, s);
+                } else {
+                    if constexpr (F64) {
+                        launch_lz_three_term(w, V, ld, j, al, be, n, st, s);
+                        for (int pass = 0; pass < 2; ++pass) {
+                            launch_dots(V, ld, j + 1, w, n, part, co, 0, st, 1, s);
+                            launch_lz_subtract(w, V, ld, j + 1, co, n, st, s);
+                        }
+                        launch_dots(w, n, 1, w, n, part, sc + 1, 0, st, 1, s);
+                        launch_lz_beta(sc + 1, al, be, j, st, 1e-14, s);
+                    } else {
+                        fail(QED_ERR_BAD_STATE, "an FP32 Lanczos basis is limited to 31 steps");
+                    }
                 }
+                if (j == 0 && exit_tol > 0.0) {
+                    if constexpr (F64) {
+                        // the exact residual of the current vector decides
+                        double ab[2];
+                        dev->download(&ab[0], al, sizeof(double));
+                        dev->download(&ab[1], be, sizeof(double));
+                        if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
+                            fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value");
+                        if (ab[1] <= exit_tol * std::max(std::fabs(ab[0]), 1e-300)) {
+                            dev->check(hipMemcpyAsync(x, V, n * sizeof(double), hipMemcpyDeviceToDevice, s),
+                                       "copy");
+                            R.theta = ab[0];
+                            R.resid = ab[1];
+                            R.cycles = cyc + 1;
+                            R.exact = true;
+                            return true;
+                        }
+                    }
+                }
+                launch_lz_next<TV>(V, ld, j, w, be, n, st, s, F64 ? vc : nullptr);
             }
-            launch_lz_next(V, ld, j, w, be, n, st, s, vc);
+            launch_tridiag(al, be, W.sv->as<double>(), st, W.work->as<double>(), s);
+            launch_ritz<TV>(x, V, ld, W.sv->as<double>(), n, st, s);
+            launch_dots(x, n, 1, x, n, part, sc + 2, 1, nullptr, 0, s);
+            launch_normalise_sign(x, n, sc + 2, W.pv->as<double>(), W.pi->as<int64_t>(), sc + 3, s);
+            dev->check(hipGetLastError(), "lanczos launch");
+            LState hs;
+            dev->download(&hs, st, sizeof(LState));
+            R.theta = hs.theta;
+            R.resid = hs.resid;
+            R.cycles = cyc + 1;
+            if (!std::isfinite(hs.theta) || !std::isfinite(hs.norm) || hs.norm == 0.0)
+                fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value (zero or invalid start vector?)");
+            if (exit_tol <= 0.0 && hs.resid <= tol * std::max(std::fabs(hs.theta), 1e-300)) break;
         }
-        launch_tridiag(al, be, W.sv->as<double>(), st, W.work->as<double>(), s);
-        launch_ritz(x, V, ld, W.sv->as<double>(), n, st, s);
-        launch_dots(x, n, 1, x, n, part, sc + 2, 1, nullptr, 0, s);
-        launch_normalise_sign(x, n, sc + 2, W.pv->as<double>(), W.pi->as<int64_t>(), sc + 3, s);
-        dev->check(hipGetLastError(), "lanczos launch");
-        LState hs;
-        dev->download(&hs, st, sizeof(LState));
-        R.theta = hs.theta;
-        R.resid = hs.resid;
-        R.cycles = cyc + 1;
-        if (!std::isfinite(hs.theta) || !std::isfinite(hs.norm) || hs.norm == 0.0)
-            fail(QED_ERR_NONFINITE, "Lanczos produced a non-finite value (zero or invalid start vector?)");
-        if (exit_tol <= 0.0 && hs.resid <= tol * std::max(std::fabs(hs.theta), 1e-300)) break;
-    }
+        return false;
+    };
+    if (b32) run(W.V32->as<float>());
+    else run(W.V->as<double>());
     return R;
 }
 

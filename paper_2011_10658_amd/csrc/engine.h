@@ -43,16 +43,20 @@ void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64
 // stages whose products are all identity products (sums of blocks): one
 // workgroup per SUM_TILE consecutive output elements of a job
 void launch_sum_stage(int dtype, const GJob*, const GProd*, const GTile*, int, const Bases&, hipStream_t);
-bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
+// (TV: the basis element type, double or float)
+template <typename TV>
+bool launch_lz_fused(int mode, double* w, const TV* V, int64_t ldv, int nrows, int j,
                      const double* alpha, const double* beta, const double* c, const double* cf,
                      int64_t n, double* partial, double* out, const LState* st, hipStream_t s);
 // mode 2 of launch_lz_fused with the beta step of launch_lz_beta fused into
 // its final reduction
-bool launch_lz_norm_beta(double* w, const double* V, int64_t ldv, int nrows, int j, double* alpha,
+template <typename TV>
+bool launch_lz_norm_beta(double* w, const TV* V, int64_t ldv, int nrows, int j, double* alpha,
                          double* beta, const double* c, const double* cf, int64_t n, double* partial,
                          double* ww, LState* st, double tol, hipStream_t s);
 // w = (double) a with the partials of v . w (layout of launch_dots, one row)
-void launch_f32_to_f64_dot(const float* a, double* w, const double* v, int64_t n, double* partial,
+template <typename TV>
+void launch_f32_to_f64_dot(const float* a, double* w, const TV* v, int64_t n, double* partial,
                            const LState* st, hipStream_t s);
 // the final pass of launch_dots alone
 void launch_dot_final(const double* partial, int64_t n, int nrows, double* out, int mode,
@@ -62,12 +66,14 @@ void launch_lz_three_term(double*, const double*, int64_t, int, const double*, c
 void launch_lz_subtract(double*, const double*, int64_t, int, const double*, int64_t,
                         const LState*, hipStream_t);
 void launch_lz_beta(const double*, double*, double*, int, LState*, double, hipStream_t);
-void launch_lz_next(double*, int64_t, int, const double*, const double*, int64_t, const LState*,
-                    hipStream_t, float* vc = nullptr);
-void launch_lz_start(double*, const double*, const double*, int64_t, LState*, int, hipStream_t);
+template <typename TV>
+void launch_lz_next(TV*, int64_t, int, const double*, const double*, int64_t, const LState*, hipStream_t,
+                    float* vc = nullptr);
+template <typename TV>
+void launch_lz_start(TV*, const double*, const double*, int64_t, LState*, int, hipStream_t);
 void launch_tridiag(const double*, const double*, double*, LState*, double*, hipStream_t);
-void launch_ritz(double*, const double*, int64_t, const double*, int64_t, const LState*,
-                 hipStream_t);
+template <typename TV>
+void launch_ritz(double*, const TV*, int64_t, const double*, int64_t, const LState*, hipStream_t);
 void launch_normalise_sign(double*, int64_t, const double*, double*, int64_t*, double*,
                            hipStream_t);
 void launch_pack(const PackBlk*, int, int64_t, double*, double*, int, hipStream_t);
@@ -372,8 +378,10 @@ void tsqr(Dev* dev, double* M, int64_t m, int n, double* R, int64_t rrs, int64_t
 struct LanczosWS {
     int m = 0;
     int64_t n = 0;
-    BufP V, w, alpha, beta, coef, partial, sv, work, st, pv, pi, scal;
-    void ensure(Dev* dev, int m, int64_t n);
+    BufP V, V32, w, alpha, beta, coef, partial, sv, work, st, pv, pi, scal;
+    // buffers for m steps on vectors of n; the basis in FP64 (V) or, with
+    // b32, in FP32 (V32)
+    void ensure(Dev* dev, int m, int64_t n, bool b32 = false);
 };
 
 struct LanczosResult {
@@ -385,19 +393,24 @@ struct LanczosResult {
 
 // Lowest eigenpair; x (device FP64, length n) is the start vector and
 // receives the normalised Ritz vector.
-// apply(v, y, part, pre) computes y = H v; it may also leave the partials
-// of v . y in part (the layout of launch_dots, one row) and then returns
-// true.  With vc set, each new basis vector is also written to vc in FP32,
-// and pre = true tells apply that vc already holds v.
+// apply(v, v32, y, part) computes y = H v: v is the FP64 basis vector, and
+// v32, where set, holds v rounded to FP32 already (written by the step that
+// formed v); with an FP32 basis v is null and v32 is the basis vector
+// itself.  apply may also leave the partials of v . y in part (the layout
+// of launch_dots, one row) and then returns true.  With vc set, each new
+// FP64 basis vector is also written to vc in FP32.  basis32 keeps the basis
+// in FP32 (m <= 31, no exit_tol; apply must then return true): the passes
+// over it read half the bytes, the matvec reads its input straight from
+// it, and w, the coefficients and the Ritz vector stay FP64.
 // exit_tol > 0 (for an apply whose first product of a cycle is exact):
 // after the first step of every cycle, alpha_0 = <x, H x> and beta_0 =
 // |H x - alpha_0 x| are those of the current vector itself; the run ends
 // there once beta_0 <= exit_tol |alpha_0| (x is left normalised, theta =
 // alpha_0, resid = beta_0, exact = true), and the estimate from the
 // tridiagonal at the end of a cycle does not end it.
-using LanczosApply = std::function<bool(const double*, double*, double*, bool)>;
+using LanczosApply = std::function<bool(const double*, const float*, double*, double*)>;
 LanczosResult lanczos(Dev* dev, LanczosWS& ws, const LanczosApply& apply, double* x, int64_t n, int m,
-                      int cycles, double tol, float* vc = nullptr, double exit_tol = 0.0);
+                      int cycles, double tol, float* vc = nullptr, double exit_tol = 0.0, bool basis32 = false);
 
 // ---- node-level effective Hamiltonian (C ABI object) ------------------
 struct Ctx;

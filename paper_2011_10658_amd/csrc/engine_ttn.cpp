@@ -865,6 +865,15 @@ void Engine::prepare() {
     centre = tree.root;
 }
 
+// QEDTTN_LZ_BASIS=fp32 keeps the FP32 path's Krylov basis in FP32 (the
+// precision of its matvec, half the bytes per Gram-Schmidt pass); by
+// default it stays FP64 with an FP32 copy of each new vector for the
+// matvec, which measured faster on the benchmark's sweep (91 against 98 ms).
+static bool basis32_enabled() {
+    const char* v = std::getenv("QEDTTN_LZ_BASIS");
+    return v && !std::strcmp(v, "fp32");
+}
+
 double Engine::update(int n, double nu, bool refine_here) {
     Dev* dev = &ctx->dev;
     const Params& P = ctx->prm;
@@ -924,21 +933,28 @@ double Engine::update(int n, double nu, bool refine_here) {
         w64 = ws64.get(dev, std::max<int64_t>(1, p64.ws_elems) * 8);
     }
     long long exact_mv = 0;
-    auto apply = [&](const double* v, double* y, double* part, bool pre) {
+    auto apply = [&](const double* v, const float* v32, double* y, double* part) {
         if (dtype == QED_FP64) {
             plan.run(dev, w, (void*)v, (void*)y);
             return false;
         }
-        if (fix && v == lws.V->as<double>()) {
+        if (fix && v && v == lws.V->as<double>()) {
             p64.run(dev, w64, (void*)v, (void*)y);
             ++exact_mv;
             return false;
         }
-        if (!pre) to_compute(dtype, v, xc->p, n_el, dev->stream);
-        plan.run(dev, w, xc->p, yc->p);
+        // the FP32 input: the FP32 basis vector itself, the FP32 copy the
+        // previous step wrote, or a conversion of the FP64 vector
+        const bool have32 = v32 && dtype == QED_FP32;
+        if (!have32) to_compute(dtype, v, xc->p, n_el, dev->stream);
+        plan.run(dev, w, have32 ? (void*)v32 : xc->p, yc->p);
         if (dtype == QED_FP32) {   // conversion back fused with the alpha dot
-            launch_f32_to_f64_dot((const float*)yc->p, y, v, n_el, part, lws.st->as<LState>(),
-                                  dev->stream);
+            if (v)
+                launch_f32_to_f64_dot<double>((const float*)yc->p, y, v, n_el, part, lws.st->as<LState>(),
+                                              dev->stream);
+            else
+                launch_f32_to_f64_dot<float>((const float*)yc->p, y, v32, n_el, part, lws.st->as<LState>(),
+                                             dev->stream);
             return true;
         }
         from_compute(dtype, yc->p, y, n_el, dev->stream);
@@ -957,7 +973,8 @@ double Engine::update(int n, double nu, bool refine_here) {
     // the FP32 path takes each new basis vector's FP32 copy from the
     // Lanczos step that writes it
     LanczosResult R = lanczos(dev, lws, apply, T.ptr(), n_el, P.lz_steps, P.lz_cycles, tol,
-                              dtype == QED_FP32 ? (float*)xc->p : nullptr, fix ? tol : 0.0);
+                              dtype == QED_FP32 ? (float*)xc->p : nullptr, fix ? tol : 0.0,
+                              dtype == QED_FP32 && !fix && basis32_enabled());
     // the Lanczos run ended in a synchronising download: every GEMM event
     // recorded so far has completed, and its pair can be reused
     if (ctx->prof.on) ctx->prof.harvest();

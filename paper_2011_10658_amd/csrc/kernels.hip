@@ -1167,9 +1167,10 @@ void launch_dots(const double* V, int64_t ldv, int nrows, const double* w, int64
 // reduction of k_dot_partial (one row): the FP32 matvec's conversion and
 // the Lanczos alpha dot in one pass, with the same results as the two
 // separate kernels
+template <typename TV>
 __global__ __launch_bounds__(256) void k_f32_to_f64_dot(const float* __restrict__ a,
                                                         double* __restrict__ w,
-                                                        const double* __restrict__ v, int64_t n,
+                                                        const TV* __restrict__ v, int64_t n,
                                                         double* __restrict__ partial,
                                                         const LState* st) {
     if (st->broken) return;
@@ -1182,7 +1183,7 @@ __global__ __launch_bounds__(256) void k_f32_to_f64_dot(const float* __restrict_
     for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
         const double wi = (double)a[i];
         w[i] = wi;
-        s += v[i] * wi;
+        s += (double)v[i] * wi;
     }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -1190,10 +1191,15 @@ __global__ __launch_bounds__(256) void k_f32_to_f64_dot(const float* __restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-void launch_f32_to_f64_dot(const float* a, double* w, const double* v, int64_t n, double* partial,
+template <typename TV>
+void launch_f32_to_f64_dot(const float* a, double* w, const TV* v, int64_t n, double* partial,
                            const LState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_f32_to_f64_dot, dim3(dot_grid(n)), dim3(256), 0, s, a, w, v, n, partial, st);
+    hipLaunchKernelGGL(k_f32_to_f64_dot<TV>, dim3(dot_grid(n)), dim3(256), 0, s, a, w, v, n, partial, st);
 }
+template void launch_f32_to_f64_dot<double>(const float*, double*, const double*, int64_t, double*, const LState*,
+                                            hipStream_t);
+template void launch_f32_to_f64_dot<float>(const float*, double*, const float*, int64_t, double*, const LState*,
+                                           hipStream_t);
 
 void launch_dot_final(const double* partial, int64_t n, int nrows, double* out, int mode,
                       const LState* st, int skip, hipStream_t s) {
@@ -1254,22 +1260,26 @@ __global__ void k_lz_beta(const double* ww, double* alpha, double* beta, int j, 
 // V[j+1] = w / beta[j]
 // (and, with vc, its FP32 copy for the next matvec: the value the separate
 // conversion would write)
-__global__ void k_lz_next(double* __restrict__ V, int64_t ldv, int j,
+// (an FP32 basis stores the rounded value itself: the basis vector is then
+// exactly the matvec's input)
+template <typename TV>
+__global__ void k_lz_next(TV* __restrict__ V, int64_t ldv, int j,
                           const double* __restrict__ w, const double* __restrict__ beta,
                           int64_t n, const LState* st, float* __restrict__ vc) {
     if (st->broken) return;
     const double inv = 1.0 / beta[j];
-    double* v = V + (int64_t)(j + 1) * ldv;
+    TV* v = V + (int64_t)(j + 1) * ldv;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double t = w[i] * inv;
-        v[i] = t;
+        v[i] = (TV)t;
         if (vc) vc[i] = (float)t;
     }
 }
 
 // dst = src / *nrm  (start vector); records the norm
-__global__ void k_lz_start(double* __restrict__ dst, const double* __restrict__ src,
+template <typename TV>
+__global__ void k_lz_start(TV* __restrict__ dst, const double* __restrict__ src,
                            const double* nrm, int64_t n, LState* st, int m) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->broken = 0;
@@ -1279,7 +1289,7 @@ __global__ void k_lz_start(double* __restrict__ dst, const double* __restrict__ 
     const double inv = 1.0 / *nrm;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i] * inv;
+        dst[i] = (TV)(src[i] * inv);
 }
 
 // lowest eigenpair of the k x k tridiagonal (alpha, beta): Sturm-count
@@ -1388,13 +1398,14 @@ __global__ void k_tridiag_lowest(const double* alpha_g, const double* beta_g, do
 }
 
 // u = sum_{r < k} s[r] V[r]
-__global__ void k_ritz(double* __restrict__ u, const double* __restrict__ V, int64_t ldv,
+template <typename TV>
+__global__ void k_ritz(double* __restrict__ u, const TV* __restrict__ V, int64_t ldv,
                        const double* __restrict__ s, int64_t n, const LState* st) {
     const int k = st->k;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double t = 0.0;
-        for (int r = 0; r < k; ++r) t += s[r] * V[(int64_t)r * ldv + i];
+        for (int r = 0; r < k; ++r) t += s[r] * (double)V[(int64_t)r * ldv + i];
         u[i] = t;
     }
 }
@@ -1486,8 +1497,8 @@ __device__ __forceinline__ bool lz_second_pass(const double* cf, int nrows) {
     return 2.0 * p > cf[nrows];
 }
 
-template <int MAXR>
-__global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const double* __restrict__ V,
+template <int MAXR, typename TV>
+__global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const TV* __restrict__ V,
                                                   int64_t ldv, int mode, int nrows, int j,
                                                   const double* __restrict__ alpha,
                                                   const double* __restrict__ beta,
@@ -1521,14 +1532,14 @@ __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const 
         double v[NV];
         if constexpr (CACHE) {
 #pragma unroll
-            for (int r = 0; r < NV; ++r) v[r] = r < nr ? V[(int64_t)r * ldv + i] : 0.0;
+            for (int r = 0; r < NV; ++r) v[r] = r < nr ? (double)V[(int64_t)r * ldv + i] : 0.0;
         }
-#define QED_ROW(r) (CACHE ? v[(r) < NV ? (r) : 0] : V[(int64_t)(r) * ldv + i])
+#define QED_ROW(r) (CACHE ? v[(r) < NV ? (r) : 0] : (double)V[(int64_t)(r) * ldv + i])
         double wi = w[i];
         if (mode == 0) {
             // rows j and j-1 are cached from the loads above
-            double t = a * V[(int64_t)j * ldv + i];
-            if (j > 0) t += b * V[(int64_t)(j - 1) * ldv + i];
+            double t = a * (double)V[(int64_t)j * ldv + i];
+            if (j > 0) t += b * (double)V[(int64_t)(j - 1) * ldv + i];
             wi -= t;
         } else {
             double t = 0.0;
@@ -1594,38 +1605,52 @@ __global__ __launch_bounds__(256) void k_dot_final_beta(const double* __restrict
     }
 }
 
-bool launch_lz_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j,
+template <typename TV>
+bool launch_lz_fused(int mode, double* w, const TV* V, int64_t ldv, int nrows, int j,
                      const double* alpha, const double* beta, const double* c, const double* cf,
                      int64_t n, double* partial, double* out, const LState* st, hipStream_t s) {
     const int nr = mode == 0 ? j + 1 : nrows;
     if (nr + 1 > 32) return false;   // mode 0 also needs the row of w.w
     const int G = dot_grid(n);
     if (nr + 1 <= 16)
-        hipLaunchKernelGGL(k_lz_fused<16>, dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
+        hipLaunchKernelGGL((k_lz_fused<16, TV>), dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
                            beta, c, cf, n, partial, st);
     else
-        hipLaunchKernelGGL(k_lz_fused<32>, dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
+        hipLaunchKernelGGL((k_lz_fused<32, TV>), dim3(G), dim3(256), 0, s, w, V, ldv, mode, nrows, j, alpha,
                            beta, c, cf, n, partial, st);
     const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;
     hipLaunchKernelGGL(k_dot_final, dim3(nd), dim3(256), 0, s, partial, G, nd, out, 0, st, 1);
     return true;
 }
+template bool launch_lz_fused<double>(int, double*, const double*, int64_t, int, int, const double*, const double*,
+                                      const double*, const double*, int64_t, double*, double*, const LState*,
+                                      hipStream_t);
+template bool launch_lz_fused<float>(int, double*, const float*, int64_t, int, int, const double*, const double*,
+                                     const double*, const double*, int64_t, double*, double*, const LState*,
+                                     hipStream_t);
 
-bool launch_lz_norm_beta(double* w, const double* V, int64_t ldv, int nrows, int j, double* alpha,
+template <typename TV>
+bool launch_lz_norm_beta(double* w, const TV* V, int64_t ldv, int nrows, int j, double* alpha,
                          double* beta, const double* c, const double* cf, int64_t n, double* partial,
                          double* ww, LState* st, double tol, hipStream_t s) {
     if (nrows + 1 > 32) return false;
     const int G = dot_grid(n);
     if (nrows + 1 <= 16)
-        hipLaunchKernelGGL(k_lz_fused<16>, dim3(G), dim3(256), 0, s, w, V, ldv, 2, nrows, j, alpha,
+        hipLaunchKernelGGL((k_lz_fused<16, TV>), dim3(G), dim3(256), 0, s, w, V, ldv, 2, nrows, j, alpha,
                            beta, c, cf, n, partial, st);
     else
-        hipLaunchKernelGGL(k_lz_fused<32>, dim3(G), dim3(256), 0, s, w, V, ldv, 2, nrows, j, alpha,
+        hipLaunchKernelGGL((k_lz_fused<32, TV>), dim3(G), dim3(256), 0, s, w, V, ldv, 2, nrows, j, alpha,
                            beta, c, cf, n, partial, st);
     hipLaunchKernelGGL(k_dot_final_beta, dim3(1), dim3(256), 0, s, partial, G, ww, alpha, beta, j, st,
                        tol);
     return true;
 }
+template bool launch_lz_norm_beta<double>(double*, const double*, int64_t, int, int, double*, double*,
+                                          const double*, const double*, int64_t, double*, double*, LState*, double,
+                                          hipStream_t);
+template bool launch_lz_norm_beta<float>(double*, const float*, int64_t, int, int, double*, double*,
+                                         const double*, const double*, int64_t, double*, double*, LState*, double,
+                                         hipStream_t);
 
 void launch_lz_three_term(double* w, const double* V, int64_t ldv, int j, const double* alpha,
                           const double* beta, int64_t n, const LState* st, hipStream_t s) {
@@ -1641,22 +1666,34 @@ void launch_lz_beta(const double* ww, double* alpha, double* beta, int j, LState
                     hipStream_t s) {
     hipLaunchKernelGGL(k_lz_beta, dim3(1), dim3(1), 0, s, ww, alpha, beta, j, st, tol);
 }
-void launch_lz_next(double* V, int64_t ldv, int j, const double* w, const double* beta, int64_t n,
+template <typename TV>
+void launch_lz_next(TV* V, int64_t ldv, int j, const double* w, const double* beta, int64_t n,
                     const LState* st, hipStream_t s, float* vc) {
-    hipLaunchKernelGGL(k_lz_next, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, j, w, beta, n, st, vc);
+    hipLaunchKernelGGL(k_lz_next<TV>, dim3(grid_for(n)), dim3(256), 0, s, V, ldv, j, w, beta, n, st, vc);
 }
-void launch_lz_start(double* dst, const double* src, const double* nrm, int64_t n, LState* st,
+template void launch_lz_next<double>(double*, int64_t, int, const double*, const double*, int64_t, const LState*,
+                                     hipStream_t, float*);
+template void launch_lz_next<float>(float*, int64_t, int, const double*, const double*, int64_t, const LState*,
+                                    hipStream_t, float*);
+template <typename TV>
+void launch_lz_start(TV* dst, const double* src, const double* nrm, int64_t n, LState* st,
                      int m, hipStream_t s) {
-    hipLaunchKernelGGL(k_lz_start, dim3(grid_for(n)), dim3(256), 0, s, dst, src, nrm, n, st, m);
+    hipLaunchKernelGGL(k_lz_start<TV>, dim3(grid_for(n)), dim3(256), 0, s, dst, src, nrm, n, st, m);
 }
+template void launch_lz_start<double>(double*, const double*, const double*, int64_t, LState*, int, hipStream_t);
+template void launch_lz_start<float>(float*, const double*, const double*, int64_t, LState*, int, hipStream_t);
 void launch_tridiag(const double* alpha, const double* beta, double* sv, LState* st, double* work,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_tridiag_lowest, dim3(1), dim3(64), 0, s, alpha, beta, sv, st, work);
 }
-void launch_ritz(double* u, const double* V, int64_t ldv, const double* sv, int64_t n,
+template <typename TV>
+void launch_ritz(double* u, const TV* V, int64_t ldv, const double* sv, int64_t n,
                  const LState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_ritz, dim3(grid_for(n)), dim3(256), 0, s, u, V, ldv, sv, n, st);
+    hipLaunchKernelGGL(k_ritz<TV>, dim3(grid_for(n)), dim3(256), 0, s, u, V, ldv, sv, n, st);
 }
+template void launch_ritz<double>(double*, const double*, int64_t, const double*, int64_t, const LState*,
+                                  hipStream_t);
+template void launch_ritz<float>(double*, const float*, int64_t, const double*, int64_t, const LState*, hipStream_t);
 void launch_normalise_sign(double* u, int64_t n, const double* nrm, double* pv, int64_t* pi,
                            double* fac, hipStream_t s) {
     const int G = dot_grid(n);

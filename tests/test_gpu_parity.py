@@ -569,9 +569,9 @@ GOLDEN_SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"
                             "sweep_2x2x2_free_chi64.json")
 
 
-@pytest.mark.parametrize("plan", ["staged", "fused"])
+@pytest.mark.parametrize("plan,basis", [("staged", "fp64"), ("fused", "fp64"), ("staged", "fp32")])
 @pytest.mark.parametrize("dtype", [lib.FP64, lib.FP32])
-def test_bench_config_sweeps_vs_oracle(ctx, dtype, plan, monkeypatch):
+def test_bench_config_sweeps_vs_oracle(ctx, dtype, plan, basis, monkeypatch):
     """The benchmark's lattice (2x2x2, free-flux boundary, d = 267 at every
     site, m = t = 1, g^2 = 1 on the physical line, Q = 0, chi = 64) against
     two sweeps of the oracle's tree tensor network from the same seeded
@@ -586,8 +586,10 @@ def test_bench_config_sweeps_vs_oracle(ctx, dtype, plan, monkeypatch):
     error), so the stated bound is 1e-5 relative for the energies and 1e-4
     for the observables (measured 1.2e-5 on the link fields).  Both H_eff
     plans: three mode-product stages, and the fused stages for the terms
-    with a bond-leg factor."""
+    with a bond-leg factor; the FP32 path also with its Krylov basis kept in
+    FP32 (QEDTTN_LZ_BASIS=fp32; the FP64 path ignores the switch)."""
     monkeypatch.setenv("QEDTTN_HEFF_FUSED", "1" if plan == "fused" else "0")
+    monkeypatch.setenv("QEDTTN_LZ_BASIS", basis)
     with open(GOLDEN_SWEEP) as f:
         G = json.load(f)
     c = G["couplings"]
