@@ -343,7 +343,8 @@ def finite_density(lib, torch, steps):
     charge Q = +8, m = t = 1, g^2 = 1 (g_e^2 = 1, g_m^2 = 8), chi = 256 with
     internal charges up to |q| <= 8; the same seeded start and penalty
     schedule on the FP64, FP32 and BF16 GEMM paths (FP64 Lanczos, QR and
-    energies on all three).  Reports per-sweep energies, times, and the
+    energies on all three; the refinement of each path as in the sweep
+    benchmark: BF16 with the FP64 residual correction).  Reports per-sweep energies, times, and the
     energy and site-density differences of the reduced-precision paths from
     the FP64 path after the same sweeps."""
     res = {}
@@ -356,7 +357,7 @@ def finite_density(lib, torch, steps):
         ctx.set_bond_dim(256)
         ctx.set_penalty(40.0, max(1, steps // 2), max(0, steps - steps // 2))
         ctx.set_lanczos(16, 1, 1e-8)
-        ctx.set_precision(dt, 1)
+        ctx.set_precision(dt, REFINE[name])
         ctx.build_hamiltonian()
         ctx.init_state(SEED)
         ctx.set_profiling(True)
@@ -398,7 +399,8 @@ def finite_density(lib, torch, steps):
         "data": "synthetic",
         "config": {"workload": "TTN sweeps, 4x4x4 open-lattice compact QED, free-flux boundary "
                                "(d=267), Q=+8, m=t=1, g^2=1, chi=256, BF16 vs FP32 vs FP64 GEMMs",
-                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient for the sweep energy"},
+                   "lanczos": "16 steps, 1 cycle per update, FP64 Rayleigh quotient for the sweep energy; "
+                              "BF16: FP64 residual correction (first product of every cycle in FP64)"},
         "fp64_path": dict(sweep_s=res["f64"]["seconds"], energies=res["f64"]["energies"],
                           Q=res["f64"]["Q"], rho=res["f64"]["rho"], gemm_tflops=res["f64"]["gemm_tflops"]),
         "f32_path": out["f32"], "bf16_path": out["bf16"],

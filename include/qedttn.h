@@ -323,12 +323,14 @@ int qed_pin_charges(qed_ctx* ctx, int n, const int* sites, const int* charges, d
 
 /* Cumulative counters of the context.  matvec_flops / matvecs: algorithmic
  * work of every H_eff application (sweeps and node-level objects).
- * With profiling on, every contraction launch that belongs to an H_eff
- * application (block-GEMM and fused kernels) is bracketed by HIP events
- * on the context's stream: gemm_launches, gemm_ms (sum of the event
- * intervals) and gemm_flops (algorithmic flops of those launches) count
- * all of them; fused_launches, fused_ms and fused_flops count the fused
- * kernel's launches alone. */
+ * With profiling on, the block-GEMM and fused launches of every H_eff
+ * application are timed with HIP events on the context's stream: one
+ * event pair brackets an application's GEMM launches (issued back to back),
+ * or, with QEDTTN_TRACE set or fused stages in the plan, each launch gets
+ * its own pair.  gemm_launches counts the launches, gemm_ms sums the event
+ * intervals and gemm_flops the algorithmic flops of those launches;
+ * fused_launches, fused_ms and fused_flops count the fused kernel's
+ * launches alone. */
 typedef struct {
     double matvec_flops;
     long long matvecs;

@@ -798,6 +798,7 @@ void Prof::report() const {
     static const char* shapes[] = {"64x64", "128x32", "32x128"};
     static const char* pipes[] = {"loop", "flat", "dma", "skinny"};
     for (const auto& kv : by_key) {
+        if (kv.first == RUN_KEY) continue;   // whole-run brackets: no per-stage split
         const int st = kv.first / 16, k = kv.first % 16;
         const int sh = k % 4, pp = k / 4;
         const auto& v = kv.second;
@@ -826,16 +827,39 @@ Prof::~Prof() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
+// Profiling: every GEMM and fused launch of the plan counts.  Timing
+// events around each launch add their own processing to every interval
+// (about 30 us per launch on the benchmark's sweep against a rocprofv3
+// kernel trace), so by default one event pair brackets the run's GEMM
+// launches, which are issued back to back (a summation stage between two
+// GEMM stages would fall inside; the matvec plans end with theirs).  With
+// QEDTTN_TRACE set, or for plans with fused stages (whose share is reported
+// apart), every launch gets its own pair, for the per-stage breakdown.
 void Plan::run(Dev* dev, void* ws, void* x, void* y) {
     Bases b;
     b.b[TAG_ABS] = nullptr;
     b.b[TAG_WS] = ws;
     b.b[TAG_X] = x;
     b.b[TAG_Y] = y;
+    const bool on = prof && prof->on;
+    static const bool trace = std::getenv("QEDTTN_TRACE") != nullptr;
+    bool any_fused = false;
+    int last = -1;   // the last stage with a timed launch
+    for (size_t s = 0; s < dj.size(); ++s) {
+        const bool f = s < nftiles.size() && nftiles[s];
+        any_fused = any_fused || f;
+        if ((ntiles[s] && !sumk[s]) || f) last = (int)s;
+    }
+    const bool per_launch = on && (trace || any_fused);
+    const bool bracket = on && !per_launch && last >= 0;
+    hipEvent_t b0 = nullptr;
+    long long nb = 0;
+    double fb = 0.0;
+    if (bracket) prof->record_begin(dev->stream, b0);
     for (size_t s = 0; s < dj.size(); ++s) {
         if (ntiles[s]) {
             // summation stages run another kernel: only GEMM launches are timed
-            const bool timed = prof && prof->on && !sumk[s];
+            const bool timed = per_launch && !sumk[s];
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed) prof->record_begin(dev->stream, e0);
             launch_stage(s, b, dev->stream);
@@ -846,9 +870,13 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
                 prof->ev_key.push_back((int)s * 16 + shape[s] + 4 * pipe[s]);
                 prof->launches += 1;
             }
+            if (bracket && !sumk[s]) {
+                nb += 1;
+                fb += s < stage_flops.size() ? stage_flops[s] : 0.0;
+            }
         }
         if (s < nftiles.size() && nftiles[s]) {
-            const bool timed = prof && prof->on;
+            const bool timed = per_launch;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed) prof->record_begin(dev->stream, e0);
             launch_fused(s, b, dev->stream);
@@ -860,6 +888,14 @@ void Plan::run(Dev* dev, void* ws, void* x, void* y) {
                 prof->launches += 1;
                 prof->f_launches += 1;
             }
+        }
+        if (bracket && (int)s == last) {
+            hipEvent_t b1 = nullptr;
+            prof->record_begin(dev->stream, b1);
+            prof->ev.push_back({b0, b1});
+            prof->ev_flops.push_back(fb);
+            prof->ev_key.push_back(Prof::RUN_KEY);
+            prof->launches += nb;
         }
     }
     dev->check(hipGetLastError(), "brgemm launch");

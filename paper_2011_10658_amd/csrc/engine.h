@@ -239,6 +239,7 @@ struct Prof {
     long long f_launches = 0;            // the fused kernel's share of the above
     double f_ms = 0.0, f_flops = 0.0;
     static constexpr int FUSED_KEY = 15;
+    static constexpr int RUN_KEY = -2;    // one bracket around a plan run's GEMM launches
     std::map<int, std::array<double, 3>> by_key;   // launches, ms, flops per stage and shape
     void record_begin(hipStream_t s, hipEvent_t& a);
     void harvest();     // fold finished event pairs into ms (stream synced)
