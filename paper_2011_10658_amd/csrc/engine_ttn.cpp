@@ -161,11 +161,11 @@ double Engine::nu_for(int s) const {
 // ---------------------------------------------------------------------
 // QEDTTN_QR=cholesky takes the shifted CholeskyQR3 route for the centre
 // moves, where it applies; by default every move takes the Householder
-// route.  On the benchmark lattice the sector matrices of the bottom nodes
-// toward their parent become numerically rank deficient as the state
-// converges (Schmidt weights far below 1e-8), where the Cholesky route has
-// to hand over to Householder after its passes: measured 103 against
-// 99 ms per FP32 sweep, so it is not the default.
+// route.  On the 2x2x2 free-flux lattice at chi = 64 the sector matrices
+// of the bottom nodes toward their parent become numerically rank
+// deficient as the state converges (Schmidt weights far below 1e-8), where
+// the Cholesky route has to hand over to Householder after its passes:
+// measured 103 against 99 ms per FP32 sweep, so it is not the default.
 static bool use_cholqr() {
     const char* v = std::getenv("QEDTTN_QR");
     return v && !std::strcmp(v, "cholesky");
@@ -868,7 +868,8 @@ void Engine::prepare() {
 // QEDTTN_LZ_BASIS=fp32 keeps the FP32 path's Krylov basis in FP32 (the
 // precision of its matvec, half the bytes per Gram-Schmidt pass); by
 // default it stays FP64 with an FP32 copy of each new vector for the
-// matvec, which measured faster on the benchmark's sweep (91 against 98 ms).
+// matvec, which measured faster on the 2x2x2 free-flux chi = 64 sweep (91
+// against 98 ms).
 static bool basis32_enabled() {
     const char* v = std::getenv("QEDTTN_LZ_BASIS");
     return v && !std::strcmp(v, "fp32");
