@@ -1531,8 +1531,19 @@ __global__ __launch_bounds__(256) void k_lz_fused(double* __restrict__ w, const 
         constexpr int NV = CACHE ? MAXR : 1;
         double v[NV];
         if constexpr (CACHE) {
+            // every row's load is issued before any is converted: left to
+            // itself the compiler converts a float row inside its guarded load
+            // and so waits for each load in turn; the empty asm statements
+            // (no instruction) hold the loaded values until all are issued
+            TV vt[NV];
 #pragma unroll
-            for (int r = 0; r < NV; ++r) v[r] = r < nr ? (double)V[(int64_t)r * ldv + i] : 0.0;
+            for (int r = 0; r < NV; ++r) vt[r] = r < nr ? V[(int64_t)r * ldv + i] : (TV)0;
+            if constexpr (sizeof(TV) == 4) {
+#pragma unroll
+                for (int r = 0; r < NV; ++r) asm volatile("" : "+v"(vt[r]));
+            }
+#pragma unroll
+            for (int r = 0; r < NV; ++r) v[r] = (double)vt[r];
         }
 #define QED_ROW(r) (CACHE ? v[(r) < NV ? (r) : 0] : (double)V[(int64_t)(r) * ldv + i])
         double wi = w[i];

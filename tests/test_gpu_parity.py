@@ -586,8 +586,9 @@ def test_bench_config_sweeps_vs_oracle(ctx, dtype, plan, basis, monkeypatch):
     error), so the stated bound is 1e-5 relative for the energies and 1e-4
     for the observables (measured 1.2e-5 on the link fields).  Both H_eff
     plans: three mode-product stages, and the fused stages for the terms
-    with a bond-leg factor; the FP32 path also with its Krylov basis kept in
-    FP32 (QEDTTN_LZ_BASIS=fp32; the FP64 path ignores the switch)."""
+    with a bond-leg factor; the FP32 path with its Krylov basis in FP32 (its
+    default) and in FP64 (QEDTTN_LZ_BASIS=fp64; the FP64 path ignores the
+    switch)."""
     monkeypatch.setenv("QEDTTN_HEFF_FUSED", "1" if plan == "fused" else "0")
     monkeypatch.setenv("QEDTTN_LZ_BASIS", basis)
     with open(GOLDEN_SWEEP) as f:
