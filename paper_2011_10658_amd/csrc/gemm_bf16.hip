@@ -27,10 +27,16 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// blocks in device (global) memory: global rather than flat loads and
+// stores, so that the MFMA loop's LDS waits do not also wait for the next
+// chunk's operand prefetch (flat loads count against the LDS counter)
 template <typename P>
-__device__ __forceinline__ P* at(const GRef& r, const Bases& bs) {
-    if (r.tag == TAG_ABS) return (P*)r.abs;
-    return (P*)bs.b[r.tag] + r.off;
+using gmem = __attribute__((address_space(1))) P;
+
+template <typename P>
+__device__ __forceinline__ gmem<P>* at(const GRef& r, const Bases& bs) {
+    if (r.tag == TAG_ABS) return (gmem<P>*)r.abs;
+    return (gmem<P>*)bs.b[r.tag] + r.off;
 }
 
 // K advances in chunks of KB = 32, one MFMA depth.  LDS holds the chunk
@@ -78,7 +84,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_bf16(const GJob* __restrict__
     const int t_tn = tid % TN, t_nq = tid / TN;
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
-        const uint16_t* Bb = at<const uint16_t>(P.B, bases) + (int64_t)tl.b * P.bsB;
+        gmem<const uint16_t>* Bb = at<const uint16_t>(P.B, bases) + (int64_t)tl.b * P.bsB;
         const float alpha = (float)P.alpha;
         if (P.ident) {
 #pragma unroll
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_bf16(const GJob* __restrict__
                 }
             continue;
         }
-        const uint16_t* Ab = at<const uint16_t>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        gmem<const uint16_t>* Ab = at<const uint16_t>(P.A, bases) + (int64_t)tl.b * P.bsA;
         const bool scale = alpha != 1.0f;
         const int nchunk = (P.K + KB - 1) / KB;
         const int am0 = P.tA ? t_tm : t_kq, amE = P.tA ? 0 : ASA;
@@ -117,17 +123,17 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_bf16(const GJob* __restrict__
             bbase = (int64_t)bk0 * P.ldb + col;
         }
         for (int r = 0; r < P.nred; ++r) {
-            const uint16_t* A = Ab + (int64_t)r * P.rsA + abase;
-            const uint16_t* B = Bb + (int64_t)r * P.rsB + bbase;
+            gmem<const uint16_t>* A = Ab + (int64_t)r * P.rsA + abase;
+            gmem<const uint16_t>* B = Bb + (int64_t)r * P.rsB + bbase;
             auto fetch = [&](int c) {
                 const int k0 = c * KB;
-                const uint16_t* pa = A + k0 * akm;
-                const uint16_t* pb = B + k0 * bkm;
+                gmem<const uint16_t>* pa = A + k0 * akm;
+                gmem<const uint16_t>* pb = B + k0 * bkm;
 #pragma unroll
                 for (int e = 0; e < AE; ++e) {
                     uint16_t v = 0;
                     if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
-                    ra[e] = scale ? f2bf(alpha * bf2f(v)) : v;
+                    ra[e] = v;
                 }
 #pragma unroll
                 for (int e = 0; e < BE; ++e) {
@@ -136,9 +142,26 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_bf16(const GJob* __restrict__
                     rb[e] = v;
                 }
             };
+            // the scaling is applied here, not at the load: a use right after
+            // the load would make the prefetch wait before the MFMAs; the
+            // empty asm statements (no instruction) hold the loaded values
+            // until this point
             auto stash = [&](int buf) {
 #pragma unroll
-                for (int e = 0; e < AE; ++e) As[buf][am0 + e * amE][ak0 + e * akE] = ra[e];
+                for (int e = 0; e < AE; ++e) {
+                    uint32_t t = ra[e];
+                    asm volatile("" : "+v"(t));
+                    ra[e] = (uint16_t)t;
+                }
+#pragma unroll
+                for (int e = 0; e < BE; ++e) {
+                    uint32_t t = rb[e];
+                    asm volatile("" : "+v"(t));
+                    rb[e] = (uint16_t)t;
+                }
+#pragma unroll
+                for (int e = 0; e < AE; ++e)
+                    As[buf][am0 + e * amE][ak0 + e * akE] = scale ? f2bf(alpha * bf2f(ra[e])) : ra[e];
 #pragma unroll
                 for (int e = 0; e < BE; ++e) Bs[buf][bn0 + e * bnE][bk0 + e * bkE] = rb[e];
             };
@@ -166,7 +189,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_bf16(const GJob* __restrict__
             }
         }
     }
-    uint16_t* C = at<uint16_t>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    gmem<uint16_t>* C = at<uint16_t>(J.C, bases) + (int64_t)tl.b * J.bsC;
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -177,7 +200,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_bf16(const GJob* __restrict__
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm0 + bi * 16 + 4 * lk + i;
                 if (row < J.M && col < J.N) {
-                    uint16_t* c = C + (int64_t)row * J.ldc + co;
+                    gmem<uint16_t>* c = C + (int64_t)row * J.ldc + co;
                     *c = f2bf(J.acc ? bf2f(*c) + acc[bi][bj][i] : acc[bi][bj][i]);
                 }
             }
@@ -194,18 +217,18 @@ __global__ __launch_bounds__(256) void k_sum_stage_bf16(const GJob* __restrict__
     const int64_t total = (int64_t)J.M * J.N;
     const int64_t e0 = (int64_t)tl.tm * SUM_TILE;
     const int64_t e1 = e0 + SUM_TILE < total ? e0 + SUM_TILE : total;
-    uint16_t* C = at<uint16_t>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    gmem<uint16_t>* C = at<uint16_t>(J.C, bases) + (int64_t)tl.b * J.bsC;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
         const int row = (int)(e / J.N), col = (int)(e % J.N);
         float acc = 0.0f;
         for (int p = J.p0; p < J.p1; ++p) {
             const GProd P = prods[p];
-            const uint16_t* Bb = at<const uint16_t>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            gmem<const uint16_t>* Bb = at<const uint16_t>(P.B, bases) + (int64_t)tl.b * P.bsB;
             const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
             acc += (float)P.alpha * bf2f(Bb[(int64_t)row * P.ldb + co]);
         }
         const int64_t cc = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
-        uint16_t* c = C + (int64_t)row * J.ldc + cc;
+        gmem<uint16_t>* c = C + (int64_t)row * J.ldc + cc;
         *c = f2bf(J.acc ? bf2f(*c) + acc : acc);
     }
 }

@@ -42,10 +42,19 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
+// Operand and output blocks of the GEMM kernels live in device (global)
+// memory; pointers read from the job lists are generic to the compiler,
+// which would emit flat loads, and a flat load also counts against the LDS
+// wait counter: every LDS wait of the MFMA loop would then wait for the
+// next chunk's operand prefetch too.  resolve() returns the pointer in the
+// global address space.
 template <typename T>
-__device__ __forceinline__ T* resolve(const GRef& r, const Bases& bs) {
-    if (r.tag == TAG_ABS) return (T*)r.abs;
-    return (T*)bs.b[r.tag] + r.off;
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ gmem<T>* resolve(const GRef& r, const Bases& bs) {
+    if (r.tag == TAG_ABS) return (gmem<T>*)r.abs;
+    return (gmem<T>*)bs.b[r.tag] + r.off;
 }
 
 // ---------------------------------------------------------------------
@@ -59,6 +68,18 @@ __device__ __forceinline__ T* resolve(const GRef& r, const Bases& bs) {
 // chunk c is multiplied, then stored into the other buffer, so a chunk
 // costs one barrier.  Each thread's element offsets are computed once per
 // product; a chunk only adds its k offset.
+// An empty asm statement per prefetched operand register (no instruction):
+// the values stay untouched until the stage that stores them to LDS, so the
+// compiler cannot place their first use, and the wait for their loads,
+// before the MFMAs that the prefetch is meant to overlap.
+template <typename T, int NA, int NB>
+__device__ __forceinline__ void hold_regs(T (&ra)[NA], T (&rb)[NB]) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) asm volatile("" : "+v"(ra[e]));
+#pragma unroll
+    for (int e = 0; e < NB; ++e) asm volatile("" : "+v"(rb[e]));
+}
+
 template <typename T> struct GemmK;
 template <> struct GemmK<float> { static constexpr int KC = 16; };
 template <> struct GemmK<double> { static constexpr int KC = 16; };
@@ -106,7 +127,7 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         // one product after the other, each with its own pipeline prologue
         for (int p = J.p0; p < J.p1; ++p) {
             const GProd P = prods[p];
-            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            gmem<const T>* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
             const T alpha = (T)P.alpha;
             if (P.ident) {
     #pragma unroll
@@ -124,7 +145,7 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
                     }
                 continue;
             }
-            const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
+            gmem<const T>* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
             const int nchunk = (P.K + KC - 1) / KC;
             // element e of this thread: A row am0 + e amE, A column (k) ak0 + e akE
             // within the chunk (and likewise for B), one branch-free form for
@@ -147,17 +168,17 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
                 bbase = (int64_t)bk0 * P.ldb + col;
             }
             for (int r = 0; r < P.nred; ++r) {
-                const T* A = Ab + (int64_t)r * P.rsA + abase;
-                const T* B = Bb + (int64_t)r * P.rsB + bbase;
+                gmem<const T>* A = Ab + (int64_t)r * P.rsA + abase;
+                gmem<const T>* B = Bb + (int64_t)r * P.rsB + bbase;
                 auto fetch = [&](int c) {
                     const int k0 = c * KC;
-                    const T* pa = A + k0 * akm;
-                    const T* pb = B + k0 * bkm;
+                    gmem<const T>* pa = A + k0 * akm;
+                    gmem<const T>* pb = B + k0 * bkm;
     #pragma unroll
                     for (int e = 0; e < AE; ++e) {
                         T v = (T)0;
                         if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
-                        ra[e] = v * alpha;
+                        ra[e] = v;
                     }
     #pragma unroll
                     for (int e = 0; e < BE; ++e) {
@@ -166,9 +187,12 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
                         rb[e] = v;
                     }
                 };
+                // alpha is applied here, not at the load: a use right after
+                // the load would make the prefetch wait before the MFMAs
                 auto stash = [&](int buf) {
+                    hold_regs(ra, rb);
     #pragma unroll
-                    for (int e = 0; e < AE; ++e) As[buf][ak0 + e * akE][am0 + e * amE] = ra[e];
+                    for (int e = 0; e < AE; ++e) As[buf][ak0 + e * akE][am0 + e * amE] = ra[e] * alpha;
     #pragma unroll
                     for (int e = 0; e < BE; ++e) Bs[buf][bk0 + e * bkE][bn0 + e * bnE] = rb[e];
                 };
@@ -203,7 +227,7 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         for (int p = J.p0; p < J.p1; ++p) {
             const GProd P = prods[p];
             if (!P.ident) continue;
-            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            gmem<const T>* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
             const T alpha = (T)P.alpha;
     #pragma unroll
             for (int bi = 0; bi < BM; ++bi)
@@ -222,8 +246,8 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         // chunk) steps: the next step's operands are fetched while the current
         // chunk is multiplied, also across product boundaries.
         struct Step {
-            const T* A;   // element 0 of this thread at k0 = 0
-            const T* B;
+            gmem<const T>* A;   // element 0 of this thread at k0 = 0
+            gmem<const T>* B;
             int64_t akm, aes, bkm, bes;
             int am0, amE, ak0, akE, bn0, bnE, bk0, bkE;
             int K, nchunk, nred;
@@ -231,8 +255,8 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         };
         auto describe = [&](int p, int r, Step& D) {
             const GProd P = prods[p];
-            const T* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
-            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            gmem<const T>* Ab = resolve<T>(P.A, bases) + (int64_t)tl.b * P.bsA;
+            gmem<const T>* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
             D.am0 = P.tA ? t_tm : t_kq;
             D.amE = P.tA ? 0 : ASA;
             D.ak0 = P.tA ? t_tq : t_kc;
@@ -264,13 +288,13 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         };
         auto fetch = [&](const Step& D, int c) {
             const int k0 = c * KC;
-            const T* pa = D.A + k0 * D.akm;
-            const T* pb = D.B + k0 * D.bkm;
+            gmem<const T>* pa = D.A + k0 * D.akm;
+            gmem<const T>* pb = D.B + k0 * D.bkm;
     #pragma unroll
             for (int e = 0; e < AE; ++e) {
                 T v = (T)0;
                 if (m0 + D.am0 + e * D.amE < J.M && k0 + D.ak0 + e * D.akE < D.K) v = pa[e * D.aes];
-                ra[e] = v * D.alpha;
+                ra[e] = v;
             }
     #pragma unroll
             for (int e = 0; e < BE; ++e) {
@@ -279,9 +303,11 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
                 rb[e] = v;
             }
         };
+        // alpha is applied here (see the loop pipeline)
         auto stash = [&](const Step& D, int buf) {
+            hold_regs(ra, rb);
     #pragma unroll
-            for (int e = 0; e < AE; ++e) As[buf][D.ak0 + e * D.akE][D.am0 + e * D.amE] = ra[e];
+            for (int e = 0; e < AE; ++e) As[buf][D.ak0 + e * D.akE][D.am0 + e * D.amE] = ra[e] * D.alpha;
     #pragma unroll
             for (int e = 0; e < BE; ++e) Bs[buf][D.bk0 + e * D.bkE][D.bn0 + e * D.bnE] = rb[e];
         };
@@ -333,7 +359,7 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
             }
         }
     }
-    T* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    gmem<T>* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -344,7 +370,7 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
                 if (row < J.M && col < J.N) {
-                    T* c = C + (int64_t)row * J.ldc + co;
+                    gmem<T>* c = C + (int64_t)row * J.ldc + co;
                     *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
                 }
             }
@@ -365,7 +391,7 @@ __global__ __launch_bounds__(256) void k_sum_stage(const GJob* __restrict__ jobs
     const int64_t total = (int64_t)J.M * J.N;
     const int64_t e0 = (int64_t)tl.tm * SUM_TILE;
     const int64_t e1 = e0 + SUM_TILE < total ? e0 + SUM_TILE : total;
-    T* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    gmem<T>* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
         const int row = (int)(e / J.N), col = (int)(e % J.N);
         T acc = (T)0;
@@ -376,7 +402,7 @@ __global__ __launch_bounds__(256) void k_sum_stage(const GJob* __restrict__ jobs
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const GProd& P = prods[p + u];
-                const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+                gmem<const T>* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
                 const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
                 v[u] = Bb[(int64_t)row * P.ldb + co];
                 al[u] = (T)P.alpha;
@@ -386,12 +412,12 @@ __global__ __launch_bounds__(256) void k_sum_stage(const GJob* __restrict__ jobs
         }
         for (; p < J.p1; ++p) {
             const GProd P = prods[p];
-            const T* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
+            gmem<const T>* Bb = resolve<T>(P.B, bases) + (int64_t)tl.b * P.bsB;
             const int64_t co = P.nsb ? (int64_t)(col / P.nsb) * P.nob + col % P.nsb : col;
             acc += (T)P.alpha * Bb[(int64_t)row * P.ldb + co];
         }
         const int64_t cc = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
-        T* c = C + (int64_t)row * J.ldc + cc;
+        gmem<T>* c = C + (int64_t)row * J.ldc + cc;
         *c = J.acc ? *c + acc : acc;
     }
 }
@@ -490,7 +516,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ 
     const int sw = ((lr & 2) << 2);       // the A swizzle of row m (m % 4 = lr % 4)
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
-        const float* Bb = resolve<float>(P.B, bases) + (int64_t)tl.b * P.bsB;
+        gmem<const float>* Bb = resolve<float>(P.B, bases) + (int64_t)tl.b * P.bsB;
         if (P.ident) {
             const float alpha = (float)P.alpha;
 #pragma unroll
@@ -507,7 +533,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ 
                 }
             continue;
         }
-        const float* Ab = resolve<float>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        const float* Ab = (const float*)(resolve<float>(P.A, bases) + (int64_t)tl.b * P.bsA);
         const float alpha = (float)P.alpha;
         const int nchunk = (P.K + KC - 1) / KC;
         // B instruction j of this wave: row wave IB / HS + j / HS of the
@@ -597,7 +623,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ 
             }
         }
     }
-    float* C = resolve<float>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    gmem<float>* C = resolve<float>(J.C, bases) + (int64_t)tl.b * J.bsC;
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -608,7 +634,7 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ 
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm0 + bi * 16 + Mfma<float>::row(lane, i);
                 if (row < J.M && col < J.N) {
-                    float* c = C + (int64_t)row * J.ldc + co;
+                    gmem<float>* c = C + (int64_t)row * J.ldc + co;
                     *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
                 }
             }
@@ -653,8 +679,8 @@ __device__ __forceinline__ void skinny_fetch(SkinnyRegs<T>& R, const GJob& J, co
     const int K = P.K, Kp = (K + 3) & ~3;
     const int rows = min(RS, J.M - m0);
     const float inv = 1.0f / (float)Kp;
-    const T* A = resolve<T>(P.A, bases) + (int64_t)m0 * K;
-    const T* B = resolve<T>(P.B, bases);
+    gmem<const T>* A = resolve<T>(P.A, bases) + (int64_t)m0 * K;
+    gmem<const T>* B = resolve<T>(P.B, bases);
 #pragma unroll
     for (int u = 0; u < SkinnyRegs<T>::UA; ++u) {
         const int e = tid + 256 * u;
@@ -745,7 +771,7 @@ __device__ __forceinline__ void skinny_strip(const GJob& J, int m0, const GProd*
         }
     __syncthreads();
     const int rows = min(64 * BMR, J.M - m0);
-    T* C = resolve<T>(J.C, bases) + (int64_t)m0 * N;
+    gmem<T>* C = resolve<T>(J.C, bases) + (int64_t)m0 * N;
     const int tot = rows * N;
 #pragma unroll 8
     for (int e = tid; e < tot; e += 256) C[e] = Cs[e];
@@ -867,7 +893,7 @@ __global__ __launch_bounds__(256, 2) void k_brgemm_dma64(const GJob* __restrict_
     }
     for (int p = J.p0; p < J.p1; ++p) {
         const GProd P = prods[p];
-        const double* Bb = resolve<double>(P.B, bases) + (int64_t)tl.b * P.bsB;
+        gmem<const double>* Bb = resolve<double>(P.B, bases) + (int64_t)tl.b * P.bsB;
         if (P.ident) {
             const double alpha = P.alpha;
 #pragma unroll
@@ -884,7 +910,7 @@ __global__ __launch_bounds__(256, 2) void k_brgemm_dma64(const GJob* __restrict_
                 }
             continue;
         }
-        const double* Ab = resolve<double>(P.A, bases) + (int64_t)tl.b * P.bsA;
+        const double* Ab = (const double*)(resolve<double>(P.A, bases) + (int64_t)tl.b * P.bsA);
         const double alpha = P.alpha;
         const int nchunk = (P.K + KC - 1) / KC;
         // byte offsets of this lane's words relative to the chunk's first
@@ -961,7 +987,7 @@ __global__ __launch_bounds__(256, 2) void k_brgemm_dma64(const GJob* __restrict_
             }
         }
     }
-    double* C = resolve<double>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    gmem<double>* C = resolve<double>(J.C, bases) + (int64_t)tl.b * J.bsC;
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -972,7 +998,7 @@ __global__ __launch_bounds__(256, 2) void k_brgemm_dma64(const GJob* __restrict_
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm0 + bi * 16 + Mfma<double>::row(lane, i);
                 if (row < J.M && col < J.N) {
-                    double* c = C + (int64_t)row * J.ldc + co;
+                    gmem<double>* c = C + (int64_t)row * J.ldc + co;
                     *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
                 }
             }
