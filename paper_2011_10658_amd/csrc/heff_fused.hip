@@ -104,10 +104,16 @@ template <int N> struct IC {
         default: break;                   \
     }
 
+// blocks in device (global) memory: global rather than flat loads, so that
+// the LDS waits of the MFMA loops and epilogues do not also wait for the
+// operand prefetch (flat loads count against the LDS counter)
 template <typename T>
-__device__ __forceinline__ const T* fres(const GRef& r, const Bases& bs) {
-    if (r.tag == TAG_ABS) return (const T*)r.abs;
-    return (const T*)bs.b[r.tag] + r.off;
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ gmem<const T>* fres(const GRef& r, const Bases& bs) {
+    if (r.tag == TAG_ABS) return (gmem<const T>*)r.abs;
+    return (gmem<const T>*)bs.b[r.tag] + r.off;
 }
 
 template <typename T, int WC>
@@ -167,17 +173,18 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
 
     // operand pointers of the product being fetched
     struct Src {
-        const T* F;      // row fm, column fk of chunk 0 (rows m0 + fm)
-        const T* X;      // row xk, column xc of chunk 0
+        gmem<const T>* F;   // row fm, column fk of chunk 0 (rows m0 + fm)
+        gmem<const T>* X;   // row xk, column xc of chunk 0
         int64_t fes;     // F stride between this thread's elements
         int64_t xkm;     // X stride per k row
         int K, nchunk;
         bool xok;        // this thread's X column is inside the tile's groups
         T alpha;
     };
+    Src S{};   // the product whose chunks are fetched
     auto describe = [&](const FProd& P, Src& S) {
-        const T* Fb = fres<T>(P.F, bases);
-        const T* Xb = fres<T>(P.X, bases);
+        gmem<const T>* Fb = fres<T>(P.F, bases);
+        gmem<const T>* Xb = fres<T>(P.X, bases);
         S.F = Fb + (int64_t)(m0 + fm) * P.lda + fk;
         S.fes = (int64_t)16 * P.lda;
         S.xok = xc < ngv * P.np_in;
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
         for (int e = 0; e < AE; ++e) {
             T v = (T)0;
             if (m0 + fm + 16 * e < J.M && k0 + fk < S.K) v = S.F[e * S.fes + k0];
-            ra[e] = v * S.alpha;
+            ra[e] = v;
         }
 #pragma unroll
         for (int e = 0; e < XE; ++e) {
@@ -203,11 +210,19 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
             rx[e] = v;
         }
     };
+    // the product's alpha is applied here, not at the load: a use right after
+    // the load would make the prefetch wait before the work it overlaps; the
+    // empty asm statements (no instruction) hold the loaded values until now.
+    // S describes the fetched chunk's product whenever a chunk is stashed.
     auto stash = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) asm volatile("" : "+v"(ra[e]));
+#pragma unroll
+        for (int e = 0; e < XE; ++e) asm volatile("" : "+v"(rx[e]));
         T* As = lds + buf * (A_WORDS + X_WORDS);
         T* Xs = As + A_WORDS;
 #pragma unroll
-        for (int e = 0; e < AE; ++e) As[(fm + 16 * e) * LDA + fk] = ra[e];
+        for (int e = 0; e < AE; ++e) As[(fm + 16 * e) * LDA + fk] = ra[e] * S.alpha;
 #pragma unroll
         for (int e = 0; e < XE; ++e) Xs[(xk + XR * e) * LDX + xc] = rx[e];
     };
@@ -215,7 +230,7 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
     // for k < np_in, c' < p16 (zero beyond np); loads of a batch in flight
     // together
     auto load_c = [&](const FProd& P) {
-        const T* Cb = fres<T>(P.Cb, bases);
+        gmem<const T>* Cb = fres<T>(P.Cb, bases);
         const int npi = P.np_in, n = npi * p16;
         for (int base = 0; base < n; base += 256 * CE) {
             T cr[CE];
@@ -240,7 +255,6 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
         }
     };
 
-    Src S{};
     bool have = false;   // ra/rx hold the first chunk of product p
     for (int p = J.p0; p < J.p1; ++p) {
         const FProd P = prods[p];
@@ -251,11 +265,11 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
         if (P.identF) {
             // W = alpha X: rows m0.. of the tile straight from X; this thread
             // keeps one column and loads IB rows at a time
-            const T* Xb = fres<T>(P.X, bases);
+            gmem<const T>* Xb = fres<T>(P.X, bases);
             const T alpha = (T)P.alpha;
             const bool cok = xc < ngv * npi;
             const int g = xc / npi, cc = xc - g * npi;
-            const T* xp = Xb + (int64_t)(g0 + g) * P.gox + cc;
+            gmem<const T>* xp = Xb + (int64_t)(g0 + g) * P.gox + cc;
 #pragma unroll
             for (int r0 = 0; r0 < TM; r0 += XR * IB) {
                 T v[IB];
@@ -369,18 +383,18 @@ __global__ __launch_bounds__(256, 3) void k_heff_fused(const FJob* __restrict__ 
         }
     }
     if (!wrows) return;
-    T* Y = (T*)fres<T>(J.Y, bases);
+    gmem<T>* Y = (gmem<T>*)fres<T>(J.Y, bases);
 #pragma unroll
     for (int j = 0; j < NB; ++j)
         if (j < nyb) {
             const int g = (16 * j) / p16, cp = (16 * j) % p16 + lr;
             if (cp >= J.np) continue;
-            T* yg = Y + (int64_t)(g0 + g) * J.goy + cp;
+            gmem<T>* yg = Y + (int64_t)(g0 + g) * J.goy + cp;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wr0 + FMfma<T>::row(lane, i);
                 if (row < J.M) {
-                    T* y = yg + (int64_t)row * J.ldy;
+                    gmem<T>* y = yg + (int64_t)row * J.ldy;
                     *y = J.acc ? *y + accy[j][i] : accy[j][i];
                 }
             }
