@@ -480,7 +480,9 @@ int qed_heff_batch_matvec(qed_heff_batch* b, const double* x, double* y);
  * estimates.  use_graph != 0 replays a HIP graph of one whole cycle
  * (captured on first use for this step count).  Cycles and tolerance as
  * set by qed_set_lanczos (a cycle ends for all nodes when every node has
- * converged). */
+ * converged).  The recurrence runs in FP64; with FP32 GEMMs and at most 31
+ * steps the Krylov basis is stored in FP32 (the matvec reads its input
+ * from it; environment QEDTTN_LZ_BASIS=fp64 keeps it in FP64). */
 int qed_heff_batch_lanczos(qed_heff_batch* b, double* x_inout, int steps, double* evals,
                            double* resids, int use_graph);
 

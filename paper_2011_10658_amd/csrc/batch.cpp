@@ -1,6 +1,7 @@
 // Batched node updates: many independent tree nodes of uneven shape share
 // one grouped block-GEMM launch per contraction stage and one segmented
-// FP64 Lanczos (one recurrence per node).  A whole Lanczos cycle is
+// Lanczos (one recurrence per node, FP64 arithmetic; an FP32 plan keeps the
+// basis in FP32).  A whole Lanczos cycle is
 // captured once into a HIP graph and replayed.  The GEMM tile shape and
 // operand pipeline of every stage can be chosen by timing (autotuner)
 // instead of the padding and reduction-length heuristics.
@@ -9,6 +10,7 @@
 #include <cstdio>
 #include <fstream>
 #include <sstream>
+#include <type_traits>
 
 #include "engine.h"
 
@@ -17,10 +19,11 @@ namespace qed {
 // ---------------------------------------------------------------------
 // segmented Lanczos
 // ---------------------------------------------------------------------
-void SegLanczos::setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t NN, int mm) {
+void SegLanczos::setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t NN, int mm, bool basis32) {
     nseg = (int)seg_off.size() - 1;
     N = NN;
     m = mm;
+    b32 = basis32 && m + 1 <= 32;
     const int64_t CH = 4096;
     std::vector<SegChunk> ch;
     std::vector<int> c0;
@@ -35,7 +38,7 @@ void SegLanczos::setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t NN
     seg_c0 = std::make_shared<DBuf>(dev, c0.size() * sizeof(int));
     dev->upload(chunks->p, ch.data(), ch.size() * sizeof(SegChunk));
     dev->upload(seg_c0->p, c0.data(), c0.size() * sizeof(int));
-    V = std::make_shared<DBuf>(dev, (size_t)(m + 1) * N * sizeof(double));
+    V = std::make_shared<DBuf>(dev, (size_t)(m + 1) * N * (b32 ? sizeof(float) : sizeof(double)));
     w = std::make_shared<DBuf>(dev, (size_t)N * sizeof(double));
     const size_t ps = (size_t)nseg * LDS * sizeof(double);
     alpha = std::make_shared<DBuf>(dev, ps);
@@ -52,11 +55,10 @@ void SegLanczos::setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t NN
     fac = std::make_shared<DBuf>(dev, (size_t)nseg * sizeof(double));
 }
 
-void SegLanczos::cycle(const std::function<void(const double*, double*)>& apply, double* x,
+void SegLanczos::cycle(const std::function<void(const double*, const float*, double*)>& apply, double* x,
                        hipStream_t s) {
     const SegChunk* ch = chunks->as<SegChunk>();
     const int* c0 = seg_c0->as<int>();
-    double* Vp = V->as<double>();
     double* wp = w->as<double>();
     double* al = alpha->as<double>();
     double* be = beta->as<double>();
@@ -65,36 +67,47 @@ void SegLanczos::cycle(const std::function<void(const double*, double*)>& apply,
     double* part = partial->as<double>();
     double* nr = nrm->as<double>();
     LState* sp = st->as<LState>();
-    seg_dots(x, N, 1, x, ch, nch, c0, nseg, part, nr + 0, LDN, 1, sp, 0, s);
-    seg_init(sp, nseg, m, nr + 0, LDN, s);
-    seg_start(Vp, x, nr + 0, LDN, ch, nch, s);
-    for (int j = 0; j < m; ++j) {
-        double* vj = Vp + (int64_t)j * N;
-        apply(vj, wp);
-        seg_dots(vj, N, 1, wp, ch, nch, c0, nseg, part, al + j, LDS, 0, sp, 1, s);
-        // three-term recurrence, classical Gram-Schmidt against V with a
-        // second pass where a segment's first one removed more than half
-        // of |w|^2, norm: three fused passes over the basis
-        if (seg_fused(0, wp, Vp, N, 0, j, al, be, LDS, nullptr, nullptr, ch, nch, c0, nseg, part, co, LDS, sp,
-                      s)) {
-            seg_fused(1, wp, Vp, N, j + 1, j, al, be, LDS, co, co, ch, nch, c0, nseg, part, co2, LDS, sp, s);
-            seg_fused(2, wp, Vp, N, j + 1, j, al, be, LDS, co2, co, ch, nch, c0, nseg, part, nr + 1, LDN, sp, s);
-        } else {
-            seg_three_term(wp, Vp, N, j, al, be, LDS, ch, nch, sp, s);
-            for (int pass = 0; pass < 2; ++pass) {
-                seg_dots(Vp, N, j + 1, wp, ch, nch, c0, nseg, part, co, LDS, 0, sp, 1, s);
-                seg_subtract(wp, Vp, N, j + 1, co, LDS, ch, nch, sp, s);
+    auto run = [&](auto* Vp) {
+        using TV = typename std::remove_pointer<decltype(Vp)>::type;
+        constexpr bool F64 = std::is_same<TV, double>::value;
+        seg_dots<double>(x, N, 1, x, ch, nch, c0, nseg, part, nr + 0, LDN, 1, sp, 0, s);
+        seg_init(sp, nseg, m, nr + 0, LDN, s);
+        seg_start<TV>(Vp, x, nr + 0, LDN, ch, nch, s);
+        for (int j = 0; j < m; ++j) {
+            TV* vj = Vp + (int64_t)j * N;
+            if constexpr (F64) apply(vj, nullptr, wp);
+            else apply(nullptr, vj, wp);
+            seg_dots<TV>(vj, N, 1, wp, ch, nch, c0, nseg, part, al + j, LDS, 0, sp, 1, s);
+            // three-term recurrence, classical Gram-Schmidt against V with a
+            // second pass where a segment's first one removed more than half
+            // of |w|^2, norm: three fused passes over the basis
+            if (seg_fused<TV>(0, wp, Vp, N, 0, j, al, be, LDS, nullptr, nullptr, ch, nch, c0, nseg, part, co, LDS,
+                              sp, s)) {
+                seg_fused<TV>(1, wp, Vp, N, j + 1, j, al, be, LDS, co, co, ch, nch, c0, nseg, part, co2, LDS, sp, s);
+                seg_fused<TV>(2, wp, Vp, N, j + 1, j, al, be, LDS, co2, co, ch, nch, c0, nseg, part, nr + 1, LDN, sp,
+                              s);
+            } else {
+                // (an FP32 basis always fits the fused passes: m + 1 <= 32)
+                if constexpr (F64) {
+                    seg_three_term(wp, Vp, N, j, al, be, LDS, ch, nch, sp, s);
+                    for (int pass = 0; pass < 2; ++pass) {
+                        seg_dots<double>(Vp, N, j + 1, wp, ch, nch, c0, nseg, part, co, LDS, 0, sp, 1, s);
+                        seg_subtract(wp, Vp, N, j + 1, co, LDS, ch, nch, sp, s);
+                    }
+                    seg_dots<double>(wp, N, 1, wp, ch, nch, c0, nseg, part, nr + 1, LDN, 0, sp, 1, s);
+                }
             }
-            seg_dots(wp, N, 1, wp, ch, nch, c0, nseg, part, nr + 1, LDN, 0, sp, 1, s);
+            seg_beta(nr + 1, LDN, al, be, LDS, j, sp, nseg, 1e-14, s);
+            seg_next<TV>(Vp, N, j, wp, be, LDS, ch, nch, sp, s);
         }
-        seg_beta(nr + 1, LDN, al, be, LDS, j, sp, nseg, 1e-14, s);
-        seg_next(Vp, N, j, wp, be, LDS, ch, nch, sp, s);
-    }
-    seg_tridiag(al, be, LDS, sv->as<double>(), sp, work->as<double>(), nseg, s);
-    seg_ritz(x, Vp, N, sv->as<double>(), LDS, ch, nch, sp, s);
-    seg_dots(x, N, 1, x, ch, nch, c0, nseg, part, nr + 2, LDN, 1, sp, 0, s);
-    seg_normalise_sign(x, ch, nch, c0, nseg, nr + 2, LDN, pv->as<double>(), pi->as<int64_t>(),
-                       fac->as<double>(), s);
+        seg_tridiag(al, be, LDS, sv->as<double>(), sp, work->as<double>(), nseg, s);
+        seg_ritz<TV>(x, Vp, N, sv->as<double>(), LDS, ch, nch, sp, s);
+        seg_dots<double>(x, N, 1, x, ch, nch, c0, nseg, part, nr + 2, LDN, 1, sp, 0, s);
+        seg_normalise_sign(x, ch, nch, c0, nseg, nr + 2, LDN, pv->as<double>(), pi->as<int64_t>(),
+                           fac->as<double>(), s);
+    };
+    if (b32) run(V->as<float>());
+    else run(V->as<double>());
 }
 
 // ---------------------------------------------------------------------
@@ -193,6 +206,15 @@ void HeffBatch::matvec(const double* x, double* y, hipStream_t s) {
         plan.run(dev, ws->p, xc->p, yc->p);
         from_compute(plan.dtype, yc->p, y, off.back(), s);
     }
+    dev->stream = keep;
+}
+
+void HeffBatch::matvec32(const float* x, double* y, hipStream_t s) {
+    Dev* dev = &ctx->dev;
+    hipStream_t keep = dev->stream;
+    dev->stream = s;
+    plan.run(dev, ws->p, (void*)x, yc->p);
+    from_compute(plan.dtype, yc->p, y, off.back(), s);
     dev->stream = keep;
 }
 

@@ -1138,10 +1138,25 @@ int qed_heff_batch_lanczos(qed_heff_batch* b, double* x, int steps, double* eval
         const Params& P = c.prm;
         const int m = steps > 0 ? steps : P.lz_steps;
         if (m < 1 || m > 64) fail(QED_ERR_INVALID_ARG, "1 .. 64 Lanczos steps");
-        if (B.lz.m != m || B.lz.nseg != B.nn) B.lz.setup(&dev, B.off, B.off.back(), m);
+        // an FP32 plan keeps the basis in FP32 (its matvec reads the basis
+        // row itself), as the sweep path does; QEDTTN_LZ_BASIS=fp64 keeps it
+        // in FP64
+        const char* bv = std::getenv("QEDTTN_LZ_BASIS");
+        const bool b32 = B.plan.dtype == QED_FP32 && m + 1 <= 32 && !(bv && !std::strcmp(bv, "fp64"));
+        if (B.lz.m != m || B.lz.nseg != B.nn || B.lz.b32 != b32) {
+            B.lz.setup(&dev, B.off, B.off.back(), m, b32);
+            // a captured cycle refers to the old buffers
+            if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
+            if (B.graph) (void)hipGraphDestroy(B.graph);
+            B.gexec = nullptr;
+            B.graph = nullptr;
+        }
         // the batch runs on its own stream (graph capture needs one)
         dev.sync();
-        auto apply = [&](const double* v, double* y) { B.matvec(v, y, B.stream); };
+        auto apply = [&](const double* v, const float* v32, double* y) {
+            if (v32) B.matvec32(v32, y, B.stream);
+            else B.matvec(v, y, B.stream);
+        };
         if (use_graph && (!B.gexec || B.gm != m || B.gx != x)) {
             if (B.gexec) (void)hipGraphExecDestroy(B.gexec);
             if (B.graph) (void)hipGraphDestroy(B.graph);

@@ -88,14 +88,19 @@ void launch_jacobi_svd(const SvdMat*, int nmats, hipStream_t);
 void launch_chol_inv(const CholMat*, int nmats, int maxn, hipStream_t);
 void launch_axpy(double* y, const double* x, double f, int64_t n, hipStream_t);
 
-void seg_dots(const double*, int64_t, int, const double*, const SegChunk*, int, const int*, int,
-              double*, double*, int, int, const LState*, int, hipStream_t);
+// (TV: the basis element type, double or float; w, the coefficients and
+// the Ritz vector are FP64 either way)
+template <typename TV>
+void seg_dots(const TV* V, int64_t ldv, int nrows, const double* w, const SegChunk* ch, int nch, const int* seg_c0,
+              int nseg, double* partial, double* out, int ldo, int mode, const LState* st, int skip, hipStream_t s);
 void seg_init(LState*, int, int, const double*, int, hipStream_t);
-void seg_start(double*, const double*, const double*, int, const SegChunk*, int, hipStream_t);
+template <typename TV>
+void seg_start(TV* dst, const double* src, const double* nrm, int ldn, const SegChunk* ch, int nch, hipStream_t s);
 // one fused pass of a Lanczos step per segment (mode 0, 1, 2 as in
 // launch_lz_fused), with its final sums into out[seg * ldo + r]; false
 // (nothing launched) when the pass would need more than 32 rows
-bool seg_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j, const double* al,
+template <typename TV>
+bool seg_fused(int mode, double* w, const TV* V, int64_t ldv, int nrows, int j, const double* al,
                const double* be, int lds, const double* c, const double* cf, const SegChunk* ch, int nch,
                const int* seg_c0, int nseg, double* partial, double* out, int ldo, const LState* st,
                hipStream_t s);
@@ -104,11 +109,13 @@ void seg_three_term(double*, const double*, int64_t, int, const double*, const d
 void seg_subtract(double*, const double*, int64_t, int, const double*, int, const SegChunk*, int,
                   const LState*, hipStream_t);
 void seg_beta(const double*, int, double*, double*, int, int, LState*, int, double, hipStream_t);
-void seg_next(double*, int64_t, int, const double*, const double*, int, const SegChunk*, int,
-              const LState*, hipStream_t);
+template <typename TV>
+void seg_next(TV* V, int64_t ldv, int j, const double* w, const double* be, int lds, const SegChunk* ch, int nch,
+              const LState* st, hipStream_t s);
 void seg_tridiag(const double*, const double*, int, double*, LState*, double*, int, hipStream_t);
-void seg_ritz(double*, const double*, int64_t, const double*, int, const SegChunk*, int,
-              const LState*, hipStream_t);
+template <typename TV>
+void seg_ritz(double* u, const TV* V, int64_t ldv, const double* sv, int lds, const SegChunk* ch, int nch,
+              const LState* st, hipStream_t s);
 void seg_normalise_sign(double*, const SegChunk*, int, const int*, int, const double*, int,
                         double*, int64_t*, double*, hipStream_t);
 
@@ -541,10 +548,15 @@ struct SegLanczos {
     static constexpr int LDN = 8;    // per-segment norm slots
     int nseg = 0, nch = 0, m = 0;
     int64_t N = 0;
+    bool b32 = false;                // the basis V is stored in FP32
     BufP chunks, seg_c0, V, w, alpha, beta, coef, coef2, sv, work, st, partial, pv, pi, nrm, fac;
-    void setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t N, int m);
-    // enqueue one cycle on `s` (no host synchronisation: capturable)
-    void cycle(const std::function<void(const double*, double*)>& apply, double* x, hipStream_t s);
+    // b32 (an FP32 basis) needs m + 1 <= 32, the rows of the fused passes
+    void setup(Dev* dev, const std::vector<int64_t>& seg_off, int64_t N, int m, bool b32);
+    // enqueue one cycle on `s` (no host synchronisation: capturable);
+    // apply(v, v32, y): y = H v with the basis vector in FP64 (v) or, for an
+    // FP32 basis, in FP32 (v32; v null)
+    void cycle(const std::function<void(const double*, const float*, double*)>& apply, double* x,
+               hipStream_t s);
 };
 
 // ---- autotuner of the GEMM tile shape and pipeline per plan stage --------
@@ -574,6 +586,8 @@ struct HeffBatch {
     double* gx = nullptr;
     int gm = 0;
     void matvec(const double* x, double* y, hipStream_t s);
+    // y = H x with x already in the plan's FP32 compute type
+    void matvec32(const float* x, double* y, hipStream_t s);
     ~HeffBatch();
 };
 

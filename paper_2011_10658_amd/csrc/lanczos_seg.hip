@@ -1,5 +1,7 @@
-// Segmented FP64 Lanczos kernels: one independent recurrence per segment
-// of a concatenated vector (many tree nodes optimised at once).  Work is
+// Segmented Lanczos kernels: one independent recurrence per segment of a
+// concatenated vector (many tree nodes optimised at once), in FP64; the
+// basis is stored in FP64 or, for an FP32 matvec, in FP32 (TV, the basis
+// element type).  Work is
 // split into fixed chunks that never straddle a segment, so every
 // reduction has a fixed partition and order (bitwise reproducible), and
 // per-segment scalars (alpha, beta, coefficients, state) live on the
@@ -17,7 +19,8 @@ __device__ __forceinline__ double seg_wave_sum(double v) {
 constexpr int SROWS = 8;
 
 // partial[r * nch + c] = sum over chunk c of V[r] . w   (r < nrows)
-__global__ __launch_bounds__(256) void k_sdot_partial(const double* __restrict__ V, int64_t ldv,
+template <typename TV>
+__global__ __launch_bounds__(256) void k_sdot_partial(const TV* __restrict__ V, int64_t ldv,
                                                       int nrows, const double* __restrict__ w,
                                                       const SegChunk* __restrict__ ch, int nch,
                                                       double* __restrict__ partial,
@@ -33,7 +36,7 @@ __global__ __launch_bounds__(256) void k_sdot_partial(const double* __restrict__
             const double wi = w[i];
 #pragma unroll
             for (int q = 0; q < SROWS; ++q)
-                if (r0 + q < nrows) s[q] += V[(int64_t)(r0 + q) * ldv + i] * wi;
+                if (r0 + q < nrows) s[q] += (double)V[(int64_t)(r0 + q) * ldv + i] * wi;
         }
 #pragma unroll
         for (int q = 0; q < SROWS; ++q) {
@@ -79,11 +82,12 @@ __global__ void k_s_init(LState* st, int nseg, int m, const double* nrm, int ldn
 }
 
 // dst = src / nrm[seg]
-__global__ void k_s_start(double* __restrict__ dst, const double* __restrict__ src,
+template <typename TV>
+__global__ void k_s_start(TV* __restrict__ dst, const double* __restrict__ src,
                           const double* __restrict__ nrm, int ldn, const SegChunk* __restrict__ ch) {
     const SegChunk C = ch[blockIdx.x];
     const double inv = 1.0 / nrm[(int64_t)C.seg * ldn];
-    for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) dst[i] = src[i] * inv;
+    for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) dst[i] = (TV)(src[i] * inv);
 }
 
 // w -= alpha[seg][j] v_j + beta[seg][j-1] v_{j-1}
@@ -139,14 +143,15 @@ __global__ void k_s_beta(const double* ww, int ldw, double* alpha, double* beta,
 }
 
 // V[j+1] = w / beta[seg][j]
-__global__ void k_s_next(double* __restrict__ V, int64_t ldv, int j, const double* __restrict__ w,
+template <typename TV>
+__global__ void k_s_next(TV* __restrict__ V, int64_t ldv, int j, const double* __restrict__ w,
                          const double* __restrict__ beta, int lds, const SegChunk* __restrict__ ch,
                          const LState* st) {
     const SegChunk C = ch[blockIdx.x];
     if (st[C.seg].broken) return;
     const double inv = 1.0 / beta[(int64_t)C.seg * lds + j];
-    double* v = V + (int64_t)(j + 1) * ldv;
-    for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) v[i] = w[i] * inv;
+    TV* v = V + (int64_t)(j + 1) * ldv;
+    for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) v[i] = (TV)(w[i] * inv);
 }
 
 // Fused vector update + dot products of one Lanczos step, segment by
@@ -173,8 +178,8 @@ __device__ __forceinline__ bool s_second_pass(const double* cf, int nrows) {
     return 2.0 * p > cf[nrows];
 }
 
-template <int MAXR>
-__global__ __launch_bounds__(256) void k_s_fused(double* __restrict__ w, const double* __restrict__ V,
+template <int MAXR, typename TV>
+__global__ __launch_bounds__(256) void k_s_fused(double* __restrict__ w, const TV* __restrict__ V,
                                                  int64_t ldv, int mode, int nrows, int j,
                                                  const double* __restrict__ alpha,
                                                  const double* __restrict__ beta, int lds,
@@ -202,13 +207,23 @@ __global__ __launch_bounds__(256) void k_s_fused(double* __restrict__ w, const d
 #pragma unroll
     for (int q = 0; q < MAXR; ++q) s[q] = 0.0;
     for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) {
+        // every row's load is issued before any is converted (an FP32 row
+        // converted inside its guarded load would wait for each load in
+        // turn); the empty asm statements (no instruction) hold the values
+        TV vt[MAXR];
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) vt[r] = r < nr ? V[(int64_t)r * ldv + i] : (TV)0;
+        if constexpr (sizeof(TV) == 4) {
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) asm volatile("" : "+v"(vt[r]));
+        }
         double v[MAXR];
 #pragma unroll
-        for (int r = 0; r < MAXR; ++r) v[r] = r < nr ? V[(int64_t)r * ldv + i] : 0.0;
+        for (int r = 0; r < MAXR; ++r) v[r] = (double)vt[r];
         double wi = w[i];
         if (mode == 0) {
-            double t = a * V[(int64_t)j * ldv + i];
-            if (j > 0) t += b * V[(int64_t)(j - 1) * ldv + i];
+            double t = a * (double)V[(int64_t)j * ldv + i];
+            if (j > 0) t += b * (double)V[(int64_t)(j - 1) * ldv + i];
             wi -= t;
         } else {
             double t = 0.0;
@@ -335,7 +350,8 @@ __global__ void k_s_tridiag(const double* alpha, const double* beta, int lds, do
 }
 
 // u = sum_{r < k_seg} s[seg][r] V[r]
-__global__ void k_s_ritz(double* __restrict__ u, const double* __restrict__ V, int64_t ldv,
+template <typename TV>
+__global__ void k_s_ritz(double* __restrict__ u, const TV* __restrict__ V, int64_t ldv,
                          const double* __restrict__ sv, int lds, const SegChunk* __restrict__ ch,
                          const LState* st) {
     const SegChunk C = ch[blockIdx.x];
@@ -343,7 +359,7 @@ __global__ void k_s_ritz(double* __restrict__ u, const double* __restrict__ V, i
     const double* s = sv + (int64_t)C.seg * lds;
     for (int64_t i = C.lo + threadIdx.x; i < C.hi; i += 256) {
         double t = 0.0;
-        for (int r = 0; r < k; ++r) t += s[r] * V[(int64_t)r * ldv + i];
+        for (int r = 0; r < k; ++r) t += s[r] * (double)V[(int64_t)r * ldv + i];
         u[i] = t;
     }
 }
@@ -405,25 +421,27 @@ __global__ void k_s_scale(double* __restrict__ u, const double* __restrict__ fac
 }
 
 // ---------------------------------------------------------------------
-void seg_dots(const double* V, int64_t ldv, int nrows, const double* w, const SegChunk* ch, int nch,
+template <typename TV>
+void seg_dots(const TV* V, int64_t ldv, int nrows, const double* w, const SegChunk* ch, int nch,
               const int* seg_c0, int nseg, double* partial, double* out, int ldo, int mode,
               const LState* st, int skip, hipStream_t s) {
-    hipLaunchKernelGGL(k_sdot_partial, dim3(nch), dim3(256), 0, s, V, ldv, nrows, w, ch, nch,
+    hipLaunchKernelGGL(k_sdot_partial<TV>, dim3(nch), dim3(256), 0, s, V, ldv, nrows, w, ch, nch,
                        partial, st, skip);
     hipLaunchKernelGGL(k_sdot_final, dim3(nseg * nrows), dim3(256), 0, s, partial, nch, seg_c0,
                        nrows, out, ldo, mode, st, skip);
 }
-bool seg_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int j, const double* al,
+template <typename TV>
+bool seg_fused(int mode, double* w, const TV* V, int64_t ldv, int nrows, int j, const double* al,
                const double* be, int lds, const double* c, const double* cf, const SegChunk* ch, int nch,
                const int* seg_c0, int nseg, double* partial, double* out, int ldo, const LState* st,
                hipStream_t s) {
     const int nr = mode == 0 ? j + 1 : nrows;
     if (nr + 1 > 32) return false;   // mode 0 also needs the row of w.w
     if (nr + 1 <= 16)
-        hipLaunchKernelGGL(k_s_fused<16>, dim3(nch), dim3(256), 0, s, w, V, ldv, mode, nrows, j, al, be, lds, c,
+        hipLaunchKernelGGL((k_s_fused<16, TV>), dim3(nch), dim3(256), 0, s, w, V, ldv, mode, nrows, j, al, be, lds, c,
                            cf, ch, nch, seg_c0, partial, st);
     else
-        hipLaunchKernelGGL(k_s_fused<32>, dim3(nch), dim3(256), 0, s, w, V, ldv, mode, nrows, j, al, be, lds, c,
+        hipLaunchKernelGGL((k_s_fused<32, TV>), dim3(nch), dim3(256), 0, s, w, V, ldv, mode, nrows, j, al, be, lds, c,
                            cf, ch, nch, seg_c0, partial, st);
     const int nd = mode == 0 ? j + 2 : mode == 2 ? 1 : nr;
     hipLaunchKernelGGL(k_sdot_final, dim3(nseg * nd), dim3(256), 0, s, partial, nch, seg_c0, nd, out, ldo, 0,
@@ -433,9 +451,10 @@ bool seg_fused(int mode, double* w, const double* V, int64_t ldv, int nrows, int
 void seg_init(LState* st, int nseg, int m, const double* nrm, int ldn, hipStream_t s) {
     hipLaunchKernelGGL(k_s_init, dim3((nseg + 63) / 64), dim3(64), 0, s, st, nseg, m, nrm, ldn);
 }
-void seg_start(double* dst, const double* src, const double* nrm, int ldn, const SegChunk* ch,
-               int nch, hipStream_t s) {
-    hipLaunchKernelGGL(k_s_start, dim3(nch), dim3(256), 0, s, dst, src, nrm, ldn, ch);
+template <typename TV>
+void seg_start(TV* dst, const double* src, const double* nrm, int ldn, const SegChunk* ch, int nch,
+               hipStream_t s) {
+    hipLaunchKernelGGL(k_s_start<TV>, dim3(nch), dim3(256), 0, s, dst, src, nrm, ldn, ch);
 }
 void seg_three_term(double* w, const double* V, int64_t ldv, int j, const double* al,
                     const double* be, int lds, const SegChunk* ch, int nch, const LState* st,
@@ -451,18 +470,20 @@ void seg_beta(const double* ww, int ldw, double* al, double* be, int lds, int j,
     hipLaunchKernelGGL(k_s_beta, dim3((nseg + 63) / 64), dim3(64), 0, s, ww, ldw, al, be, lds, j, st,
                        nseg, tol);
 }
-void seg_next(double* V, int64_t ldv, int j, const double* w, const double* be, int lds,
-              const SegChunk* ch, int nch, const LState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_s_next, dim3(nch), dim3(256), 0, s, V, ldv, j, w, be, lds, ch, st);
+template <typename TV>
+void seg_next(TV* V, int64_t ldv, int j, const double* w, const double* be, int lds, const SegChunk* ch,
+              int nch, const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_s_next<TV>, dim3(nch), dim3(256), 0, s, V, ldv, j, w, be, lds, ch, st);
 }
 void seg_tridiag(const double* al, const double* be, int lds, double* sv, LState* st, double* work,
                  int nseg, hipStream_t s) {
     hipLaunchKernelGGL(k_s_tridiag, dim3((nseg + 63) / 64), dim3(64), 0, s, al, be, lds, sv, st, work,
                        nseg);
 }
-void seg_ritz(double* u, const double* V, int64_t ldv, const double* sv, int lds,
-              const SegChunk* ch, int nch, const LState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_s_ritz, dim3(nch), dim3(256), 0, s, u, V, ldv, sv, lds, ch, st);
+template <typename TV>
+void seg_ritz(double* u, const TV* V, int64_t ldv, const double* sv, int lds, const SegChunk* ch, int nch,
+              const LState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_s_ritz<TV>, dim3(nch), dim3(256), 0, s, u, V, ldv, sv, lds, ch, st);
 }
 void seg_normalise_sign(double* u, const SegChunk* ch, int nch, const int* seg_c0, int nseg,
                         const double* nrm, int ldn, double* pv, int64_t* pi, double* fac,
@@ -472,5 +493,20 @@ void seg_normalise_sign(double* u, const SegChunk* ch, int nch, const int* seg_c
                        fac, nseg);
     hipLaunchKernelGGL(k_s_scale, dim3(nch), dim3(256), 0, s, u, fac, ch);
 }
+
+#define QED_SEG_TV(TV)                                                                                          \
+    template void seg_dots<TV>(const TV*, int64_t, int, const double*, const SegChunk*, int, const int*, int,     \
+                               double*, double*, int, int, const LState*, int, hipStream_t);                      \
+    template bool seg_fused<TV>(int, double*, const TV*, int64_t, int, int, const double*, const double*, int,    \
+                                const double*, const double*, const SegChunk*, int, const int*, int, double*,     \
+                                double*, int, const LState*, hipStream_t);                                        \
+    template void seg_start<TV>(TV*, const double*, const double*, int, const SegChunk*, int, hipStream_t);      \
+    template void seg_next<TV>(TV*, int64_t, int, const double*, const double*, int, const SegChunk*, int,        \
+                               const LState*, hipStream_t);                                                       \
+    template void seg_ritz<TV>(double*, const TV*, int64_t, const double*, int, const SegChunk*, int,             \
+                               const LState*, hipStream_t);
+QED_SEG_TV(double)
+QED_SEG_TV(float)
+#undef QED_SEG_TV
 
 }  // namespace qed

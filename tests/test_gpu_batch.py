@@ -115,6 +115,43 @@ def test_batch_restarts_until_converged(ctx):
     ctx.set_lanczos(30, 1, 0.0)
 
 
+@pytest.mark.parametrize("basis", ["fp32", "fp64"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_lanczos_fp32_gemm(ctx, monkeypatch, basis, graph):
+    """FP32 GEMMs with the FP32 Krylov basis (the default at these step
+    counts) and with the FP64 one: one cycle against the oracle's cycle from
+    the same start within the FP32 operator's accuracy, then restarts to
+    the exact lowest eigenvalue of each node's dense matrix."""
+    if basis == "fp64":
+        monkeypatch.setenv("QEDTTN_LZ_BASIS", "fp64")
+    else:
+        monkeypatch.delenv("QEDTTN_LZ_BASIS", raising=False)
+    ctx.set_precision(lib.FP32)
+    ctx.set_lanczos(10, 1, 0.0)
+    spec, dterms, keep = upload(SMALL)
+    b = ctx.heff_batch(spec)
+    x0 = synth.normal(21, 5, b.size)
+    xd = dev(x0)
+    ev, res, rc = b.lanczos(xd.data_ptr(), 10, graph=graph)
+    u = xd.cpu().numpy()
+    for i, (legs, _) in enumerate(SMALL):
+        s0, s1 = b.offsets[i], b.offsets[i + 1]
+        th, uo, _, _, _ = olanczos.lanczos_cycle(
+            lambda v: oheff.apply_flat(v, tuple(legs), dterms[i]), x0[s0:s1], 10)
+        assert abs(ev[i] - th) <= 1e-5 * abs(th), (i, ev[i], th)
+        assert abs(np.linalg.norm(u[s0:s1]) - 1.0) < 1e-12
+        assert 1.0 - abs(u[s0:s1] @ uo) < 1e-6, i
+    ctx.set_lanczos(24, 12, 1e-6)
+    xd = dev(synth.normal(21, 6, b.size))
+    ev, res, rc = b.lanczos(xd.data_ptr(), 24, graph=graph)
+    for i, (legs, _) in enumerate(SMALL):
+        lam = np.linalg.eigvalsh(oheff.matrix(tuple(legs), dterms[i]))[0]
+        assert abs(ev[i] - lam) <= 1e-5 * abs(lam), (i, ev[i], lam)
+    b.close()
+    ctx.set_lanczos(30, 1, 0.0)
+    ctx.set_precision(lib.FP64)
+
+
 def test_autotuner_keeps_results(ctx, tmp_path):
     ctx.set_precision(lib.FP32)
     cache = str(tmp_path / "tiles.txt")
