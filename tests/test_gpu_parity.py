@@ -97,9 +97,13 @@ def test_c1_matvec(ctx, dtype, tol):
     ctx.set_precision(lib.FP64)
 
 
-def test_matvec_shifted_and_partial_terms(ctx):
+@pytest.mark.parametrize("order", ["prl", "lrp"])
+def test_matvec_shifted_and_partial_terms(ctx, order, monkeypatch):
     """Charge-shifting factors (delta_A + delta_B = delta_C), identity
-    factors in every position, uneven sectors with a ragged tail."""
+    factors in every position, uneven sectors with a ragged tail; with the
+    bond-leg factor applied first (default) and last (the terms summed on
+    the bond leg).  The flop count is the algorithmic one either way."""
+    monkeypatch.setenv("QEDTTN_HEFF_ORDER", order)
     ctx.set_precision(lib.FP64)
     L = [(-2, 3), (-1, 17), (0, 33), (1, 20), (2, 5)]
     R = [(-1, 9), (0, 40), (1, 7)]
@@ -517,7 +521,8 @@ def bottom_node(ctx):
 
 
 @pytest.mark.parametrize("plan,pipeline", [("fused", None), ("staged", None), ("staged", "flat"),
-                                           ("staged", "loop"), ("staged", "dma"), ("staged", "skinny")])
+                                           ("staged", "loop"), ("staged", "dma"), ("staged", "skinny"),
+                                           ("staged_lrp", None)])
 @pytest.mark.parametrize("dtype", [lib.FP64, lib.FP32])
 def test_bench_bottom_node_matvec(ctx, bottom_node, dtype, plan, pipeline, monkeypatch):
     """H_eff application at the benchmark's bottom-node shape, element by
@@ -525,7 +530,8 @@ def test_bench_bottom_node_matvec(ctx, bottom_node, dtype, plan, pipeline, monke
     bond-leg factor applied per output tile), and with three mode-product
     stages, their GEMM pipeline chosen per stage or forced to one pipeline
     on every stage that allows it (register-staged loop, flat, LDS-DMA ring
-    for FP32, skinny strips for the parent-leg stage).  FP64: 1e-13 of
+    for FP32, skinny strips for the parent-leg stage), and with the legs in
+    the opposite order (terms summed on the bond leg).  FP64: 1e-13 of
     max|y|.
     FP32: 2e-6 of max|y|, and every element within the first-order
     worst-case bound (4 input roundings, 2 stored intermediates, the three
@@ -536,6 +542,7 @@ def test_bench_bottom_node_matvec(ctx, bottom_node, dtype, plan, pipeline, monke
     else:
         monkeypatch.setenv("QEDTTN_GEMM_PIPELINE", pipeline)
     monkeypatch.setenv("QEDTTN_HEFF_FUSED", "1" if plan == "fused" else "0")
+    monkeypatch.setenv("QEDTTN_HEFF_ORDER", "lrp" if plan == "staged_lrp" else "prl")
     ctx.set_precision(dtype)
     B = bottom_node
     legs = B["legs"]
