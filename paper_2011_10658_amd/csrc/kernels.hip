@@ -2314,13 +2314,16 @@ __global__ __launch_bounds__(256) void k_chol_inv(const CholMat* __restrict__ ma
 // the whole chunk resident in LDS (qr_lds_fits); the same contract as
 // k_householder_qr (explicit Q written over the input, R through (rout,
 // rrs, rcs), diag(R) >= 0, tau = 0 and R_jj = 0 for a zero column).
-// Lane l of every wave owns column k = i + 1 + l (and k + 64) of the
-// trailing matrix, and the rows below the diagonal are split into four
-// ranges, one per wave: the products v^T a_k are per-lane sums over the
-// wave's rows (eight rows' loads issued together), combined across the
-// waves through LDS in a fixed order (one barrier), so no cross-lane
-// reduction is on the path.  The norm of the next column is gathered while
-// its update is written.  Q is then formed in place from the reflectors,
+// The rows below the diagonal are split into four ranges, one per wave.
+// With more than 64 trailing columns lane l of every wave owns column
+// k = i + 1 + l and k + 64; with at most 64 the wave's lanes are spread
+// over the trailing columns and slices of its rows (qrl_lanes), so that the
+// per-lane loops shrink with the trailing matrix instead of idling lanes
+// (the loops are bound by the LDS instructions a wave issues).  The
+// products v^T a_k are per-lane sums over a lane's rows (eight rows' loads
+// issued together), summed over the slices by lane exchanges and across
+// the waves through LDS in a fixed order (one barrier).  The norm of the
+// next column is gathered while its update is written.  Q is then formed in place from the reflectors,
 // last to first (column i becomes H_i e_i once the columns right of it
 // hold H_i+1 ... [I; 0]), with the same column-per-lane products.  The
 // leading dimension in LDS is odd, so the lanes of a wave read different
@@ -2329,6 +2332,31 @@ __device__ __forceinline__ void qrl_rows(int r0, int m, int wave, int& rb, int& 
     const int nr = m - r0;
     rb = r0 + (nr * wave) / 4;
     re = r0 + (nr * (wave + 1)) / 4;
+}
+
+// Lanes of a column step with nc <= 64 trailing columns: lane = s * ncp + c
+// with ncp the power of two at or above nc, so each of the 64 / ncp slices
+// s of the wave takes column c on its share [sb, se) of the wave's rows
+// [rb, re) (every lane busy however few columns are left); the slices'
+// sums meet by exchanges across the lane bits at and above ncp.
+struct QRLanes {
+    int ncp, c, s, sb, se;
+    bool act;
+};
+__device__ __forceinline__ QRLanes qrl_lanes(int nc, int lane, int rb, int re) {
+    QRLanes L;
+    L.ncp = nc <= 1 ? 1 : 1 << (32 - __clz(nc - 1));
+    const int f = 64 / L.ncp;
+    L.c = lane & (L.ncp - 1);
+    L.s = lane / L.ncp;
+    L.act = L.c < nc;
+    L.sb = rb + ((re - rb) * L.s) / f;
+    L.se = rb + ((re - rb) * (L.s + 1)) / f;
+    return L;
+}
+__device__ __forceinline__ double qrl_slices_sum(double v, int ncp) {
+    for (int o = ncp; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // sum over rows [rb, re) of v[r] c[r]
@@ -2416,44 +2444,70 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QRMat* __restrict__ mats) 
         }
         int rb, re;
         qrl_rows(i + 1, m, wave, rb, re);
-        const int k0 = i + 1 + lane, k1 = k0 + 64;
-        const bool a0 = k0 < n, a1 = k1 < n;
-        double* c0 = As + (int64_t)(a0 ? k0 : i) * ld;
-        double* c1 = As + (int64_t)(a1 ? k1 : i) * ld;
-        if (ti != 0.0) {
-            double p0 = 0.0, p1 = 0.0;
-            if (wave == 0) {
-                p0 = v0 * c0[i];
-                p1 = v0 * c1[i];
-            }
-            p0 += qrl_dot(ci, c0, rb, re);
-            if (i + 65 < n) p1 += qrl_dot(ci, c1, rb, re);
-            part[wave * 128 + lane] = p0;
-            part[wave * 128 + 64 + lane] = p1;
-        }
         if (tid == 0) {
             tau[i] = ti;
             vd[i] = v0;
             dg[i] = al;
         }
-        __syncthreads();
-        // updates, and the next column's squares below its diagonal
         double nx = 0.0;
-        if (ti != 0.0) {
-            const double w0 = ti * (((part[lane] + part[128 + lane]) + part[256 + lane]) + part[384 + lane]);
-            const double w1 =
-                ti * (((part[64 + lane] + part[192 + lane]) + part[320 + lane]) + part[448 + lane]);
-            if (a0) {
+        if (n - i - 1 > 64) {
+            const int k0 = i + 1 + lane, k1 = k0 + 64;
+            const bool a0 = k0 < n, a1 = k1 < n;
+            double* c0 = As + (int64_t)(a0 ? k0 : i) * ld;
+            double* c1 = As + (int64_t)(a1 ? k1 : i) * ld;
+            if (ti != 0.0) {
+                double p0 = 0.0, p1 = 0.0;
+                if (wave == 0) {
+                    p0 = v0 * c0[i];
+                    p1 = v0 * c1[i];
+                }
+                p0 += qrl_dot(ci, c0, rb, re);
+                p1 += qrl_dot(ci, c1, rb, re);
+                part[wave * 128 + lane] = p0;
+                part[wave * 128 + 64 + lane] = p1;
+            }
+            __syncthreads();
+            // updates, and the next column's squares below its diagonal
+            if (ti != 0.0) {
+                const double w0 =
+                    ti * (((part[lane] + part[128 + lane]) + part[256 + lane]) + part[384 + lane]);
+                const double w1 =
+                    ti * (((part[64 + lane] + part[192 + lane]) + part[320 + lane]) + part[448 + lane]);
                 nx = qrl_axpy(c0, ci, w0, rb, re, i + 1);
                 if (wave == 0) c0[i] -= w0 * v0;
+                if (a1) {
+                    (void)qrl_axpy(c1, ci, w1, rb, re, m);
+                    if (wave == 0) c1[i] -= w1 * v0;
+                }
+            } else {
+                for (int r = rb; r < re; ++r)
+                    if (r > i + 1) nx += c0[r] * c0[r];
             }
-            if (a1) {
-                (void)qrl_axpy(c1, ci, w1, rb, re, m);
-                if (wave == 0) c1[i] -= w1 * v0;
+        } else {
+            const QRLanes L = qrl_lanes(n - i - 1, lane, rb, re);
+            double* ck = As + (int64_t)(L.act ? i + 1 + L.c : i) * ld;
+            if (ti != 0.0) {
+                double p = 0.0;
+                if (L.act) {
+                    if (wave == 0 && L.s == 0) p = v0 * ck[i];
+                    p += qrl_dot(ci, ck, L.sb, L.se);
+                }
+                p = qrl_slices_sum(p, L.ncp);
+                if (L.s == 0) part[wave * 128 + L.c] = p;
             }
-        } else if (a0) {
-            for (int r = rb; r < re; ++r)
-                if (r > i + 1) nx += c0[r] * c0[r];
+            __syncthreads();
+            if (ti != 0.0) {
+                const double w =
+                    ti * (((part[L.c] + part[128 + L.c]) + part[256 + L.c]) + part[384 + L.c]);
+                if (L.act) {
+                    nx = qrl_axpy(ck, ci, w, L.sb, L.se, i + 1);
+                    if (wave == 0 && L.s == 0) ck[i] -= w * v0;
+                }
+            } else if (L.act) {
+                for (int r = L.sb; r < L.se; ++r)
+                    if (r > i + 1) nx += ck[r] * ck[r];
+            }
+            nx = qrl_slices_sum(nx, L.ncp);
         }
         if (lane == 0) red[wave] = nx;   // lane 0 holds column i + 1
         __syncthreads();
@@ -2471,32 +2525,50 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QRMat* __restrict__ mats) 
         const double ti = tau[i], v0 = vd[i];
         int rb, re;
         qrl_rows(i + 1, m, wave, rb, re);
-        const int k0 = i + 1 + lane, k1 = k0 + 64;
-        const bool a0 = k0 < n, a1 = k1 < n;
-        double* c0 = As + (int64_t)(a0 ? k0 : i) * ld;
-        double* c1 = As + (int64_t)(a1 ? k1 : i) * ld;
-        if (ti != 0.0) {
-            const double p0 = qrl_dot(ci, c0, rb, re);
-            const double p1 = i + 65 < n ? qrl_dot(ci, c1, rb, re) : 0.0;
-            part[wave * 128 + lane] = p0;
-            part[wave * 128 + 64 + lane] = p1;
-        }
-        __syncthreads();
-        if (ti != 0.0) {
-            const double w0 = ti * (((part[lane] + part[128 + lane]) + part[256 + lane]) + part[384 + lane]);
-            const double w1 =
-                ti * (((part[64 + lane] + part[192 + lane]) + part[320 + lane]) + part[448 + lane]);
-            if (a0) {
+        if (n - i - 1 > 64) {
+            const int k0 = i + 1 + lane, k1 = k0 + 64;
+            const bool a1 = k1 < n;
+            double* c0 = As + (int64_t)k0 * ld;
+            double* c1 = As + (int64_t)(a1 ? k1 : i) * ld;
+            if (ti != 0.0) {
+                part[wave * 128 + lane] = qrl_dot(ci, c0, rb, re);
+                part[wave * 128 + 64 + lane] = qrl_dot(ci, c1, rb, re);
+            }
+            __syncthreads();
+            if (ti != 0.0) {
+                const double w0 =
+                    ti * (((part[lane] + part[128 + lane]) + part[256 + lane]) + part[384 + lane]);
+                const double w1 =
+                    ti * (((part[64 + lane] + part[192 + lane]) + part[320 + lane]) + part[448 + lane]);
                 (void)qrl_axpy(c0, ci, w0, rb, re, m);
                 if (wave == 0) c0[i] = -w0 * v0;
+                if (a1) {
+                    (void)qrl_axpy(c1, ci, w1, rb, re, m);
+                    if (wave == 0) c1[i] = -w1 * v0;
+                }
+            } else if (wave == 0) {
+                c0[i] = 0.0;
+                if (a1) c1[i] = 0.0;
             }
-            if (a1) {
-                (void)qrl_axpy(c1, ci, w1, rb, re, m);
-                if (wave == 0) c1[i] = -w1 * v0;
+        } else {
+            const QRLanes L = qrl_lanes(n - i - 1, lane, rb, re);
+            double* ck = As + (int64_t)(L.act ? i + 1 + L.c : i) * ld;
+            if (ti != 0.0) {
+                double p = L.act ? qrl_dot(ci, ck, L.sb, L.se) : 0.0;
+                p = qrl_slices_sum(p, L.ncp);
+                if (L.s == 0) part[wave * 128 + L.c] = p;
             }
-        } else if (wave == 0) {
-            if (a0) c0[i] = 0.0;
-            if (a1) c1[i] = 0.0;
+            __syncthreads();
+            if (ti != 0.0) {
+                const double w =
+                    ti * (((part[L.c] + part[128 + L.c]) + part[256 + L.c]) + part[384 + L.c]);
+                if (L.act) {
+                    (void)qrl_axpy(ck, ci, w, L.sb, L.se, m);
+                    if (wave == 0 && L.s == 0) ck[i] = -w * v0;
+                }
+            } else if (wave == 0 && L.s == 0 && L.act) {
+                ck[i] = 0.0;
+            }
         }
         __syncthreads();
         // column i: H_i e_i (every row of it is read above, by every wave)
