@@ -516,6 +516,29 @@ static bool dma_operands_ok(int esize, const std::vector<GJob>& jobs, const std:
     return any;
 }
 
+// The flat pipeline reads operands and writes its output through buffer
+// resources with 32-bit byte offsets from each block's start: every element
+// a tile reads or writes must lie within 2^31 bytes of it.
+static bool flat_operands_ok(int esize, const std::vector<GJob>& jobs, const std::vector<GProd>& prods) {
+    const int64_t LIM = ((int64_t)1 << 31) / esize - 2;
+    for (const GJob& J : jobs) {
+        // the output block (its tiles are stored the same way)
+        const int64_t M = std::max(J.M, 1), N = std::max(J.N, 1);
+        const int64_t omax = (M - 1) * J.ldc + (J.nsc ? (N / J.nsc + 1) * J.noc + J.nsc : N - 1);
+        if (omax >= LIM) return false;
+        for (int p = J.p0; p < J.p1; ++p) {
+            const GProd& P = prods[p];
+            if (P.ident) continue;
+            const int64_t M = std::max(J.M, 1), N = std::max(J.N, 1), K = std::max(P.K, 1);
+            const int64_t amax = P.tA ? (K - 1) * P.lda + (M - 1) : (M - 1) * P.lda + (K - 1);
+            const int64_t cmax = P.nsb ? (N / P.nsb + 1) * P.nob + P.nsb : N - 1;
+            const int64_t bmax = P.tB ? (N - 1) * P.ldb + (K - 1) : (K - 1) * P.ldb + cmax;
+            if (amax >= LIM || bmax >= LIM) return false;
+        }
+    }
+    return true;
+}
+
 // The skinny kernel takes stages whose every product is A B^T on a
 // contiguous panel (lda = K, ldb = K, K <= SK_KMAX, one reduction term)
 // into contiguous overwritten outputs of at most SK_NMAX columns (FP32 and
@@ -538,7 +561,8 @@ static bool skinny_operands_ok(int dtype, const std::vector<GJob>& jobs, const s
 
 bool Plan::pipe_valid(size_t s, int pp, int sh) const {
     if (pp == GEMM_PIPE_SKINNY) return skinny_ok[s] != 0;
-    if (pp != GEMM_PIPE_DMA) return pp == GEMM_PIPE_LOOP || pp == GEMM_PIPE_FLAT;
+    if (pp == GEMM_PIPE_FLAT) return flat_ok[s] != 0;
+    if (pp != GEMM_PIPE_DMA) return pp == GEMM_PIPE_LOOP;
     return (dtype == QED_FP32 || dtype == QED_FP64) && dma_ok[s] && brgemm_dma_shape(sh);
 }
 
@@ -564,6 +588,7 @@ void Plan::upload(Dev* dev) {
     sumk.clear();
     pipe.clear();
     dma_ok.clear();
+    flat_ok.clear();
     skinny_ok.clear();
     std::vector<std::vector<GTile>> stiles;
     for (size_t s = 0; s < jobs.size(); ++s) {
@@ -580,6 +605,7 @@ void Plan::upload(Dev* dev) {
                                  dma_operands_ok(dtype_size(dtype), jobs[s], prods[s])
                              ? 1
                              : 0);
+        flat_ok.push_back(flat_operands_ok(dtype_size(dtype), jobs[s], prods[s]) ? 1 : 0);
         skinny_ok.push_back(!only_ident && skinny_operands_ok(dtype, jobs[s], prods[s]) ? 1 : 0);
         stiles.push_back(skinny_ok.back() ? make_skinny_tiles(jobs[s], prods[s], skinny_rows(dtype))
                                           : std::vector<GTile>());
@@ -745,7 +771,7 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
         launch_sum_stage(dtype, J, Pp, T, ntiles[s], b, st);
         return;
     }
-    const bool fl = pipe[s] == GEMM_PIPE_FLAT;
+    const bool fl = pipe[s] == GEMM_PIPE_FLAT && flat_ok[s];
     if (pipe[s] == GEMM_PIPE_SKINNY && skinny_ok[s]) {
         if (dtype == QED_FP64) launch_skinny<double>(J, Pp, dts[s], nts[s], b, st);
         else launch_skinny<float>(J, Pp, dts[s], nts[s], b, st);

@@ -279,6 +279,7 @@ struct Plan {
     // operands it can read (dma_ok), the register-staged loop otherwise
     std::vector<char> pipe;
     std::vector<char> dma_ok;
+    std::vector<char> flat_ok;                   // operands within the flat pipeline's 2^31-byte offsets
     std::vector<char> skinny_ok;                 // stage the skinny kernel can run
     std::vector<const GTile*> dts;               // its strip tiles
     std::vector<int> nts;

@@ -57,6 +57,40 @@ __device__ __forceinline__ gmem<T>* resolve(const GRef& r, const Bases& bs) {
     return (gmem<T>*)bs.b[r.tag] + r.off;
 }
 
+// word 3 of a raw (untyped, stride 0) buffer resource on gfx9-family
+// parts, and a byte offset beyond every resource's range
+constexpr int DMA_RSRC_W3 = 0x00020000;
+constexpr uint32_t DMA_OOB = 0x80000000u;
+
+// one element through a raw buffer resource; an offset past the resource's
+// range reads as zero
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+}
+// one element stored through a raw buffer resource; a store past the
+// resource's range is dropped
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ void buf_store<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store<double>(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 w = {(unsigned)__double2loint(v), (unsigned)__double2hiint(v)};
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+}
+
 // ---------------------------------------------------------------------
 // grouped batch-reduce GEMM
 // ---------------------------------------------------------------------
@@ -245,10 +279,15 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         // The other products run as one flat sequence of (product, reduction,
         // chunk) steps: the next step's operands are fetched while the current
         // chunk is multiplied, also across product boundaries.
+        // Operands are read through raw buffer resources over the product's
+        // blocks, an element outside the tile's range at the out-of-range
+        // offset (read as zero): every load is issued unconditionally, with
+        // no branch around it (the host routes here only products whose
+        // operands span less than 2^31 bytes).
         struct Step {
-            gmem<const T>* A;   // element 0 of this thread at k0 = 0
-            gmem<const T>* B;
-            int64_t akm, aes, bkm, bes;
+            __amdgpu_buffer_rsrc_t ra, rb;
+            uint32_t ao, bo;            // byte offset of this thread's element 0 at k0 = 0
+            uint32_t akb, aeb, bkb, beb;   // bytes per k and per element index e
             int am0, amE, ak0, akE, bn0, bnE, bk0, bkE;
             int K, nchunk, nred;
             T alpha;
@@ -261,16 +300,16 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
             D.amE = P.tA ? 0 : ASA;
             D.ak0 = P.tA ? t_tq : t_kc;
             D.akE = P.tA ? ASB : 0;
-            D.akm = P.tA ? (int64_t)P.lda : 1;
-            D.aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
+            const int64_t akm = P.tA ? (int64_t)P.lda : 1;
+            const int64_t aes = (int64_t)(P.tA ? ASB : ASA) * P.lda;
             const int64_t abase =
                 P.tA ? (int64_t)D.ak0 * P.lda + m0 + D.am0 : (int64_t)(m0 + D.am0) * P.lda + D.ak0;
             D.bn0 = P.tB ? t_kq : t_tn;
             D.bnE = P.tB ? BSB : 0;
             D.bk0 = P.tB ? t_kc : t_nq;
             D.bkE = P.tB ? 0 : BSN;
-            D.bkm = P.tB ? 1 : (int64_t)P.ldb;
-            D.bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
+            const int64_t bkm = P.tB ? 1 : (int64_t)P.ldb;
+            const int64_t bes = (int64_t)(P.tB ? BSB : BSN) * P.ldb;
             int64_t bbase;
             if (P.tB) {
                 bbase = (int64_t)(n0 + D.bn0) * P.ldb + D.bk0;
@@ -279,8 +318,16 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
                 const int64_t col = P.nsb ? (int64_t)(gn / P.nsb) * P.nob + gn % P.nsb : gn;
                 bbase = (int64_t)D.bk0 * P.ldb + col;
             }
-            D.A = Ab + (int64_t)r * P.rsA + abase;
-            D.B = Bb + (int64_t)r * P.rsB + bbase;
+            D.ra = __builtin_amdgcn_make_buffer_rsrc((void*)(Ab + (int64_t)r * P.rsA), (short)0, 0x7fffffff,
+                                                     DMA_RSRC_W3);
+            D.rb = __builtin_amdgcn_make_buffer_rsrc((void*)(Bb + (int64_t)r * P.rsB), (short)0, 0x7fffffff,
+                                                     DMA_RSRC_W3);
+            D.ao = (uint32_t)(abase * (int64_t)sizeof(T));
+            D.bo = (uint32_t)(bbase * (int64_t)sizeof(T));
+            D.akb = (uint32_t)(akm * (int64_t)sizeof(T));
+            D.aeb = (uint32_t)(aes * (int64_t)sizeof(T));
+            D.bkb = (uint32_t)(bkm * (int64_t)sizeof(T));
+            D.beb = (uint32_t)(bes * (int64_t)sizeof(T));
             D.K = P.K;
             D.nchunk = (P.K + KC - 1) / KC;
             D.nred = P.nred;
@@ -288,19 +335,17 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         };
         auto fetch = [&](const Step& D, int c) {
             const int k0 = c * KC;
-            gmem<const T>* pa = D.A + k0 * D.akm;
-            gmem<const T>* pb = D.B + k0 * D.bkm;
+            const uint32_t pa = D.ao + (uint32_t)k0 * D.akb;
+            const uint32_t pb = D.bo + (uint32_t)k0 * D.bkb;
     #pragma unroll
             for (int e = 0; e < AE; ++e) {
-                T v = (T)0;
-                if (m0 + D.am0 + e * D.amE < J.M && k0 + D.ak0 + e * D.akE < D.K) v = pa[e * D.aes];
-                ra[e] = v;
+                const bool ok = (m0 + D.am0 + e * D.amE < J.M) & (k0 + D.ak0 + e * D.akE < D.K);
+                ra[e] = buf_load<T>(D.ra, ok ? pa + (uint32_t)e * D.aeb : DMA_OOB);
             }
     #pragma unroll
             for (int e = 0; e < BE; ++e) {
-                T v = (T)0;
-                if (n0 + D.bn0 + e * D.bnE < J.N && k0 + D.bk0 + e * D.bkE < D.K) v = pb[e * D.bes];
-                rb[e] = v;
+                const bool ok = (n0 + D.bn0 + e * D.bnE < J.N) & (k0 + D.bk0 + e * D.bkE < D.K);
+                rb[e] = buf_load<T>(D.rb, ok ? pb + (uint32_t)e * D.beb : DMA_OOB);
             }
         };
         // alpha is applied here (see the loop pipeline)
@@ -360,6 +405,32 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         }
     }
     gmem<T>* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    if constexpr (FLAT) {
+        // the output through a buffer resource as well: an element outside
+        // the job stores to the out-of-range offset, which drops the store
+        const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void*)C, (short)0, 0x7fffffff,
+                                                                            DMA_RSRC_W3);
+#pragma unroll
+        for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < BN; ++bj) {
+                const int col = n0 + wn0 + bj * 16 + lr;
+                // unsigned arithmetic: exact wherever the element is in range
+                const uint32_t co = J.nsc ? (uint32_t)(col / J.nsc) * (uint32_t)J.noc + (uint32_t)(col % J.nsc)
+                                          : (uint32_t)col;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = m0 + wm0 + bi * 16 + Mfma<T>::row(lane, i);
+                    const bool ok = (row < J.M) & (col < J.N);
+                    const uint32_t o =
+                        ok ? ((uint32_t)row * (uint32_t)J.ldc + co) * (uint32_t)sizeof(T) : DMA_OOB;
+                    T v = acc[bi][bj][i];
+                    if (J.acc) v += buf_load<T>(rc, o);
+                    buf_store<T>(v, rc, o);
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -456,11 +527,6 @@ void launch_sum_stage(int dtype, const GJob* jobs, const GProd* prods, const GTi
 //   A: element (m, k) at (m / 4) 66 + (m % 4) 16 + (k ^ (8 [m % 4 >= 2]));
 //      one load instruction fills 4 rows of 16 k;
 //   B: element (k, n) at k (TN + 16) + n; one instruction fills 64 n of a row.
-// word 3 of a raw (untyped, stride 0) buffer resource on gfx9-family
-// parts, and a byte offset beyond every resource's range
-constexpr int DMA_RSRC_W3 = 0x00020000;
-constexpr uint32_t DMA_OOB = 0x80000000u;
-
 template <int N> struct VmWait {
     // s_waitcnt with vmcnt(N) only (expcnt and lgkmcnt left unconstrained)
     static constexpr int imm = (N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8);
