@@ -502,7 +502,10 @@ static int forced_pipeline() {
 static bool dma_operands_ok(int esize, const std::vector<GJob>& jobs, const std::vector<GProd>& prods) {
     const int64_t LIM = ((int64_t)1 << 31) / esize;
     bool any = false;
-    for (const GJob& J : jobs)
+    for (const GJob& J : jobs) {
+        // the output block, stored through a buffer resource as well
+        const int64_t M = std::max(J.M, 1), N = std::max(J.N, 1);
+        if ((M - 1) * J.ldc + (J.nsc ? (N / J.nsc + 1) * J.noc + J.nsc : N - 1) >= LIM - 2) return false;
         for (int p = J.p0; p < J.p1; ++p) {
             const GProd& P = prods[p];
             if (P.ident) continue;
@@ -513,6 +516,7 @@ static bool dma_operands_ok(int esize, const std::vector<GJob>& jobs, const std:
             if ((int64_t)(J.M + 128) * P.lda + P.K + 16 >= LIM) return false;
             if ((int64_t)(P.K + 16) * P.ldb + co >= LIM) return false;
         }
+    }
     return any;
 }
 

@@ -689,20 +689,26 @@ __global__ __launch_bounds__(256, 4) void k_brgemm_dma(const GJob* __restrict__ 
             }
         }
     }
+    // the output through a buffer resource: an element outside the job
+    // stores to the out-of-range offset, which drops the store
     gmem<float>* C = resolve<float>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void*)C, (short)0, 0x7fffffff, DMA_RSRC_W3);
 #pragma unroll
     for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
         for (int bj = 0; bj < BN; ++bj) {
             const int col = n0 + wn0 + bj * 16 + lr;
-            const int64_t co = J.nsc ? (int64_t)(col / J.nsc) * J.noc + col % J.nsc : col;
+            // unsigned arithmetic: exact wherever the element is in range
+            const uint32_t co = J.nsc ? (uint32_t)(col / J.nsc) * (uint32_t)J.noc + (uint32_t)(col % J.nsc)
+                                      : (uint32_t)col;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm0 + bi * 16 + Mfma<float>::row(lane, i);
-                if (row < J.M && col < J.N) {
-                    gmem<float>* c = C + (int64_t)row * J.ldc + co;
-                    *c = J.acc ? *c + acc[bi][bj][i] : acc[bi][bj][i];
-                }
+                const bool ok = (row < J.M) & (col < J.N);
+                const uint32_t o = ok ? ((uint32_t)row * (uint32_t)J.ldc + co) * 4u : DMA_OOB;
+                float v = acc[bi][bj][i];
+                if (J.acc) v += buf_load<float>(rc, o);
+                buf_store<float>(v, rc, o);
             }
         }
 }
