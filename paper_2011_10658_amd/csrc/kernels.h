@@ -153,7 +153,7 @@ struct PackBlk {
 // dimension ld at `mat` (in the packed buffer and, for the scratch copy of
 // Q, in the scratch buffer); R(r, c) is written at rout + r*rrs + c*rcs.
 // Output elements per workgroup of an identity-only (summation) stage.
-constexpr int SUM_TILE = 256;
+constexpr int SUM_TILE = 1024;
 
 // Sizes one QR workgroup handles (the panel and the T factors live in LDS).
 constexpr int QR_ROWS = 2048;

@@ -463,6 +463,54 @@ __global__ __launch_bounds__(256) void k_sum_stage(const GJob* __restrict__ jobs
     const int64_t e0 = (int64_t)tl.tm * SUM_TILE;
     const int64_t e1 = e0 + SUM_TILE < total ? e0 + SUM_TILE : total;
     gmem<T>* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
+    // output and every input stored densely (no column split, leading
+    // dimension N): element e sits at offset e everywhere, and each thread
+    // sums SUM_TILE / 256 elements with all their loads issued together
+    // (an index past the tile reads the tile's last element and is not
+    // stored)
+    bool dense = J.nsc == 0 && J.ldc == J.N;
+    for (int p = J.p0; p < J.p1 && dense; ++p) dense = prods[p].nsb == 0 && prods[p].ldb == J.N;
+    if (dense) {
+        constexpr int U = SUM_TILE / 256;
+        int64_t ix[U];
+        T acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + threadIdx.x + 256 * u;
+            ix[u] = e < e1 ? e : e1 - 1;
+            acc[u] = (T)0;
+        }
+        int p = J.p0;
+        for (; p + 2 <= J.p1; p += 2) {
+            const GProd& P0 = prods[p];
+            const GProd& P1 = prods[p + 1];
+            gmem<const T>* B0 = resolve<T>(P0.B, bases) + (int64_t)tl.b * P0.bsB;
+            gmem<const T>* B1 = resolve<T>(P1.B, bases) + (int64_t)tl.b * P1.bsB;
+            T v0[U], v1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v0[u] = B0[ix[u]];
+                v1[u] = B1[ix[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                acc[u] += (T)P0.alpha * v0[u];
+                acc[u] += (T)P1.alpha * v1[u];
+            }
+        }
+        if (p < J.p1) {
+            const GProd& P0 = prods[p];
+            gmem<const T>* B0 = resolve<T>(P0.B, bases) + (int64_t)tl.b * P0.bsB;
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[u] += (T)P0.alpha * B0[ix[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + threadIdx.x + 256 * u;
+            if (e < e1) C[e] = J.acc ? C[e] + acc[u] : acc[u];
+        }
+        return;
+    }
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
         const int row = (int)(e / J.N), col = (int)(e % J.N);
         T acc = (T)0;
