@@ -378,12 +378,16 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
                     }
                 }
                 const bool more = np < J.p1;
+                // reduction indices of the current chunk (the steps past
+                // them would multiply zero padding only)
+                const int kv = D.K - c * KC;
                 if (more) {
                     if (np != p || nr != r) describe(np, nr, D);
                     fetch(D, nc);
                 }
     #pragma unroll
                 for (int kk = 0; kk < KC; kk += 4) {
+                    if (kk >= kv) break;
                     T a[BM], bb[BN];
     #pragma unroll
                     for (int i = 0; i < BM; ++i) a[i] = As[cur][kk + lk][wm0 + i * 16 + lr];
