@@ -2542,9 +2542,10 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QRMat* __restrict__ mats) 
     double* red = dg + n;                     // [4]
     double* part = red + 4;                   // [4][128]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
-        const int c = (int)(e / m), r = (int)(e % m);
-        As[(int64_t)c * ld + r] = Mt.a[(int64_t)c * ldg + r];
+    // (m n fits 32 bits here: 32-bit index arithmetic)
+    for (int e = tid; e < m * n; e += 256) {
+        const int c = e / m, r = e - c * m;
+        As[c * ld + r] = Mt.a[(int64_t)c * ldg + r];
     }
     __syncthreads();
     {
@@ -2705,9 +2706,9 @@ __global__ __launch_bounds__(256) void k_qr_lds(const QRMat* __restrict__ mats) 
         }
         __syncthreads();
     }
-    for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
-        const int c = (int)(e / m), r = (int)(e % m);
-        const double q = As[(int64_t)c * ld + r];
+    for (int e = tid; e < m * n; e += 256) {
+        const int c = e / m, r = e - c * m;
+        const double q = As[c * ld + r];
         Mt.a[(int64_t)c * ldg + r] = dg[c] < 0.0 ? -q : q;
     }
 }
