@@ -675,7 +675,7 @@ def main():
                          "written) to calibrate hardware byte counters")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the node update is measured on one device)", file=sys.stderr)
         sys.exit(2)
     import torch

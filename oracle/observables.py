@@ -27,7 +27,7 @@ with A the number of sites of a plane orthogonal to axis a.  The charge
 profile and the surface density use the Gauss-law charge q_x: the
 paper's printed forms multiply psi^dag psi by the staggered sign, which
 equals q_x in the convention where odd sites are hole-transformed; with
-this build's convention (vacuum: even sites empty, odd sites filled) q_x
+the convention used here (vacuum: even sites empty, odd sites filled) q_x
 is what vanishes in the vacuum and reaches +-1 on charged plates.
 
 Static potential (Results, "Confinement properties"): opposite static
