@@ -52,8 +52,12 @@ def upload(nodes):
 SMALL = synth.batched_nodes(21, 9, chis=(8, 12, 16, 20), kmin=3, kmax=6, allowed=has_blocks)
 
 
+@pytest.mark.parametrize("order", ["prl", "lrp"])
 @pytest.mark.parametrize("dtype,tol", [(lib.FP64, 1e-13), (lib.FP32, 3e-6)])
-def test_batch_matvec_each_node(ctx, dtype, tol):
+def test_batch_matvec_each_node(ctx, dtype, tol, order, monkeypatch):
+    """Every node of a batched plan against the oracle, with the bond-leg
+    factor applied first (default) and last (QEDTTN_HEFF_ORDER=lrp)."""
+    monkeypatch.setenv("QEDTTN_HEFF_ORDER", order)
     ctx.set_precision(dtype)
     spec, dterms, keep = upload(SMALL)
     b = ctx.heff_batch(spec)
