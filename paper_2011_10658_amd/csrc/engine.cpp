@@ -785,11 +785,11 @@ void Plan::launch_stage(size_t s, const Bases& b, hipStream_t st) const {
         if (pipe[s] == GEMM_PIPE_DMA && pipe_valid(s, GEMM_PIPE_DMA, shape[s]))
             launch_brgemm_dma64(J, Pp, T, ntiles[s], b, shape[s], st);
         else
-            launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
+            launch_brgemm<double>(J, Pp, T, ntiles[s], b, shape[s], fl, flat_ok[s] != 0, st);
     } else if (dtype == QED_BF16) launch_brgemm_bf16(J, Pp, T, ntiles[s], b, shape[s], st);
     else if (pipe[s] == GEMM_PIPE_DMA && pipe_valid(s, GEMM_PIPE_DMA, shape[s]))
         launch_brgemm_dma(J, Pp, T, ntiles[s], b, shape[s], st);
-    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], fl, st);
+    else launch_brgemm<float>(J, Pp, T, ntiles[s], b, shape[s], fl, flat_ok[s] != 0, st);
 }
 
 void Prof::record_begin(hipStream_t s, hipEvent_t& a) {

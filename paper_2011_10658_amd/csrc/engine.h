@@ -21,10 +21,12 @@ namespace qed {
 
 // ---- kernel launchers (kernels.hip) ----------------------------------
 // flat: products of a job as one pipelined sequence of K chunks (pays off
-// for short reductions); otherwise one pipeline per product
+// for short reductions); otherwise one pipeline per product.  buf: operands
+// and output through buffer resources (every block of the stage within
+// 2^31-byte offsets; the flat pipeline always needs it)
 template <typename T>
 void launch_brgemm(const GJob*, const GProd*, const GTile*, int, const Bases&, int shape, bool flat,
-                   hipStream_t);
+                   bool buf, hipStream_t);
 // fused H_eff stage: per output tile, every term's child-leg product and
 // bond-leg epilogue (heff_fused.hip)
 // (cs_rows x cs_cols: the largest bond-factor block of the launch, input

@@ -121,7 +121,10 @@ template <> struct GemmK<double> { static constexpr int KC = 16; };
 // Occupancy hint of five waves per SIMD: the FP32 instances fit in 96 VGPRs
 // without spills (four waves otherwise); measured faster on the sweep, the
 // batched matvec and the adjoint.
-template <typename T, int WM, int WN, int BM, int BN, bool FLAT>
+// FLAT selects the flat pipeline (operands and output through buffer
+// resources, below); BUF gives the register-staged loop the same buffer
+// access (the host sets it where every block fits 2^31-byte offsets).
+template <typename T, int WM, int WN, int BM, int BN, bool FLAT, bool BUF>
 __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs,
                                                 const GProd* __restrict__ prods,
                                                 const GTile* __restrict__ tiles, Bases bases) {
@@ -204,21 +207,42 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
             for (int r = 0; r < P.nred; ++r) {
                 gmem<const T>* A = Ab + (int64_t)r * P.rsA + abase;
                 gmem<const T>* B = Bb + (int64_t)r * P.rsB + bbase;
+                const __amdgpu_buffer_rsrc_t rsa =
+                    __builtin_amdgcn_make_buffer_rsrc((void*)(Ab + (int64_t)r * P.rsA), (short)0, 0x7fffffff, DMA_RSRC_W3);
+                const __amdgpu_buffer_rsrc_t rsb =
+                    __builtin_amdgcn_make_buffer_rsrc((void*)(Bb + (int64_t)r * P.rsB), (short)0, 0x7fffffff, DMA_RSRC_W3);
                 auto fetch = [&](int c) {
                     const int k0 = c * KC;
-                    gmem<const T>* pa = A + k0 * akm;
-                    gmem<const T>* pb = B + k0 * bkm;
+                    if constexpr (BUF) {
+                        const uint32_t pa = (uint32_t)((abase + k0 * akm) * (int64_t)sizeof(T));
+                        const uint32_t pb = (uint32_t)((bbase + k0 * bkm) * (int64_t)sizeof(T));
+                        const uint32_t aeb = (uint32_t)(aes * (int64_t)sizeof(T));
+                        const uint32_t beb = (uint32_t)(bes * (int64_t)sizeof(T));
     #pragma unroll
-                    for (int e = 0; e < AE; ++e) {
-                        T v = (T)0;
-                        if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
-                        ra[e] = v;
-                    }
+                        for (int e = 0; e < AE; ++e) {
+                            const bool ok = (m0 + am0 + e * amE < J.M) & (k0 + ak0 + e * akE < P.K);
+                            ra[e] = buf_load<T>(rsa, ok ? pa + (uint32_t)e * aeb : DMA_OOB);
+                        }
     #pragma unroll
-                    for (int e = 0; e < BE; ++e) {
-                        T v = (T)0;
-                        if (n0 + bn0 + e * bnE < J.N && k0 + bk0 + e * bkE < P.K) v = pb[e * bes];
-                        rb[e] = v;
+                        for (int e = 0; e < BE; ++e) {
+                            const bool ok = (n0 + bn0 + e * bnE < J.N) & (k0 + bk0 + e * bkE < P.K);
+                            rb[e] = buf_load<T>(rsb, ok ? pb + (uint32_t)e * beb : DMA_OOB);
+                        }
+                    } else {
+                        gmem<const T>* pa = A + k0 * akm;
+                        gmem<const T>* pb = B + k0 * bkm;
+    #pragma unroll
+                        for (int e = 0; e < AE; ++e) {
+                            T v = (T)0;
+                            if (m0 + am0 + e * amE < J.M && k0 + ak0 + e * akE < P.K) v = pa[e * aes];
+                            ra[e] = v;
+                        }
+    #pragma unroll
+                        for (int e = 0; e < BE; ++e) {
+                            T v = (T)0;
+                            if (n0 + bn0 + e * bnE < J.N && k0 + bk0 + e * bkE < P.K) v = pb[e * bes];
+                            rb[e] = v;
+                        }
                     }
                 };
                 // alpha is applied here, not at the load: a use right after
@@ -409,7 +433,7 @@ __global__ __launch_bounds__(256, 5) void k_brgemm(const GJob* __restrict__ jobs
         }
     }
     gmem<T>* C = resolve<T>(J.C, bases) + (int64_t)tl.b * J.bsC;
-    if constexpr (FLAT) {
+    if constexpr (FLAT || BUF) {
         // the output through a buffer resource as well: an element outside
         // the job stores to the out-of-range offset, which drops the store
         const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void*)C, (short)0, 0x7fffffff,
@@ -1155,27 +1179,29 @@ void launch_brgemm_dma(const GJob* jobs, const GProd* prods, const GTile* tiles,
 
 template <typename T>
 void launch_brgemm(const GJob* jobs, const GProd* prods, const GTile* tiles, int ntiles,
-                   const Bases& bases, int shape, bool flat, hipStream_t st) {
+                   const Bases& bases, int shape, bool flat, bool buf, hipStream_t st) {
     if (ntiles <= 0) return;
-#define QED_LAUNCH(WM, WN, F) \
-    hipLaunchKernelGGL((k_brgemm<T, WM, WN, 2, 2, F>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases)
+#define QED_LAUNCH(WM, WN, F, B) \
+    hipLaunchKernelGGL((k_brgemm<T, WM, WN, 2, 2, F, B>), dim3(ntiles), dim3(256), 0, st, jobs, prods, tiles, bases)
+#define QED_LAUNCH3(WM, WN)                 \
+    do {                                    \
+        if (flat) QED_LAUNCH(WM, WN, true, true);   \
+        else if (buf) QED_LAUNCH(WM, WN, false, true); \
+        else QED_LAUNCH(WM, WN, false, false);      \
+    } while (0)
     switch (shape) {
-        case GEMM_SHAPE_TALL:
-            if (flat) QED_LAUNCH(4, 1, true); else QED_LAUNCH(4, 1, false);
-            break;
-        case GEMM_SHAPE_WIDE:
-            if (flat) QED_LAUNCH(1, 4, true); else QED_LAUNCH(1, 4, false);
-            break;
-        default:
-            if (flat) QED_LAUNCH(2, 2, true); else QED_LAUNCH(2, 2, false);
+        case GEMM_SHAPE_TALL: QED_LAUNCH3(4, 1); break;
+        case GEMM_SHAPE_WIDE: QED_LAUNCH3(1, 4); break;
+        default: QED_LAUNCH3(2, 2);
     }
+#undef QED_LAUNCH3
 #undef QED_LAUNCH
 }
 
 template void launch_brgemm<double>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
-                                    bool, hipStream_t);
+                                    bool, bool, hipStream_t);
 template void launch_brgemm<float>(const GJob*, const GProd*, const GTile*, int, const Bases&, int,
-                                   bool, hipStream_t);
+                                   bool, bool, hipStream_t);
 
 // ---------------------------------------------------------------------
 // element-wise helpers
